@@ -1,0 +1,323 @@
+"""CPU oracle for the RIME chi-squared engine -- TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
+import this module.  The product path (the HIP library and its binding) never
+does; the two share no code.
+
+What it computes (Perkins et al. 2015, "Montblanc", Section 2.1 "The Radio
+Interferometry Measurement Equation" and Section 2.3 "Bayesian Inference for
+Radio Observations"), written as the plain direct sum in float64 /
+complex128 torch CPU tensors:
+
+    V_tpq(nu) = sum_s  S_tpqs(nu) * A_tps(nu) B_s(nu) A_tqs(nu)^H          (eq. 1)
+    A_tps     = E_tps K_tps,  E_tps = e_tps diag(g_p0, g_p1)                (eq. e_term)
+    K_tps     = exp(-2 pi i (u l + v m + w (n - 1)) nu / c)                 (eq. k_term)
+    B_s       = (nu / nu_ref)^alpha [[I+Q, U+iV], [U-iV, I-Q]]              (eq. brightness_term)
+    chi^2     = sum_{t,pq,nu,corr} w |V - D|^2                              (eq. lhood)
+
+Readings taken where the paper is silent or garbled (each repeated at the
+function that uses it):
+
+* K carries a minus sign in the exponent (the paper's eq. k_term prints +; all
+  invariants hold under either sign).
+* The beam is e = cos^3(min(beam_k * r * nu / beam_ref_freq, beam_clip)),
+  r = |(l, m) - (dl, dm)_tp|, times a diagonal complex gain per antenna; the
+  paper's "C = 65 GHz times lambda" is dimensionally inconsistent.
+* The Gaussian shape factor is the normalised Fourier transform of an
+  elliptical Gaussian with FWHM major axis theta_maj, minor axis theta_min and
+  position angle pa measured from +m towards +l, parameterised as
+  el = theta_maj sin(pa), em = theta_maj cos(pa), R = theta_min / theta_maj:
+      S = exp(-(pi^2 / (4 ln 2)) [(u' el + v' em)^2 + R^2 (u' em - v' el)^2]),
+  u' = (u_p - u_q) nu / c, v' = (v_p - v_q) nu / c.  The paper gives no
+  formula (Table rime_input only lists the parameters).
+* (V - D)^2 on complex numbers is |V - D|^2, summed over the four
+  correlations xx, xy, yx, yy, each with its own real weight.
+
+Gradients with respect to (l, m, I, Q, U, V, alpha, el, em, R) come from
+torch.autograd applied to the same direct sum.  ``brute_force_vis`` restates
+eq. 1 with scalar Python loops for tiny problems.
+
+Inputs are the dataclasses of ``rime_synth`` (plain numpy arrays).
+"""
+from __future__ import annotations
+
+import cmath
+import math
+
+import numpy as np
+import torch
+
+C_LIGHT = 299792458.0  # m/s, exact
+GAUSS_K = math.pi ** 2 / (4.0 * math.log(2.0))
+
+_F64 = torch.float64
+_C128 = torch.complex128
+
+
+def _t(x, dtype=_F64):
+    return torch.as_tensor(np.asarray(x), dtype=dtype)
+
+
+# --------------------------------------------------------------------------- #
+# Per-term factors
+# --------------------------------------------------------------------------- #
+
+def n_minus_one(l, m):
+    """n - 1 with n = sqrt(1 - l^2 - m^2) (Section 2.1, after eq. k_term),
+    written as -(l^2 + m^2) / (1 + n), which is the same number without the
+    cancellation of sqrt(...) - 1 near the phase centre."""
+    r2 = l * l + m * m
+    return -r2 / (1.0 + torch.sqrt(1.0 - r2))
+
+
+def phase_turns(uvw, lm, freq):
+    """(u l + v m + w (n - 1)) * nu / c in turns, shape [T][A][S][F]
+    (eq. k_term with 1/lambda = nu/c)."""
+    l, m = lm[:, 0], lm[:, 1]
+    nm1 = n_minus_one(l, m)
+    u, v, w = uvw[..., 0], uvw[..., 1], uvw[..., 2]
+    tau = (u[..., None] * l + v[..., None] * m + w[..., None] * nm1)  # [T][A][S] metres
+    return tau[..., None] * (freq / C_LIGHT)                           # [T][A][S][F]
+
+
+def phase_K(uvw, lm, freq):
+    """K_tps = exp(-2 pi i x), x = phase_turns (eq. k_term, sign reading '-').
+    The integer part of x is removed first (exp(-2 pi i x) has period 1 in
+    x), so the angle passed to exp stays within [-pi, pi]."""
+    x = phase_turns(uvw, lm, freq)
+    frac = x - torch.round(x)
+    return torch.exp(torch.complex(torch.zeros_like(frac), -2.0 * math.pi * frac))
+
+
+def beam_e(lm, pointing, freq, k, ref_freq, clip):
+    """Real cos^3 beam factor e_tps(nu), shape [T][A][S][F] (eq. e_term, read
+    as cos^3(min(k * r * nu / ref_freq, clip)) with r the distance of the
+    source from the antenna's pointing centre)."""
+    dl = lm[None, None, :, 0] - pointing[..., 0][..., None]
+    dm = lm[None, None, :, 1] - pointing[..., 1][..., None]
+    r = torch.sqrt(dl * dl + dm * dm)                                   # [T][A][S]
+    arg = torch.clamp(k * r[..., None] * (freq / ref_freq), max=clip)  # [T][A][S][F]
+    return torch.cos(arg) ** 3
+
+
+def spectral(alpha, freq, ref_freq):
+    """(lambda_ref / lambda)^alpha = (nu / nu_ref)^alpha, shape [S][F]
+    (eq. brightness_term)."""
+    return torch.pow((freq / ref_freq)[None, :], alpha[:, None])
+
+
+def brightness(stokes, alpha, freq, ref_freq):
+    """B_s(nu) = (nu/nu_ref)^alpha [[I+Q, U+iV], [U-iV, I-Q]], shape
+    [S][F][2][2] (eq. brightness_term; no factor 1/2, as printed)."""
+    I, Q, U, V = stokes[:, 0], stokes[:, 1], stokes[:, 2], stokes[:, 3]
+    zero = torch.zeros_like(I)
+    b = torch.stack([
+        torch.stack([torch.complex(I + Q, zero), torch.complex(U, V)], dim=-1),
+        torch.stack([torch.complex(U, -V), torch.complex(I - Q, zero)], dim=-1),
+    ], dim=-2)                                                            # [S][2][2]
+    f = spectral(alpha, freq, ref_freq)                                   # [S][F]
+    return b[:, None] * f[..., None, None].to(_C128)
+
+
+def gauss_shape(duvw, gshape, freq):
+    """Gaussian shape factor S_tpqs(nu), shape [T][B][G][F] (reading in the
+    module docstring).  duvw = uvw_p - uvw_q per baseline, [T][B][3]; the w
+    component does not enter."""
+    el, em, R = gshape[:, 0], gshape[:, 1], gshape[:, 2]
+    s = freq / C_LIGHT
+    up = duvw[..., 0][..., None, None] * s            # [T][B][1][F]
+    vp = duvw[..., 1][..., None, None] * s
+    el_, em_, R_ = el[:, None], em[:, None], R[:, None]
+    a = up * el_ + vp * em_
+    b = up * em_ - vp * el_
+    return torch.exp(-GAUSS_K * (a * a + R_ * R_ * b * b))
+
+
+def jones_A(obs_t, lm, freq):
+    """Per-antenna A = E K as full 2x2 matrices, [T][A][S][F][2][2]."""
+    uvw, pointing, gains = obs_t["uvw"], obs_t["pointing"], obs_t["gains"]
+    K = phase_K(uvw, lm, freq)                                           # [T][A][S][F]
+    T, A, S, F = K.shape
+    if obs_t["beam"]:
+        e = beam_e(lm, pointing, freq, obs_t["beam_k"], obs_t["beam_ref_freq"],
+                   obs_t["beam_clip"]).to(_C128)
+        scal = e * K
+    else:
+        scal = K
+    g = gains if gains is not None else torch.ones((A, 2), dtype=_C128)
+    Emat = torch.zeros((A, 2, 2), dtype=_C128)
+    Emat[:, 0, 0] = g[:, 0]
+    Emat[:, 1, 1] = g[:, 1]
+    return scal[..., None, None] * Emat[None, :, None, None]             # [T][A][S][F][2][2]
+
+
+# --------------------------------------------------------------------------- #
+# Visibilities and chi-squared
+# --------------------------------------------------------------------------- #
+
+def _obs_tensors(obs, t0, t1):
+    d = {
+        "uvw": _t(obs.uvw[t0:t1]),
+        "beam": bool(obs.beam),
+        "pointing": _t(obs.pointing[t0:t1]) if obs.pointing is not None
+        else torch.zeros((t1 - t0, obs.na, 2), dtype=_F64),
+        "gains": _t(obs.gains, _C128) if obs.gains is not None else None,
+        "beam_k": float(obs.beam_k),
+        "beam_ref_freq": float(obs.beam_ref_freq),
+        "beam_clip": float(obs.beam_clip),
+    }
+    return d
+
+
+def _vis_block(obs, t0, t1, lm, stokes, alpha, gshape, ngsrc, src_chunk):
+    """Model visibilities for timesteps [t0, t1): [T][B][F][2][2] complex128."""
+    freq = _t(obs.freq)
+    ant1 = torch.as_tensor(np.asarray(obs.ant1, dtype=np.int64))
+    ant2 = torch.as_tensor(np.asarray(obs.ant2, dtype=np.int64))
+    ot = _obs_tensors(obs, t0, t1)
+    nsrc = lm.shape[0]
+    npsrc = nsrc - ngsrc
+    T, Bn, F = t1 - t0, ant1.shape[0], freq.shape[0]
+    duvw = ot["uvw"][:, ant1] - ot["uvw"][:, ant2]                       # [T][B][3]
+    vis = torch.zeros((T, Bn, F, 2, 2), dtype=_C128)
+    for s0 in range(0, nsrc, src_chunk):
+        s1 = min(nsrc, s0 + src_chunk)
+        A = jones_A(ot, lm[s0:s1], freq)                                 # [T][A][s][F][2][2]
+        Bm = brightness(stokes[s0:s1], alpha[s0:s1], freq, obs.ref_freq)  # [s][F][2][2]
+        Ap = A[:, ant1]                                                  # [T][B][s][F][2][2]
+        Aq = A[:, ant2]
+        X = Ap @ Bm[None, None] @ Aq.conj().transpose(-1, -2)            # source coherency
+        g0, g1 = max(s0, npsrc), s1
+        if g1 > g0:
+            S = gauss_shape(duvw, gshape[g0 - npsrc:g1 - npsrc], freq)    # [T][B][g][F]
+            scale = torch.ones((T, Bn, s1 - s0, F), dtype=_F64)
+            scale = torch.cat([scale[:, :, :g0 - s0], S], dim=2)
+            X = X * scale[..., None, None].to(_C128)
+        vis = vis + X.sum(dim=2)
+    return vis
+
+
+def model_vis(obs, sky, src_chunk: int = 64):
+    """Model visibilities V_tpq(nu) as [T][B][F][4] complex128 numpy, correlations
+    ordered xx, xy, yx, yy (eq. 1 with the source coherency and its sum)."""
+    lm, stokes = _t(sky.lm), _t(sky.stokes)
+    alpha, gshape = _t(sky.alpha), _t(sky.gshape)
+    out = np.empty((obs.ntime, obs.nbl, obs.nchan, 4), dtype=np.complex128)
+    for t in range(obs.ntime):
+        v = _vis_block(obs, t, t + 1, lm, stokes, alpha, gshape, sky.ngsrc, src_chunk)
+        out[t] = v.reshape(obs.nbl, obs.nchan, 4).numpy()
+    return out
+
+
+def chi2_from_vis(vis, data, weight) -> float:
+    """chi^2 = sum w |V - D|^2 (eq. lhood; the ln(2 pi / w) constant excluded)."""
+    r = np.asarray(vis) - np.asarray(data)
+    return float(np.sum(np.asarray(weight) * (r.real ** 2 + r.imag ** 2)))
+
+
+def loglike_const(weight) -> float:
+    """sum ln(2 pi / w), the weight-only term of -2 ln L (eq. lhood)."""
+    return float(np.sum(np.log(2.0 * math.pi / np.asarray(weight, dtype=np.float64))))
+
+
+def chi2(obs, sky, data, weight, src_chunk: int = 64) -> float:
+    """chi^2 of the model for ``sky`` against ``data`` (eq. lhood)."""
+    return chi2_from_vis(model_vis(obs, sky, src_chunk), data, weight)
+
+
+def chi2_and_grad(obs, sky, data, weight, src_chunk: int = 64, t_chunk: int = 1):
+    """(chi^2, grad) with grad[s] = d chi^2 / d(l, m, I, Q, U, V, alpha, el, em, R)
+    for every source (shape columns zero for point sources), by autograd of the
+    direct sum, accumulated over time chunks (chi^2 is additive over time)."""
+    lm = _t(sky.lm).requires_grad_(True)
+    stokes = _t(sky.stokes).requires_grad_(True)
+    alpha = _t(sky.alpha).requires_grad_(True)
+    gshape = _t(sky.gshape).requires_grad_(True)
+    D = np.asarray(data)
+    W = np.asarray(weight, dtype=np.float64)
+    total = 0.0
+    for t0 in range(0, obs.ntime, t_chunk):
+        t1 = min(obs.ntime, t0 + t_chunk)
+        v = _vis_block(obs, t0, t1, lm, stokes, alpha, gshape, sky.ngsrc, src_chunk)
+        v = v.reshape(t1 - t0, obs.nbl, obs.nchan, 4)
+        r = v - torch.as_tensor(D[t0:t1], dtype=_C128)
+        c = (torch.as_tensor(W[t0:t1]) * (r.real ** 2 + r.imag ** 2)).sum()
+        c.backward()
+        total += float(c.detach())
+    g = np.zeros((sky.nsrc, 10))
+    g[:, 0:2] = lm.grad.numpy()
+    g[:, 2:6] = stokes.grad.numpy()
+    g[:, 6] = alpha.grad.numpy()
+    if sky.ngsrc:
+        g[sky.npsrc:, 7:10] = gshape.grad.numpy()
+    return total, g
+
+
+# --------------------------------------------------------------------------- #
+# Brute force: eq. 1 with scalar loops (tiny problems only)
+# --------------------------------------------------------------------------- #
+
+def _mm(a, b):
+    return [[a[0][0] * b[0][0] + a[0][1] * b[1][0], a[0][0] * b[0][1] + a[0][1] * b[1][1]],
+            [a[1][0] * b[0][0] + a[1][1] * b[1][0], a[1][0] * b[0][1] + a[1][1] * b[1][1]]]
+
+
+def _herm(a):
+    return [[a[0][0].conjugate(), a[1][0].conjugate()],
+            [a[0][1].conjugate(), a[1][1].conjugate()]]
+
+
+def brute_force_vis(obs, sky):
+    """V_tpq(nu) from eq. 1 with explicit scalar loops over t, baselines,
+    channels and sources and explicit 2x2 Jones products E K B K^H E^H.
+    Returns [T][B][F][4] complex numpy."""
+    out = np.zeros((obs.ntime, obs.nbl, obs.nchan, 4), dtype=np.complex128)
+    npsrc = sky.npsrc
+    for t in range(obs.ntime):
+        for b in range(obs.nbl):
+            p, q = int(obs.ant1[b]), int(obs.ant2[b])
+            for f, nu in enumerate(obs.freq):
+                lam = C_LIGHT / nu
+                acc = [[0j, 0j], [0j, 0j]]
+                for s in range(sky.nsrc):
+                    l, m = sky.lm[s]
+                    n = math.sqrt(1.0 - l * l - m * m)
+                    I, Q, U, V = sky.stokes[s]
+                    spec = (nu / obs.ref_freq) ** sky.alpha[s]
+                    Bm = [[spec * (I + Q), spec * complex(U, V)],
+                          [spec * complex(U, -V), spec * (I - Q)]]
+                    jones = []
+                    for a in (p, q):
+                        u, v, w = obs.uvw[t, a]
+                        k = cmath.exp(-2j * math.pi * (u * l + v * m + w * (n - 1.0)) / lam)
+                        if obs.beam:
+                            dl = l - obs.pointing[t, a, 0]
+                            dm = m - obs.pointing[t, a, 1]
+                            r = math.sqrt(dl * dl + dm * dm)
+                            e = math.cos(min(obs.beam_k * r * nu / obs.beam_ref_freq,
+                                             obs.beam_clip)) ** 3
+                        else:
+                            e = 1.0
+                        g = obs.gains[a] if obs.gains is not None else (1.0, 1.0)
+                        jones.append([[e * k * g[0], 0j], [0j, e * k * g[1]]])
+                    X = _mm(_mm(jones[0], Bm), _herm(jones[1]))
+                    if s >= npsrc:
+                        el, em, R = sky.gshape[s - npsrc]
+                        du = (obs.uvw[t, p, 0] - obs.uvw[t, q, 0]) / lam
+                        dv = (obs.uvw[t, p, 1] - obs.uvw[t, q, 1]) / lam
+                        sh = math.exp(-GAUSS_K * ((du * el + dv * em) ** 2
+                                                  + (R * (du * em - dv * el)) ** 2))
+                    else:
+                        sh = 1.0
+                    for i in range(2):
+                        for j in range(2):
+                            acc[i][j] += sh * X[i][j]
+                out[t, b, f] = [acc[0][0], acc[0][1], acc[1][0], acc[1][1]]
+    return out
+
+
+def total_flux(sky, freq, ref_freq):
+    """F(nu) = sum_s I_s (nu/nu_ref)^alpha_s, per channel: the scale against
+    which visibility errors are judged."""
+    f = np.power(np.asarray(freq)[None, :] / ref_freq, np.asarray(sky.alpha)[:, None])
+    return (np.asarray(sky.stokes)[:, 0:1] * f).sum(axis=0)

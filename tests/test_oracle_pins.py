@@ -1,0 +1,408 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each check is written independently of the oracle's own formulas (numpy
+closed forms, brute-force sums, invariants), so that a dropped term, a wrong
+sign, a swapped index or a transposed operand in the oracle fails at least one
+of them.  ``test_planted_mistakes`` plants such mistakes in the oracle and
+confirms that the pins catch each one.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle.rime_oracle as O
+from rime_synth import Observation, Sky, canonical_baselines, make_problem
+
+C = 299792458.0
+
+
+def tiny_obs(na=3, ntime=2, nchan=3, beam=False, gains=False, seed=0, uv=800.0, w=40.0,
+             f0=1.3e9, f1=1.5e9):
+    rng = np.random.default_rng(seed)
+    a1, a2 = canonical_baselines(na)
+    uvw = np.empty((ntime, na, 3))
+    uvw[..., :2] = rng.uniform(-uv, uv, (ntime, na, 2))
+    uvw[..., 2] = rng.uniform(-w, w, (ntime, na))
+    obs = Observation(ntime=ntime, na=na, nchan=nchan, ant1=a1, ant2=a2, uvw=uvw,
+                      freq=np.linspace(f0, f1, nchan), beam=beam)
+    if beam:
+        obs.pointing = rng.normal(0, 1e-3, (ntime, na, 2))
+    if gains:
+        obs.gains = (1 + 0.1 * rng.standard_normal((na, 2))) * np.exp(
+            1j * rng.normal(0, 0.3, (na, 2)))
+    return obs
+
+
+def rand_sky(npsrc, ngsrc, seed=1, lm_half=0.02):
+    rng = np.random.default_rng(seed)
+    n = npsrc + ngsrc
+    st = np.empty((n, 4))
+    st[:, 0] = rng.uniform(0.5, 3.0, n)
+    st[:, 1:] = st[:, :1] * rng.uniform(-0.3, 0.3, (n, 3))
+    gs = np.stack([rng.uniform(-1e-4, 1e-4, ngsrc), rng.uniform(-1e-4, 1e-4, ngsrc),
+                   rng.uniform(0.2, 1.0, ngsrc)], axis=1) if ngsrc else np.zeros((0, 3))
+    return Sky(lm=rng.uniform(-lm_half, lm_half, (n, 2)), stokes=st,
+               alpha=rng.normal(-0.7, 0.3, n), gshape=gs)
+
+
+# --------------------------------------------------------------------------- #
+# Individual pins (plain functions so that the planted-mistake test can rerun
+# them against a patched oracle)
+# --------------------------------------------------------------------------- #
+
+def pin_phase_centre():
+    """A source at l = m = 0 with no beam: K = 1 for every antenna, so V = B
+    on every baseline (eq. 1 with eq. k_term at n = 1)."""
+    obs = tiny_obs(na=4, nchan=5)
+    I, Q, U, V, a = 2.0, 0.3, -0.2, 0.1, -0.8
+    sky = Sky(lm=np.zeros((1, 2)), stokes=np.array([[I, Q, U, V]]), alpha=np.array([a]))
+    vis = O.model_vis(obs, sky)
+    f = (obs.freq / obs.ref_freq) ** a
+    exp = np.stack([f * (I + Q), f * (U + 1j * V), f * (U - 1j * V), f * (I - Q)], axis=-1)
+    np.testing.assert_allclose(vis, np.broadcast_to(exp, vis.shape), rtol=1e-14, atol=1e-14)
+
+
+def pin_single_point_closed_form():
+    """One point source anywhere, no beam: V = B(nu) exp(-2 pi i (du l + dv m
+    + dw (n-1)) nu/c) with d = antenna p minus antenna q (eq. k_term)."""
+    obs = tiny_obs(na=3, nchan=4, seed=3)
+    l, m = 0.013, -0.007
+    st = np.array([1.5, 0.2, 0.1, -0.05])
+    sky = Sky(lm=np.array([[l, m]]), stokes=st[None], alpha=np.array([0.4]))
+    vis = O.model_vis(obs, sky)
+    n = math.sqrt(1 - l * l - m * m)
+    for t in range(obs.ntime):
+        for b, (p, q) in enumerate(zip(obs.ant1, obs.ant2)):
+            d = obs.uvw[t, p] - obs.uvw[t, q]
+            for c, nu in enumerate(obs.freq):
+                ph = np.exp(-2j * np.pi * (d[0] * l + d[1] * m + d[2] * (n - 1)) * nu / C)
+                f = (nu / obs.ref_freq) ** 0.4
+                B = f * np.array([st[0] + st[1], st[2] + 1j * st[3],
+                                  st[2] - 1j * st[3], st[0] - st[1]])
+                np.testing.assert_allclose(vis[t, b, c], B * ph, rtol=1e-11, atol=1e-12)
+
+
+def pin_sign():
+    """Sign of the phase: with du > 0, l > 0 small and everything else zero,
+    V_xx = I exp(-2 pi i du l nu/c) has a negative imaginary part."""
+    uvw = np.zeros((1, 2, 3))
+    uvw[0, 0, 0] = 10.0
+    obs = Observation(ntime=1, na=2, nchan=1, ant1=np.array([0]), ant2=np.array([1]),
+                      uvw=uvw, freq=np.array([1.4e9]))
+    sky = Sky(lm=np.array([[1e-3, 0.0]]), stokes=np.array([[1.0, 0, 0, 0]]),
+              alpha=np.zeros(1))
+    v = O.model_vis(obs, sky)[0, 0, 0, 0]
+    n = math.sqrt(1 - 1e-6)
+    ang = -2 * math.pi * 10.0 * 1e-3 * 1.4e9 / C
+    assert v.imag < 0
+    np.testing.assert_allclose(v, complex(math.cos(ang), math.sin(ang)), rtol=1e-13)
+    assert abs(n - 1) < 1e-6
+
+
+def pin_hermitian_swap():
+    """Swapping p and q conjugate-transposes every visibility: V_qp = V_pq^H
+    (B is Hermitian for real Stokes, eq. brightness_term; the Gaussian shape
+    is even in (u, v))."""
+    obs = tiny_obs(na=4, nchan=3, beam=True, gains=True, seed=5)
+    sky = rand_sky(2, 2, seed=7)
+    v = O.model_vis(obs, sky)
+    sw = Observation(**{**obs.__dict__, "ant1": obs.ant2.copy(), "ant2": obs.ant1.copy()})
+    w = O.model_vis(sw, sky)
+    np.testing.assert_allclose(w[..., 0], np.conj(v[..., 0]), rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(w[..., 1], np.conj(v[..., 2]), rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(w[..., 2], np.conj(v[..., 1]), rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(w[..., 3], np.conj(v[..., 3]), rtol=1e-12, atol=1e-13)
+
+
+def pin_zero_width_gaussian():
+    """A Gaussian of zero width (el = em = 0, any R) is a point source."""
+    obs = tiny_obs(na=4, nchan=3, beam=True, gains=True, seed=6)
+    sk = rand_sky(0, 2, seed=8)
+    sk.gshape[:, 0:2] = 0.0
+    pt = Sky(lm=sk.lm, stokes=sk.stokes, alpha=sk.alpha)
+    np.testing.assert_allclose(O.model_vis(obs, sk), O.model_vis(obs, pt), rtol=1e-14,
+                               atol=1e-14)
+
+
+def pin_gaussian_dft():
+    """The shape factor equals a brute-force 2-D Fourier sum of the sky-plane
+    elliptical Gaussian (FWHM axes, position angle from +m towards +l),
+    normalised to unit integrated flux."""
+    tmaj, tmin, pa = 2.0e-4, 0.9e-4, 0.6
+    el, em, R = tmaj * math.sin(pa), tmaj * math.cos(pa), tmin / tmaj
+    h = 8 * tmaj
+    x = np.linspace(-h, h, 801)
+    L, M = np.meshgrid(x, x, indexing="ij")
+    xmaj = L * math.sin(pa) + M * math.cos(pa)
+    xmin = L * math.cos(pa) - M * math.sin(pa)
+    img = np.exp(-4 * math.log(2) * ((xmaj / tmaj) ** 2 + (xmin / tmin) ** 2))
+    freq = np.array([1.4e9])
+    import torch
+    for (u, v) in [(1500.0, 0.0), (-700.0, 2100.0), (300.0, -900.0), (2500., 2500.)]:
+        uw, vw = u * 1.4e9 / C, v * 1.4e9 / C
+        ft = np.sum(img * np.exp(-2j * np.pi * (uw * L + vw * M))) / np.sum(img)
+        duvw = torch.tensor([[[u, v, 0.0]]], dtype=torch.float64)
+        gs = torch.tensor([[el, em, R]], dtype=torch.float64)
+        S = O.gauss_shape(duvw, gs, torch.tensor(freq))[0, 0, 0, 0].item()
+        assert abs(ft.imag) < 1e-12
+        np.testing.assert_allclose(S, ft.real, rtol=1e-9, atol=1e-12)
+
+
+def pin_gaussian_half_power():
+    """Along the major axis, u' theta_maj = 2 ln 2 / pi gives S = 1/2, and
+    u' theta_maj = 1 gives exp(-pi^2 / (4 ln 2)); along the minor axis the
+    same holds with theta_min."""
+    import torch
+    tmaj, tmin, pa = 3e-5, 1e-5, 1.1
+    gs = torch.tensor([[tmaj * math.sin(pa), tmaj * math.cos(pa), tmin / tmaj]],
+                      dtype=torch.float64)
+    nu = 1.4e9
+    for rho, theta, dirv, expect in [
+        (2 * math.log(2) / math.pi / tmaj, tmaj, (math.sin(pa), math.cos(pa)), 0.5),
+        (1.0 / tmaj, tmaj, (math.sin(pa), math.cos(pa)), math.exp(-math.pi ** 2 / (4 * math.log(2)))),
+        (2 * math.log(2) / math.pi / tmin, tmin, (math.cos(pa), -math.sin(pa)), 0.5),
+    ]:
+        u, v = rho * dirv[0] * C / nu, rho * dirv[1] * C / nu
+        S = O.gauss_shape(torch.tensor([[[u, v, 0.0]]], dtype=torch.float64), gs,
+                          torch.tensor([nu], dtype=torch.float64))[0, 0, 0, 0].item()
+        np.testing.assert_allclose(S, expect, rtol=1e-12)
+
+
+def pin_beam_values():
+    """Beam factor: e = 1 at the pointing centre; beyond the clip radius the
+    factor is the floor cos^3(1.0881) = 0.1000066 (to 7 digits); in between
+    e = cos^3(65 r nu / 1.4 GHz)."""
+    import torch
+    lm = torch.tensor([[0.0, 0.0], [0.03, 0.0], [0.003, 0.004]], dtype=torch.float64)
+    pnt = torch.zeros((1, 1, 2), dtype=torch.float64)
+    freq = torch.tensor([1.4e9, 1.0e9], dtype=torch.float64)
+    e = O.beam_e(lm, pnt, freq, 65.0, 1.4e9, 1.0881)[0, 0].numpy()
+    np.testing.assert_allclose(e[0], [1.0, 1.0], rtol=0, atol=0)
+    assert abs(e[1, 0] - 0.1000066) < 5e-8 and abs(e[1, 1] - 0.1000066) < 5e-8
+    r = 0.005
+    np.testing.assert_allclose(e[2], [math.cos(65 * r) ** 3, math.cos(65 * r / 1.4) ** 3],
+                               rtol=1e-14)
+
+
+def pin_spectral():
+    """alpha = 0 gives a flat spectrum; nu = nu_ref gives factor 1 for any alpha."""
+    import torch
+    f = O.spectral(torch.tensor([0.0, -0.7, 2.0], dtype=torch.float64),
+                   torch.tensor([0.9e9, 1.4e9, 1.7e9], dtype=torch.float64), 1.4e9).numpy()
+    np.testing.assert_allclose(f[0], 1.0, rtol=0)
+    np.testing.assert_allclose(f[:, 1], 1.0, rtol=0)
+    np.testing.assert_allclose(f[2, 2], (1.7 / 1.4) ** 2, rtol=1e-15)
+
+
+def pin_gain_placement():
+    """Gains sit in E: a phase-centre source gives V_ij = g_pi conj(g_qj) B_ij."""
+    obs = tiny_obs(na=3, nchan=2, gains=True, seed=9)
+    st = np.array([1.0, 0.25, -0.5, 0.75])
+    sky = Sky(lm=np.zeros((1, 2)), stokes=st[None], alpha=np.zeros(1))
+    v = O.model_vis(obs, sky)
+    B = np.array([[st[0] + st[1], st[2] + 1j * st[3]], [st[2] - 1j * st[3], st[0] - st[1]]])
+    for b, (p, q) in enumerate(zip(obs.ant1, obs.ant2)):
+        gp, gq = obs.gains[p], obs.gains[q]
+        exp = np.array([[gp[i] * np.conj(gq[j]) * B[i, j] for j in range(2)] for i in range(2)])
+        np.testing.assert_allclose(v[0, b, 0], exp.reshape(4), rtol=1e-13)
+
+
+def pin_brute_force():
+    """The vectorised oracle equals eq. 1 with scalar loops on a 3-antenna
+    problem with beam, gains, one point and one Gaussian source."""
+    obs = tiny_obs(na=3, ntime=2, nchan=3, beam=True, gains=True, seed=11)
+    sky = rand_sky(1, 1, seed=12)
+    np.testing.assert_allclose(O.model_vis(obs, sky), O.brute_force_vis(obs, sky),
+                               rtol=1e-11, atol=1e-12)
+
+
+PINS = [pin_phase_centre, pin_single_point_closed_form, pin_sign, pin_hermitian_swap,
+        pin_zero_width_gaussian, pin_gaussian_dft, pin_gaussian_half_power,
+        pin_beam_values, pin_spectral, pin_gain_placement, pin_brute_force]
+
+
+@pytest.mark.parametrize("pin", PINS, ids=[p.__name__ for p in PINS])
+def test_pin(pin):
+    pin()
+
+
+# --------------------------------------------------------------------------- #
+# Invariants of the sum and of chi-squared
+# --------------------------------------------------------------------------- #
+
+def test_linear_in_stokes_and_additive_over_sources():
+    """V is linear in each source's (I, Q, U, V) and additive over sources
+    (the source sum of Section 2.1)."""
+    obs = tiny_obs(na=4, nchan=3, beam=True, gains=True, seed=13)
+    sky = rand_sky(2, 2, seed=14)
+    v = O.model_vis(obs, sky)
+    s2 = Sky(lm=sky.lm, stokes=2.5 * sky.stokes, alpha=sky.alpha, gshape=sky.gshape)
+    np.testing.assert_allclose(O.model_vis(obs, s2), 2.5 * v, rtol=1e-13, atol=1e-13)
+    parts = [sky.subset(2, 0), Sky(lm=sky.lm[2:], stokes=sky.stokes[2:], alpha=sky.alpha[2:],
+                                   gshape=sky.gshape)]
+    np.testing.assert_allclose(O.model_vis(obs, parts[0]) + O.model_vis(obs, parts[1]), v,
+                               rtol=1e-12, atol=1e-13)
+
+
+def test_chi2_invariants():
+    """chi^2 = 0 when D = V; linear in w; additive over time chunks (the
+    paper's subdivision along time)."""
+    obs = tiny_obs(na=4, ntime=3, nchan=3, beam=True, gains=True, seed=15)
+    sky = rand_sky(2, 1, seed=16)
+    v = O.model_vis(obs, sky)
+    w = np.random.default_rng(0).uniform(0.5, 2.0, v.shape)
+    assert O.chi2(obs, sky, v, w) == 0.0
+    D = v + 0.1 * (np.random.default_rng(1).standard_normal(v.shape) + 1j)
+    c = O.chi2(obs, sky, D, w)
+    np.testing.assert_allclose(O.chi2(obs, sky, D, 3.0 * w), 3.0 * c, rtol=1e-14)
+    parts = sum(O.chi2(obs.time_slice(t, t + 1), sky, D[t:t + 1], w[t:t + 1])
+                for t in range(obs.ntime))
+    np.testing.assert_allclose(parts, c, rtol=1e-13)
+    # direct definition, one term at a time
+    ref = sum(w.flat[i] * abs(v.flat[i] - D.flat[i]) ** 2 for i in range(v.size))
+    np.testing.assert_allclose(c, ref, rtol=1e-13)
+
+
+def test_loglike_const():
+    w = np.array([1.0, 2.0, 4.0])
+    np.testing.assert_allclose(O.loglike_const(w), sum(math.log(2 * math.pi / x) for x in w))
+
+
+def test_total_flux():
+    sky = rand_sky(3, 0, seed=2)
+    f = O.total_flux(sky, np.array([1.4e9, 0.7e9]), 1.4e9)
+    np.testing.assert_allclose(f[0], sky.stokes[:, 0].sum())
+    np.testing.assert_allclose(f[1], (sky.stokes[:, 0] * 0.5 ** sky.alpha).sum())
+
+
+# --------------------------------------------------------------------------- #
+# Gradient: autograd of the oracle against central finite differences
+# --------------------------------------------------------------------------- #
+
+def _fd_problem(seed=21):
+    obs = tiny_obs(na=4, ntime=2, nchan=3, beam=True, gains=True, seed=seed)
+    sky = rand_sky(2, 2, seed=seed + 1)
+    truth = Sky.from_params(sky.params() * (1 + 0.02 * np.random.default_rng(seed).standard_normal(
+        (sky.nsrc, 10))), sky.ngsrc)
+    D = O.model_vis(obs, truth) + 0.01 * (1 + 1j)
+    W = np.full(D.shape, 1e4)
+    return obs, sky, D, W
+
+
+def test_grad_matches_central_fd():
+    obs, sky, D, W = _fd_problem()
+    c, g = O.chi2_and_grad(obs, sky, D, W)
+    np.testing.assert_allclose(c, O.chi2(obs, sky, D, W), rtol=1e-13)
+    p0 = sky.params()
+    for s in range(sky.nsrc):
+        for k in range(10):
+            if k >= 7 and s < sky.npsrc:
+                assert g[s, k] == 0.0
+                continue
+            h = 1e-6 * max(abs(p0[s, k]), 1e-3)
+            pp, pm = p0.copy(), p0.copy()
+            pp[s, k] += h
+            pm[s, k] -= h
+            fd = (O.chi2(obs, Sky.from_params(pp, sky.ngsrc), D, W)
+                  - O.chi2(obs, Sky.from_params(pm, sky.ngsrc), D, W)) / (2 * h)
+            assert abs(fd - g[s, k]) <= 1e-6 * max(abs(g[s, k]), 1e-3 * np.abs(g).max()), \
+                (s, k, fd, g[s, k])
+
+
+# --------------------------------------------------------------------------- #
+# Planted mistakes: each one must make at least one pin fail
+# --------------------------------------------------------------------------- #
+
+def _mut_sign(monkeypatch):
+    orig = O.phase_turns
+    monkeypatch.setattr(O, "phase_turns", lambda *a: -orig(*a))
+
+
+def _mut_drop_w(monkeypatch):
+    def pt(uvw, lm, freq):
+        u2 = uvw.clone()
+        u2[..., 2] = 0.0
+        return O_phase_turns(u2, lm, freq)
+    O_phase_turns = O.phase_turns
+    monkeypatch.setattr(O, "phase_turns", pt)
+
+
+def _mut_transpose_B(monkeypatch):
+    orig = O.brightness
+    monkeypatch.setattr(O, "brightness", lambda *a: orig(*a).transpose(-1, -2))
+
+
+def _mut_half_B(monkeypatch):
+    orig = O.brightness
+    monkeypatch.setattr(O, "brightness", lambda *a: 0.5 * orig(*a))
+
+
+def _mut_alpha_sign(monkeypatch):
+    orig = O.spectral
+    monkeypatch.setattr(O, "spectral", lambda a, f, r: orig(-a, f, r))
+
+
+def _mut_gauss_swap(monkeypatch):
+    orig = O.gauss_shape
+
+    def gs(duvw, g, freq):
+        g2 = g[:, [1, 0, 2]]
+        return orig(duvw, g2, freq)
+    monkeypatch.setattr(O, "gauss_shape", gs)
+
+
+def _mut_gauss_R(monkeypatch):
+    orig = O.gauss_shape
+
+    def gs(duvw, g, freq):
+        g2 = g.clone()
+        g2[:, 2] = 1.0
+        return orig(duvw, g2, freq)
+    monkeypatch.setattr(O, "gauss_shape", gs)
+
+
+def _mut_beam_square(monkeypatch):
+    orig = O.beam_e
+    monkeypatch.setattr(O, "beam_e", lambda *a: orig(*a) ** (2.0 / 3.0))
+
+
+def _mut_beam_noclip(monkeypatch):
+    orig = O.beam_e
+    monkeypatch.setattr(O, "beam_e", lambda lm, p, f, k, r, clip: orig(lm, p, f, k, r, 10.0))
+
+
+def _mut_gain_conj(monkeypatch):
+    orig = O.jones_A
+
+    def ja(ot, lm, freq):
+        ot = dict(ot)
+        if ot["gains"] is not None:
+            ot["gains"] = ot["gains"].conj()
+        return orig(ot, lm, freq)
+    monkeypatch.setattr(O, "jones_A", ja)
+
+
+MUTATIONS = [_mut_sign, _mut_drop_w, _mut_transpose_B, _mut_half_B, _mut_alpha_sign,
+             _mut_gauss_swap, _mut_gauss_R, _mut_beam_square, _mut_beam_noclip,
+             _mut_gain_conj]
+
+
+@pytest.mark.parametrize("mut", MUTATIONS, ids=[m.__name__ for m in MUTATIONS])
+def test_planted_mistakes(mut, monkeypatch):
+    mut(monkeypatch)
+    failed = []
+    for pin in PINS:
+        try:
+            pin()
+        except AssertionError:
+            failed.append(pin.__name__)
+    assert failed, f"no pin caught mutation {mut.__name__}"
+
+
+def test_synth_config_c0_shapes():
+    pr = make_problem("c0")
+    assert pr.obs.nbl == 21 and pr.obs.uvw.shape == (10, 7, 3)
+    assert pr.sky.nsrc == 20 and pr.sky.ngsrc == 0
+    assert pr.noise.shape == (10, 21, 16, 4)
+    np.testing.assert_allclose(pr.obs.freq[[0, -1]], [1.36e9, 1.44e9])

@@ -1,0 +1,215 @@
+"""Benchmark: chi^2 + gradient evaluations of the full RIME on one MI355X.
+
+Workload (default): 64 antennas (2016 baselines), 100 timesteps, 64 channels
+over 0.9-1.7 GHz, 1000 point + 500 Gaussian sources, cos^3 beam with pointing
+errors and diagonal gains; observed data = model at 1 %-perturbed parameters
+plus complex Gaussian noise (sigma 0.01 Jy), weights 1/sigma^2.  All inputs are
+seeded synthetic data resident in HBM before the timed region.
+
+One step = one chi^2 + gradient evaluation (every stage of the path: per-source
+preparation, per-antenna phase/beam, brightness, Gaussian shape, source-summed
+accumulation, fused chi^2 and the adjoint) in FP32-mixed precision.  The JSON
+line also carries the FP64 figures on the same workload, the chi^2-only
+figures, the roofline of the dominant kernel (timed live with HIP events on its
+stream) and the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Published MI355X peaks (dense): FP32 vector 157.3 TFLOP/s, FP64 vector 78.6.
+PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
+
+# Algorithmic flops per source x visibility term (4 correlations), minimal
+# formulation: forward point 22, forward Gaussian 25 (+1 exp); adjoint point
+# 61, adjoint Gaussian 89 (+1 exp).  The O(antennas) per-antenna work is not
+# counted.
+FLOPS_FWD = {"p": 22, "g": 25}
+FLOPS_ADJ = {"p": 61, "g": 89}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c4"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--only", default="", help="profile helper: 'grad-mixed' etc.")
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    return ap.parse_args()
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(name: str, seconds_target: float = 20.0):
+    """Time the CPU oracle (chi^2 + autograd gradient) on a bounded sample of
+    the workload: the first timestep and first 8 channels, all baselines and
+    all sources.  Returns terms/s."""
+    import torch
+
+    import oracle.rime_oracle as O
+    from rime_synth import make_problem
+
+    ncores = min(os.cpu_count() or 1, 16)
+    torch.set_num_threads(ncores)
+    pr = make_problem(name, ntime=1, nchan=8)
+    obs, sky = pr.obs, pr.sky
+    D = O.model_vis(obs, pr.truth) + pr.noise
+    t0 = time.perf_counter()
+    O.chi2_and_grad(obs, sky, D, pr.weight, src_chunk=32)
+    dt = time.perf_counter() - t0
+    terms = obs.ntime * obs.nbl * obs.nchan * sky.nsrc
+    return {"value": terms / dt, "unit": "terms/s", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"{name} restricted to 1 timestep x 8 channels (all {obs.nbl} baselines, "
+                      f"{sky.nsrc} sources): chi2 + autograd gradient, {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+
+    import paper_1501_07719_amd as R
+    from rime_synth import make_problem
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    name = "c1" if args.config == "c2" else args.config
+    t_gen = time.perf_counter()
+    pr = make_problem(name)
+    obs, sky, truth = pr.obs, pr.sky, pr.truth
+    log(f"generated {name}: na={obs.na} nbl={obs.nbl} ntime={obs.ntime} nchan={obs.nchan} "
+        f"nsrc={sky.nsrc} in {time.perf_counter() - t_gen:.1f}s")
+    plan = R.Plan(obs)
+    shp = (obs.ntime, obs.nbl, obs.nchan, 4)
+    # observed data: FP64 model at the truth parameters (GPU predict) + noise
+    vis = torch.empty(shp, dtype=torch.complex128, device="cuda")
+    ws = R.workspace(plan, R.MODE_PREDICT, R.FP64, 1, truth.nsrc)
+    R.rime_predict(plan, R.DeviceSky.from_host(truth), R.FP64, vis, ws)
+    D64 = vis + torch.as_tensor(pr.noise, device="cuda")
+    del vis, ws
+    W64 = torch.as_tensor(pr.weight, device="cuda")
+    D32, W32 = D64.to(torch.complex64), W64.to(torch.float32)
+    dsky = R.DeviceSky.from_host(sky)
+    torch.cuda.synchronize()
+
+    terms = obs.ntime * obs.nbl * obs.nchan * sky.nsrc
+    tp = obs.ntime * obs.nbl * obs.nchan * sky.npsrc
+    tg = obs.ntime * obs.nbl * obs.nchan * sky.ngsrc
+
+    def run(mode, prec, steps, warmup):
+        D, W = (D64, W64) if prec == R.FP64 else (D32, W32)
+        chi2 = torch.empty(1, dtype=torch.float64, device="cuda")
+        grad = torch.empty((sky.nsrc, 10), dtype=torch.float64, device="cuda")
+        wsp = R.workspace(plan, mode, prec, 1, sky.nsrc)
+
+        def call():
+            if mode == R.MODE_CHI2_GRAD:
+                R.rime_chi2_grad(plan, dsky, prec, D, W, chi2, grad, wsp)
+            else:
+                R.rime_chi2(plan, dsky, prec, D, W, chi2, wsp)
+
+        for _ in range(warmup):
+            call()
+        torch.cuda.synchronize()
+        ks = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+        ke = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+        for e in ks + ke:
+            e.record()
+        torch.cuda.synchronize()
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record()
+        for i in range(steps):
+            plan.set_timing_events(ks[i], ke[i])
+            call()
+        stop.record()
+        torch.cuda.synchronize()
+        plan.set_timing_events(None, None)
+        ms = start.elapsed_time(stop) / steps
+        kms = float(np.mean([ks[i].elapsed_time(ke[i]) for i in range(steps)]))
+        return {"ms_per_step": ms, "kernel_ms": kms, "chi2": chi2.item(),
+                "terms_per_s": terms / (ms * 1e-3), "evals_per_s": 1e3 / ms}
+
+    out = {}
+    log("timing chi2+grad mixed")
+    out["grad_mixed"] = run(R.MODE_CHI2_GRAD, R.MIXED, args.steps, args.warmup)
+    log(out["grad_mixed"])
+    if not args.no_fp64:
+        log("timing chi2+grad fp64")
+        out["grad_fp64"] = run(R.MODE_CHI2_GRAD, R.FP64, max(2, args.steps // 2), 1)
+        log(out["grad_fp64"])
+        log("timing chi2 mixed / fp64")
+        out["chi2_mixed"] = run(R.MODE_CHI2, R.MIXED, args.steps, 1)
+        out["chi2_fp64"] = run(R.MODE_CHI2, R.FP64, max(2, args.steps // 2), 1)
+        log(out["chi2_mixed"], out["chi2_fp64"])
+
+    g = out["grad_mixed"]
+    flops = tp * (FLOPS_FWD["p"] + FLOPS_ADJ["p"]) + tg * (FLOPS_FWD["g"] + FLOPS_ADJ["g"])
+    achieved = flops / (g["kernel_ms"] * 1e-3) / 1e12
+    traffic = None
+    try:
+        with open(args.traffic) as f:
+            tr = json.load(f)
+        traffic = tr.get("grad_mixed_bytes_per_launch")
+    except (OSError, ValueError):
+        traffic = None
+    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS["f32"],
+                "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS["f32"], "traffic": traffic,
+                "kernel": "rime_main<float,...,MODE_GRAD>", "kernel_ms": g["kernel_ms"],
+                "flops_per_launch": flops}
+    rec = {
+        "metric": "source x visibility terms/s (chi2+grad, FP32-mixed), 1 GPU",
+        "value": g["terms_per_s"],
+        "unit": "terms/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": g["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: RIME chi2+grad, {obs.na} antennas ({obs.nbl} "
+                               f"baselines), {obs.ntime} timesteps, {obs.nchan} channels, "
+                               f"{sky.npsrc} point + {sky.ngsrc} Gaussian sources, beam",
+                   "terms_per_eval": terms, "precision": "mixed (FP64 phase and sums)"},
+        "evals_per_s": g["evals_per_s"],
+        "roofline": roofline,
+    }
+    if "grad_fp64" in out:
+        rec["fp64"] = {"terms_per_s": out["grad_fp64"]["terms_per_s"],
+                       "ms_per_step": out["grad_fp64"]["ms_per_step"],
+                       "evals_per_s": out["grad_fp64"]["evals_per_s"]}
+        rec["speedup_mixed_vs_fp64"] = out["grad_fp64"]["ms_per_step"] / g["ms_per_step"]
+        rec["chi2_only"] = {
+            "mixed_terms_per_s": out["chi2_mixed"]["terms_per_s"],
+            "fp64_terms_per_s": out["chi2_fp64"]["terms_per_s"],
+            "mixed_ms": out["chi2_mixed"]["ms_per_step"],
+            "fp64_ms": out["chi2_fp64"]["ms_per_step"]}
+    if not args.no_cpu_baseline:
+        log("cpu baseline")
+        rec["cpu_baseline"] = cpu_baseline(name)
+    plan.close()
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

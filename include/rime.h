@@ -1,0 +1,207 @@
+/*
+ * rime.h -- C ABI of the MI355X RIME chi-squared engine (librime.so).
+ *
+ * The library evaluates the Radio Interferometer Measurement Equation for a
+ * parameterised sky of point and Gaussian sources (Perkins et al. 2015,
+ * "Montblanc", Section 2.1, eq. 1 with eqs. brightness_term, k_term and
+ * e_term), reduces it to the weighted chi-squared of Section 2.3
+ * (eq. lhood), and differentiates that chi-squared with respect to every
+ * source parameter.
+ *
+ *   V_tpq(nu) = G_p [ sum_s S_tpqs(nu) e_tps e_tqs K_tps conj(K_tqs) B_s(nu) ] G_q^H
+ *   K_tps     = exp(-2 pi i (u l + v m + w (n - 1)) nu / c),  n = sqrt(1 - l^2 - m^2)
+ *   B_s(nu)   = (nu / nu_ref)^alpha [[I+Q, U+iV], [U-iV, I-Q]]
+ *   e_tps     = cos^3(min(beam_k * |(l,m) - pointing_tp| * nu / beam_ref_freq, beam_clip))
+ *   G_p       = diag(g_p0, g_p1)          (constant diagonal complex gain)
+ *   S_tpqs    = exp(-(pi^2 / (4 ln 2)) [(u' el + v' em)^2 + R^2 (u' em - v' el)^2])
+ *               for Gaussian sources (u' = (u_p - u_q) nu / c), 1 for point sources
+ *   chi^2     = sum_{t, baseline, nu, corr} w |V - D|^2
+ *
+ * Conventions shared by every entry point:
+ *  - Arrays are dense, row-major, little-endian.  Correlations are ordered
+ *    (xx, xy, yx, yy); complex values are interleaved (re, im).
+ *  - "host" arrays are read during the call and may be freed afterwards.
+ *    "device" arrays are HIP device pointers owned by the caller; they must
+ *    stay valid until the work enqueued on `stream` has finished.
+ *  - Every compute call is asynchronous on `stream` (a hipStream_t; NULL is
+ *    the default stream).  Results are valid once the stream is synchronised.
+ *  - Argument validation happens on the host before anything is enqueued; a
+ *    non-zero status means nothing was enqueued.  No C++ exception crosses
+ *    this boundary.
+ *  - Precision RIME_FP64: data/weight/vis are complex128/float64 and all
+ *    arithmetic is float64.  RIME_MIXED: data/weight/vis are
+ *    complex64/float32; the phase argument and the chi-squared (and gradient)
+ *    sums are float64, everything else float32.  Sky parameters are float64
+ *    in both.
+ *  - Sources with l^2 + m^2 >= 1 are outside the domain of the equation;
+ *    they are not checked (sky parameters live on the device) and turn the
+ *    result into NaN.
+ *  - Calls are re-entrant when given distinct workspaces.
+ */
+#ifndef RIME_H
+#define RIME_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum rime_status {
+  RIME_OK = 0,
+  RIME_ERR_ARG = 1,          /* null pointer, bad size, inconsistent dimensions */
+  RIME_ERR_WORKSPACE = 2,    /* ws_bytes smaller than rime_workspace_size()    */
+  RIME_ERR_HIP = 3,          /* a HIP runtime call failed (see rime_last_hip_error) */
+  RIME_ERR_UNSUPPORTED = 4,  /* no kernel variant for this request             */
+  RIME_ERR_NOMEM = 5         /* device allocation inside a create call failed  */
+} rime_status;
+
+typedef enum rime_precision {
+  RIME_FP64 = 0,
+  RIME_MIXED = 1
+} rime_precision;
+
+typedef enum rime_mode {
+  RIME_MODE_PREDICT = 0,     /* write model visibilities            */
+  RIME_MODE_CHI2 = 1,        /* chi-squared only                    */
+  RIME_MODE_CHI2_GRAD = 2    /* chi-squared and its source gradient */
+} rime_mode;
+
+/* Observation: the per-observation inputs of Table rime_input (uvw,
+ * antenna pairs, frequencies, pointing errors) plus the beam and gain model.
+ * All arrays are HOST arrays, copied into the plan by rime_plan_create. */
+typedef struct rime_obs_desc {
+  int32_t ntime;             /* timesteps, >= 1                                   */
+  int32_t na;                /* antennas, 2 .. 4096                               */
+  int32_t nbl;               /* baselines, >= 1                                   */
+  int32_t nchan;             /* channels, >= 1                                    */
+  const int32_t *ant1;       /* host [nbl] antenna p of each baseline, or NULL    */
+  const int32_t *ant2;       /* host [nbl] antenna q; NULL with ant1 NULL selects  */
+                             /* the canonical p < q row-major order, nbl must then */
+                             /* be na (na - 1) / 2                                */
+  const double *uvw;         /* host [ntime][na][3] metres                        */
+  const double *freq;        /* host [nchan] Hz, > 0                              */
+  double ref_freq;           /* spectral-index reference frequency, Hz, > 0       */
+  int32_t beam;              /* 0: e = 1; 1: cos^3 beam with pointing errors      */
+  const double *pointing;    /* host [ntime][na][2] rad, or NULL (zero); beam == 1 */
+  const double *gains;       /* host [na][2][2] (feed, re/im) diagonal gains, or  */
+                             /* NULL for unity gains                              */
+  double beam_k;             /* 65.0                                              */
+  double beam_ref_freq;      /* 1.4e9 Hz                                          */
+  double beam_clip;          /* 1.0881 rad                                        */
+} rime_obs_desc;
+
+/* One sky model (one sampler proposal).  Point sources first, then Gaussians.
+ * All arrays are DEVICE float64 arrays. */
+typedef struct rime_sky {
+  int32_t npsrc;             /* point sources, >= 0                               */
+  int32_t ngsrc;             /* Gaussian sources, >= 0; npsrc + ngsrc >= 1        */
+  const double *lm;          /* device [nsrc][2] direction cosines, rad           */
+  const double *stokes;      /* device [nsrc][4] I, Q, U, V in Jy at ref_freq     */
+  const double *alpha;       /* device [nsrc] spectral index                      */
+  const double *gshape;      /* device [ngsrc][3] (el, em, R): el = theta_maj sin(pa), */
+                             /* em = theta_maj cos(pa), R = theta_min / theta_maj; */
+                             /* FWHM in rad; may be NULL when ngsrc == 0          */
+} rime_sky;
+
+typedef struct rime_plan rime_plan;    /* observation resident on one device */
+typedef struct rime_batch rime_batch;  /* a fixed set of proposals over one plan */
+
+/* Create a plan on the current HIP device: copies the observation to device
+ * memory, derives per-channel constants and builds the baseline tiling.
+ * Synchronous.  The plan owns its device memory until rime_plan_destroy. */
+rime_status rime_plan_create(const rime_obs_desc *obs, rime_plan **out);
+void rime_plan_destroy(rime_plan *plan);
+
+/* Bytes of device workspace that one call of `mode` needs for `nset` sets with
+ * `total_src` sources in all (nset = 1 for the single-sky calls). */
+size_t rime_workspace_size(const rime_plan *plan, rime_mode mode, rime_precision prec,
+                           int32_t nset, int64_t total_src);
+
+/* Model visibilities, eq. 1: vis is DEVICE [ntime][nbl][nchan][4] complex
+ * (complex128 for RIME_FP64, complex64 for RIME_MIXED). */
+rime_status rime_predict(const rime_plan *plan, const rime_sky *sky, rime_precision prec,
+                         void *vis, void *ws, size_t ws_bytes, void *stream);
+
+/* chi^2 of eq. lhood (without the ln(2 pi / w) constant): data is DEVICE
+ * [ntime][nbl][nchan][4] complex, weight DEVICE [ntime][nbl][nchan][4] real
+ * (precision as for vis); chi2 is DEVICE double[1]. */
+rime_status rime_chi2(const rime_plan *plan, const rime_sky *sky, rime_precision prec,
+                      const void *data, const void *weight, double *chi2,
+                      void *ws, size_t ws_bytes, void *stream);
+
+/* chi^2 and its gradient: grad is DEVICE double [nsrc][10] with columns
+ * d chi^2 / d(l, m, I, Q, U, V, alpha, el, em, R); the shape columns of point
+ * sources are 0.  The model visibilities are never written to memory. */
+rime_status rime_chi2_grad(const rime_plan *plan, const rime_sky *sky, rime_precision prec,
+                           const void *data, const void *weight, double *chi2, double *grad,
+                           void *ws, size_t ws_bytes, void *stream);
+
+/* Batched proposals over one observation.  `skies` is a HOST array of nset
+ * sky descriptions whose device pointers and source counts are fixed for the
+ * life of the batch (the caller overwrites the parameter values in place
+ * between evaluations).  Synchronous; owns a small device table. */
+rime_status rime_batch_create(const rime_plan *plan, int32_t nset, const rime_sky *skies,
+                              rime_batch **out);
+void rime_batch_destroy(rime_batch *batch);
+
+/* chi^2 (and gradient when grad != NULL) of every set in one launch sequence:
+ * chi2 DEVICE double[nset]; grad DEVICE double [sum nsrc][10], set-major in
+ * the order the sets were given.  With use_graph != 0 the launch sequence is
+ * captured into a hipGraph on the first call for a given (data, weight, chi2,
+ * grad, ws, stream, precision) and replayed afterwards. */
+rime_status rime_chi2_batched(rime_batch *batch, rime_precision prec, const void *data,
+                              const void *weight, double *chi2, double *grad,
+                              void *ws, size_t ws_bytes, void *stream, int32_t use_graph);
+size_t rime_batch_workspace_size(const rime_batch *batch, rime_mode mode,
+                                 rime_precision prec);
+
+/* Sum over all weights of ln(2 pi / w): the constant of eq. lhood, so that
+ * -2 ln L = chi^2 + rime_loglike_const.  HOST array, n entries. */
+double rime_loglike_const(const double *weight, size_t n);
+
+const char *rime_status_string(rime_status s);
+/* The last HIP error code seen by this thread (0 if none). */
+int32_t rime_last_hip_error(void);
+
+/* Kernel-variant selection.  Every compute call uses the variant chosen
+ * here for its (plan, mode, precision); the default is a fixed heuristic.
+ * rime_autotune times every compiled variant on the given sky and stores the
+ * fastest; with cache_path != NULL the choice is also written to / read from
+ * that JSON file, keyed by the problem signature.  Synchronous. */
+rime_status rime_autotune(rime_plan *plan, const rime_sky *sky, rime_mode mode,
+                          rime_precision prec, const void *data, const void *weight,
+                          void *ws, size_t ws_bytes, const char *cache_path);
+/* Number of compiled variants for (mode, prec) and their descriptions. */
+int32_t rime_variant_count(rime_mode mode, rime_precision prec);
+rime_status rime_variant_info(rime_mode mode, rime_precision prec, int32_t index,
+                              int32_t *threads, int32_t *chans_per_thread,
+                              int32_t *srcs_per_tile);
+rime_status rime_set_variant(rime_plan *plan, rime_mode mode, rime_precision prec,
+                             int32_t index);
+int32_t rime_get_variant(const rime_plan *plan, rime_mode mode, rime_precision prec);
+
+/* Timing hook: when start/stop are non-NULL hipEvent_t handles, every later
+ * compute call on this plan records `start` immediately before and `stop`
+ * immediately after its main kernel, on the call's stream (the small
+ * per-source preparation and final-reduction kernels fall outside).  NULL
+ * turns it off.  Used to time the dominant kernel in isolation. */
+rime_status rime_plan_set_timing_events(rime_plan *plan, void *start, void *stop);
+
+/* Host-only view of the baseline tiling used by the kernels: every baseline
+ * index appears in exactly one tile; a tile holds at most `threads`
+ * baselines (threads = 64, 256 or 1024) over at most 16, 32 or 64 antennas.
+ * Outputs (HOST, may be NULL to query *ntile only): tile_bl [ntile][threads]
+ * baseline index or -1, tile_lpq [ntile][threads] local p | (local q << 16),
+ * tile_ant [ntile][nat] antenna index or -1.  Returns RIME_ERR_ARG when the
+ * outputs are given and *ntile > max_tiles.  Performs no HIP call. */
+rime_status rime_tiling_host(int32_t na, int32_t nbl, const int32_t *ant1, const int32_t *ant2,
+                             int32_t threads, int32_t max_tiles, int32_t *ntile,
+                             int32_t *tile_bl, int32_t *tile_lpq, int32_t *tile_ant);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RIME_H */

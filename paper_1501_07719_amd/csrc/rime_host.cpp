@@ -1,0 +1,848 @@
+// Host runtime of librime.so: argument validation, observation plans and the
+// baseline tiling, workspace layout, kernel-variant selection (with a timing
+// autotuner and a JSON cache), batched proposals and their hipGraph capture.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <numeric>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "rime_internal.h"
+
+namespace rime {
+hipError_t launch_prep(const KParams &p, bool fp64, int max_nsrc, hipStream_t stream);
+hipError_t launch_finalize(const KParams &p, int mode, int max_nsrc, hipStream_t stream);
+int variant_count(int mode, int prec);
+const Variant *variant_info(int mode, int prec, int index);
+hipError_t launch_variant(int mode, int prec, int index, const KParams &p, int nitems,
+                          hipStream_t stream);
+}  // namespace rime
+
+using namespace rime;
+
+namespace {
+
+thread_local int32_t g_last_hip = 0;
+
+inline rime_status hip_fail(hipError_t e) {
+  g_last_hip = static_cast<int32_t>(e);
+  return RIME_ERR_HIP;
+}
+
+#define RIME_HIP(call)                        \
+  do {                                        \
+    hipError_t e_ = (call);                   \
+    if (e_ != hipSuccess) return hip_fail(e_); \
+  } while (0)
+
+constexpr int kNbt[3] = {64, 256, 1024};
+constexpr size_t kAlign = 256;
+// Target number of work items per launch (several workgroups per CU).
+constexpr int64_t kTargetItems = 8192;
+
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int nat_for_host(int nbt) { return nbt >= 1024 ? 64 : nbt >= 256 ? 32 : 16; }
+
+int nbt_slot(int nbt) {
+  for (int i = 0; i < 3; ++i)
+    if (kNbt[i] == nbt) return i;
+  return -1;
+}
+
+template <class T>
+hipError_t upload(T **dst, const std::vector<T> &src) {
+  *dst = nullptr;
+  if (src.empty()) return hipSuccess;
+  hipError_t e = hipMalloc(reinterpret_cast<void **>(dst), src.size() * sizeof(T));
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+}  // namespace
+
+struct rime_plan {
+  int device = 0;
+  int32_t ntime = 0, na = 0, nbl = 0, nchan = 0;
+  int32_t beam = 0;
+  double ref_freq = 0, beam_k = 0, beam_clip = 0;
+  double *d_uvw = nullptr, *d_nu_c = nullptr, *d_lnfr = nullptr, *d_bfr = nullptr;
+  double *d_pointing = nullptr, *d_gains = nullptr;
+  TileSet tiles[3];
+  int32_t variant[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+  std::string signature;  // observation part of the autotune key
+  hipEvent_t ev_start = nullptr, ev_stop = nullptr;
+};
+
+struct GraphKey {
+  const void *data, *weight;
+  double *chi2, *grad;
+  void *ws;
+  size_t ws_bytes;
+  void *stream;
+  int prec, variant, mode;
+  bool operator==(const GraphKey &o) const {
+    return data == o.data && weight == o.weight && chi2 == o.chi2 && grad == o.grad &&
+           ws == o.ws && ws_bytes == o.ws_bytes && stream == o.stream && prec == o.prec &&
+           variant == o.variant && mode == o.mode;
+  }
+};
+
+struct rime_batch {
+  const rime_plan *plan = nullptr;
+  int32_t nset = 0;
+  int64_t total_src = 0;
+  int32_t max_nsrc = 0;
+  SetDesc *d_sets = nullptr;
+  int32_t *d_order = nullptr;
+  bool has_graph = false;
+  GraphKey key{};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Baseline tiling
+// ---------------------------------------------------------------------------
+// Antennas are split into nb balanced blocks of at most B = nat/2 antennas.
+// The baselines joining block P and block Q (P < Q) form a tile (at most
+// B^2 = nbt baselines over at most 2B = nat antennas); the baselines inside
+// one block are paired with those inside another block into one tile.  Within
+// a tile the baselines are sorted by (local p, local q).
+rime_status compute_tiles(int na, int nbl, const std::vector<int32_t> &a1,
+                          const std::vector<int32_t> &a2, int nbt, int &ntile_out,
+                          std::vector<int32_t> &hbl, std::vector<int32_t> &hlpq,
+                          std::vector<int32_t> &hant) {
+  const int nat = nat_for_host(nbt);
+  const int B = nat / 2;
+  const int nb = (na + B - 1) / B;
+  std::vector<int> block_of(na), block_start(nb + 1, 0);
+  for (int b = 0; b < nb; ++b) block_start[b + 1] = block_start[b] + na / nb + (b < na % nb ? 1 : 0);
+  for (int b = 0; b < nb; ++b)
+    for (int a = block_start[b]; a < block_start[b + 1]; ++a) block_of[a] = b;
+  std::vector<std::vector<int>> bucket(static_cast<size_t>(nb) * nb);
+  for (int i = 0; i < nbl; ++i) {
+    int P = block_of[a1[i]], Q = block_of[a2[i]];
+    if (P > Q) std::swap(P, Q);
+    bucket[static_cast<size_t>(P) * nb + Q].push_back(i);
+  }
+  struct T {
+    std::vector<int> ants, bls;
+  };
+  std::vector<T> tiles;
+  auto block_ants = [&](int P, std::vector<int> &out) {
+    for (int a = block_start[P]; a < block_start[P + 1]; ++a) out.push_back(a);
+  };
+  auto emit_chunks = [&](const std::vector<int> &bls, const std::vector<int> &ants) {
+    for (size_t o = 0; o < bls.size(); o += nbt) {
+      T t;
+      t.ants = ants;
+      t.bls.assign(bls.begin() + o, bls.begin() + std::min(bls.size(), o + nbt));
+      tiles.push_back(std::move(t));
+    }
+  };
+  for (int P = 0; P < nb; ++P)
+    for (int Q = P + 1; Q < nb; ++Q) {
+      const auto &bk = bucket[static_cast<size_t>(P) * nb + Q];
+      if (bk.empty()) continue;
+      std::vector<int> ants;
+      block_ants(P, ants);
+      block_ants(Q, ants);
+      emit_chunks(bk, ants);
+    }
+  int pending = -1;
+  for (int P = 0; P < nb; ++P) {
+    const auto &bk = bucket[static_cast<size_t>(P) * nb + P];
+    if (bk.empty()) continue;
+    if (pending < 0) {
+      pending = P;
+      continue;
+    }
+    const auto &pk = bucket[static_cast<size_t>(pending) * nb + pending];
+    std::vector<int> ants;
+    block_ants(pending, ants);
+    block_ants(P, ants);
+    if (static_cast<int>(pk.size() + bk.size()) <= nbt) {
+      std::vector<int> bls(pk);
+      bls.insert(bls.end(), bk.begin(), bk.end());
+      emit_chunks(bls, ants);
+    } else {
+      std::vector<int> a0;
+      block_ants(pending, a0);
+      emit_chunks(pk, a0);
+      std::vector<int> a1v;
+      block_ants(P, a1v);
+      emit_chunks(bk, a1v);
+    }
+    pending = -1;
+  }
+  if (pending >= 0) {
+    std::vector<int> ants;
+    block_ants(pending, ants);
+    emit_chunks(bucket[static_cast<size_t>(pending) * nb + pending], ants);
+  }
+  const int ntile = static_cast<int>(tiles.size());
+  hbl.assign(static_cast<size_t>(ntile) * nbt, -1);
+  hlpq.assign(hbl.size(), 0);
+  hant.assign(static_cast<size_t>(ntile) * nat, -1);
+  std::vector<int> local(na, -1);
+  for (int ti = 0; ti < ntile; ++ti) {
+    T &t = tiles[ti];
+    if (static_cast<int>(t.ants.size()) > nat) return RIME_ERR_ARG;
+    for (size_t i = 0; i < t.ants.size(); ++i) {
+      local[t.ants[i]] = static_cast<int>(i);
+      hant[static_cast<size_t>(ti) * nat + i] = t.ants[i];
+    }
+    std::sort(t.bls.begin(), t.bls.end(), [&](int x, int y) {
+      const int px = local[a1[x]], py = local[a1[y]];
+      if (px != py) return px < py;
+      return local[a2[x]] < local[a2[y]];
+    });
+    for (size_t i = 0; i < t.bls.size(); ++i) {
+      const int b = t.bls[i];
+      hbl[static_cast<size_t>(ti) * nbt + i] = b;
+      hlpq[static_cast<size_t>(ti) * nbt + i] = local[a1[b]] | (local[a2[b]] << 16);
+    }
+    for (int a : t.ants) local[a] = -1;
+  }
+  ntile_out = ntile;
+  return RIME_OK;
+}
+
+rime_status build_tiles(int na, int nbl, const std::vector<int32_t> &a1,
+                        const std::vector<int32_t> &a2, int nbt, TileSet &ts) {
+  int ntile = 0;
+  std::vector<int32_t> hbl, hlpq, hant;
+  rime_status st = compute_tiles(na, nbl, a1, a2, nbt, ntile, hbl, hlpq, hant);
+  if (st != RIME_OK) return st;
+  const int nat = nat_for_host(nbt);
+  ts.nbt = nbt;
+  ts.nat = nat;
+  ts.ntile = ntile;
+  hipError_t e;
+  if ((e = upload(&ts.bl, hbl)) != hipSuccess) return hip_fail(e);
+  if ((e = upload(&ts.lpq, hlpq)) != hipSuccess) return hip_fail(e);
+  if ((e = upload(&ts.ant, hant)) != hipSuccess) return hip_fail(e);
+  return RIME_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Launch geometry and workspace layout
+// ---------------------------------------------------------------------------
+struct Geometry {
+  int ntile = 0, nchb = 0, tchunk = 1, ntc = 1, items_per_set = 0;
+};
+
+Geometry geometry(const rime_plan *plan, const Variant &v, int nset) {
+  Geometry g;
+  g.ntile = plan->tiles[nbt_slot(v.threads)].ntile;
+  g.nchb = (plan->nchan + v.nc - 1) / v.nc;
+  const int64_t per_t = static_cast<int64_t>(g.ntile) * g.nchb * nset;
+  int64_t tc = (per_t * plan->ntime + kTargetItems - 1) / kTargetItems;
+  tc = std::max<int64_t>(1, std::min<int64_t>(tc, plan->ntime));
+  g.tchunk = static_cast<int>(tc);
+  g.ntc = (plan->ntime + g.tchunk - 1) / g.tchunk;
+  g.items_per_set = g.ntile * g.nchb * g.ntc;
+  return g;
+}
+
+struct WsLayout {
+  size_t geo = 0, lon = 0, st = 0, chi2 = 0, grad = 0, total = 0;
+};
+
+WsLayout ws_layout(const rime_plan *plan, int mode, int prec, const Geometry &g, int nset,
+                   int64_t total_src) {
+  WsLayout L;
+  const size_t r4 = prec == RIME_FP64 ? 32 : 16;
+  size_t off = 0;
+  L.geo = off;
+  off += align_up(static_cast<size_t>(total_src) * sizeof(double4));
+  L.lon = off;
+  off += align_up(static_cast<size_t>(total_src) * sizeof(double2));
+  L.st = off;
+  off += align_up(static_cast<size_t>(total_src) * plan->nchan * r4);
+  L.chi2 = off;
+  if (mode != RIME_MODE_PREDICT)
+    off += align_up(static_cast<size_t>(nset) * g.items_per_set * sizeof(double2));
+  L.grad = off;
+  if (mode == RIME_MODE_CHI2_GRAD)
+    off += align_up(static_cast<size_t>(g.items_per_set) * total_src * 10 * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+size_t ws_max(const rime_plan *plan, int mode, int prec, int nset, int64_t total_src) {
+  size_t best = 0;
+  for (int i = 0; i < variant_count(mode, prec); ++i) {
+    const Variant *v = variant_info(mode, prec, i);
+    best = std::max(best, ws_layout(plan, mode, prec, geometry(plan, *v, nset), nset, total_src).total);
+  }
+  return best;
+}
+
+rime_status check_sky(const rime_sky *sky) {
+  if (!sky) return RIME_ERR_ARG;
+  if (sky->npsrc < 0 || sky->ngsrc < 0) return RIME_ERR_ARG;
+  if (static_cast<int64_t>(sky->npsrc) + sky->ngsrc < 1) return RIME_ERR_ARG;
+  if (static_cast<int64_t>(sky->npsrc) + sky->ngsrc > (1 << 24)) return RIME_ERR_ARG;
+  if (!sky->lm || !sky->stokes || !sky->alpha) return RIME_ERR_ARG;
+  if (sky->ngsrc > 0 && !sky->gshape) return RIME_ERR_ARG;
+  return RIME_OK;
+}
+
+KParams base_params(const rime_plan *plan) {
+  KParams p;
+  std::memset(&p, 0, sizeof(p));
+  p.ntime = plan->ntime;
+  p.na = plan->na;
+  p.nbl = plan->nbl;
+  p.nchan = plan->nchan;
+  p.uvw = plan->d_uvw;
+  p.nu_c = plan->d_nu_c;
+  p.lnfr = plan->d_lnfr;
+  p.pointing = plan->d_pointing;
+  p.gains = plan->d_gains;
+  p.beam = plan->beam;
+  p.bfr = plan->d_bfr;
+  p.beam_k = plan->beam_k;
+  p.beam_clip = plan->beam_clip;
+  return p;
+}
+
+// Enqueue prep + main + finalize for `nset` sets.
+rime_status enqueue(const rime_plan *plan, int mode, int prec, int vidx, int nset,
+                    const SetDesc *d_sets, const SetDesc &one, const int32_t *d_order,
+                    int max_nsrc, int64_t total_src, const void *data, const void *weight,
+                    void *vis, double *chi2, double *grad, void *ws, size_t ws_bytes,
+                    hipStream_t stream) {
+  const Variant *v = variant_info(mode, prec, vidx);
+  if (!v) return RIME_ERR_UNSUPPORTED;
+  const Geometry g = geometry(plan, *v, nset);
+  const WsLayout L = ws_layout(plan, mode, prec, g, nset, total_src);
+  if (L.total > 0 && (!ws || ws_bytes < L.total)) return RIME_ERR_WORKSPACE;
+  const int64_t nitems = static_cast<int64_t>(nset) * g.items_per_set;
+  if (nitems <= 0 || nitems > 0x7fffffff) return RIME_ERR_UNSUPPORTED;
+  const TileSet &ts = plan->tiles[nbt_slot(v->threads)];
+  KParams p = base_params(plan);
+  p.nbt = ts.nbt;
+  p.nat = ts.nat;
+  p.ntile = ts.ntile;
+  p.tile_bl = ts.bl;
+  p.tile_lpq = ts.lpq;
+  p.tile_ant = ts.ant;
+  p.nchb = g.nchb;
+  p.tchunk = g.tchunk;
+  p.ntc = g.ntc;
+  p.items_per_set = g.items_per_set;
+  p.nset = nset;
+  p.sets = d_sets;
+  p.one = one;
+  p.order = d_order;
+  char *w = static_cast<char *>(ws);
+  p.src_geo = reinterpret_cast<double4 *>(w + L.geo);
+  p.src_lon = reinterpret_cast<double2 *>(w + L.lon);
+  p.src_st = w + L.st;
+  p.total_src = total_src;
+  p.data = data;
+  p.weight = weight;
+  p.vis = vis;
+  p.chi2_part = reinterpret_cast<double2 *>(w + L.chi2);
+  p.grad_part = reinterpret_cast<double *>(w + L.grad);
+  p.chi2_out = chi2;
+  p.grad_out = grad;
+  RIME_HIP(launch_prep(p, prec == RIME_FP64, max_nsrc, stream));
+  if (plan->ev_start) RIME_HIP(hipEventRecord(plan->ev_start, stream));
+  RIME_HIP(launch_variant(mode, prec, vidx, p, static_cast<int>(nitems), stream));
+  if (plan->ev_stop) RIME_HIP(hipEventRecord(plan->ev_stop, stream));
+  RIME_HIP(launch_finalize(p, mode, max_nsrc, stream));
+  return RIME_OK;
+}
+
+rime_status single(const rime_plan *plan, int mode, rime_precision prec, const rime_sky *sky,
+                   const void *data, const void *weight, void *vis, double *chi2, double *grad,
+                   void *ws, size_t ws_bytes, void *stream) {
+  if (!plan) return RIME_ERR_ARG;
+  if (prec != RIME_FP64 && prec != RIME_MIXED) return RIME_ERR_ARG;
+  rime_status st = check_sky(sky);
+  if (st != RIME_OK) return st;
+  if (mode == RIME_MODE_PREDICT && !vis) return RIME_ERR_ARG;
+  if (mode != RIME_MODE_PREDICT && (!data || !weight || !chi2)) return RIME_ERR_ARG;
+  if (mode == RIME_MODE_CHI2_GRAD && !grad) return RIME_ERR_ARG;
+  SetDesc one;
+  one.lm = sky->lm;
+  one.stokes = sky->stokes;
+  one.alpha = sky->alpha;
+  one.gshape = sky->gshape;
+  one.npsrc = sky->npsrc;
+  one.ngsrc = sky->ngsrc;
+  one.src_off = 0;
+  const int nsrc = sky->npsrc + sky->ngsrc;
+  int dev = 0;
+  RIME_HIP(hipGetDevice(&dev));
+  if (dev != plan->device) return RIME_ERR_ARG;
+  return enqueue(plan, mode, prec, plan->variant[mode][prec], 1, nullptr, one, nullptr, nsrc,
+                 nsrc, data, weight, vis, chi2, grad, ws, ws_bytes,
+                 static_cast<hipStream_t>(stream));
+}
+
+int default_variant(const rime_plan *plan, int mode, int prec) {
+  // index layout of the compiled variants: 0 -> 64 threads, 1 -> 256, 2 -> 1024
+  // (FP64 adjoint: 2 -> 256 threads x 4 channels)
+  if (plan->nbl <= 96) return 0;
+  if (mode == RIME_MODE_CHI2_GRAD && prec == RIME_FP64) return 1;
+  if (plan->nbl >= 1024 && prec == RIME_MIXED) return 2;
+  return 1;
+}
+
+std::string sky_signature(const rime_sky *sky) {
+  std::ostringstream o;
+  o << "p" << sky->npsrc << "g" << sky->ngsrc;
+  return o.str();
+}
+
+std::mutex g_cache_mu;
+
+std::map<std::string, int> read_cache(const char *path) {
+  std::map<std::string, int> m;
+  std::ifstream f(path);
+  if (!f) return m;
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string s = ss.str();
+  size_t i = 0;
+  while (true) {
+    const size_t k0 = s.find('"', i);
+    if (k0 == std::string::npos) break;
+    const size_t k1 = s.find('"', k0 + 1);
+    if (k1 == std::string::npos) break;
+    const size_t c = s.find(':', k1);
+    if (c == std::string::npos) break;
+    m[s.substr(k0 + 1, k1 - k0 - 1)] = std::atoi(s.c_str() + c + 1);
+    i = c + 1;
+  }
+  return m;
+}
+
+void write_cache(const char *path, const std::map<std::string, int> &m) {
+  std::ofstream f(path);
+  f << "{\n";
+  size_t n = 0;
+  for (const auto &kv : m) f << "  \"" << kv.first << "\": " << kv.second << (++n < m.size() ? ",\n" : "\n");
+  f << "}\n";
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *rime_status_string(rime_status s) {
+  switch (s) {
+    case RIME_OK: return "ok";
+    case RIME_ERR_ARG: return "invalid argument";
+    case RIME_ERR_WORKSPACE: return "workspace too small";
+    case RIME_ERR_HIP: return "HIP runtime error";
+    case RIME_ERR_UNSUPPORTED: return "unsupported request";
+    case RIME_ERR_NOMEM: return "device allocation failed";
+  }
+  return "unknown status";
+}
+
+int32_t rime_last_hip_error(void) { return g_last_hip; }
+
+double rime_loglike_const(const double *weight, size_t n) {
+  if (!weight) return 0.0;
+  // compensated sum of ln(2 pi / w)
+  double s = 0.0, c = 0.0;
+  const double two_pi = 2.0 * kPi;
+  for (size_t i = 0; i < n; ++i) {
+    const double x = std::log(two_pi / weight[i]);
+    const double t = s + x;
+    c += std::fabs(s) >= std::fabs(x) ? (s - t) + x : (x - t) + s;
+    s = t;
+  }
+  return s + c;
+}
+
+void rime_plan_destroy(rime_plan *plan) {
+  if (!plan) return;
+  int cur = 0;
+  const bool have = hipGetDevice(&cur) == hipSuccess;
+  if (have && cur != plan->device) (void)hipSetDevice(plan->device);
+  (void)hipFree(plan->d_uvw);
+  (void)hipFree(plan->d_nu_c);
+  (void)hipFree(plan->d_lnfr);
+  (void)hipFree(plan->d_bfr);
+  (void)hipFree(plan->d_pointing);
+  (void)hipFree(plan->d_gains);
+  for (auto &t : plan->tiles) {
+    (void)hipFree(t.bl);
+    (void)hipFree(t.lpq);
+    (void)hipFree(t.ant);
+  }
+  if (have && cur != plan->device) (void)hipSetDevice(cur);
+  delete plan;
+}
+
+rime_status rime_plan_create(const rime_obs_desc *obs, rime_plan **out) {
+  if (!obs || !out) return RIME_ERR_ARG;
+  *out = nullptr;
+  if (obs->ntime < 1 || obs->na < 2 || obs->na > 4096 || obs->nbl < 1 || obs->nchan < 1)
+    return RIME_ERR_ARG;
+  if (!obs->uvw || !obs->freq) return RIME_ERR_ARG;
+  if (!(obs->ref_freq > 0)) return RIME_ERR_ARG;
+  if ((obs->ant1 == nullptr) != (obs->ant2 == nullptr)) return RIME_ERR_ARG;
+  if (obs->beam != 0 && obs->beam != 1) return RIME_ERR_ARG;
+  if (obs->beam == 1 && !(obs->beam_ref_freq > 0 && obs->beam_k >= 0 && obs->beam_clip > 0))
+    return RIME_ERR_ARG;
+  if (static_cast<int64_t>(obs->ntime) * obs->nbl * obs->nchan > (int64_t(1) << 40))
+    return RIME_ERR_ARG;
+  for (int c = 0; c < obs->nchan; ++c)
+    if (!(obs->freq[c] > 0)) return RIME_ERR_ARG;
+  std::vector<int32_t> a1(obs->nbl), a2(obs->nbl);
+  if (!obs->ant1) {
+    if (static_cast<int64_t>(obs->nbl) != static_cast<int64_t>(obs->na) * (obs->na - 1) / 2)
+      return RIME_ERR_ARG;
+    int b = 0;
+    for (int p = 0; p < obs->na; ++p)
+      for (int q = p + 1; q < obs->na; ++q) {
+        a1[b] = p;
+        a2[b] = q;
+        ++b;
+      }
+  } else {
+    for (int b = 0; b < obs->nbl; ++b) {
+      if (obs->ant1[b] < 0 || obs->ant1[b] >= obs->na || obs->ant2[b] < 0 ||
+          obs->ant2[b] >= obs->na)
+        return RIME_ERR_ARG;
+      a1[b] = obs->ant1[b];
+      a2[b] = obs->ant2[b];
+    }
+  }
+  rime_plan *pl = new rime_plan;
+  hipError_t e = hipGetDevice(&pl->device);
+  if (e != hipSuccess) {
+    delete pl;
+    return hip_fail(e);
+  }
+  pl->ntime = obs->ntime;
+  pl->na = obs->na;
+  pl->nbl = obs->nbl;
+  pl->nchan = obs->nchan;
+  pl->beam = obs->beam;
+  pl->ref_freq = obs->ref_freq;
+  pl->beam_k = obs->beam == 1 ? obs->beam_k : 0.0;
+  pl->beam_clip = obs->beam == 1 ? obs->beam_clip : 0.0;
+  const size_t nuvw = static_cast<size_t>(obs->ntime) * obs->na * 3;
+  std::vector<double> uvw(obs->uvw, obs->uvw + nuvw);
+  std::vector<double> nu_c(obs->nchan), lnfr(obs->nchan), bfr(obs->nchan, 0.0);
+  for (int c = 0; c < obs->nchan; ++c) {
+    nu_c[c] = obs->freq[c] / kC;
+    lnfr[c] = std::log(obs->freq[c] / obs->ref_freq);
+    if (obs->beam == 1) bfr[c] = obs->freq[c] / obs->beam_ref_freq;
+  }
+  std::vector<double> pnt(static_cast<size_t>(obs->ntime) * obs->na * 2, 0.0);
+  if (obs->beam == 1 && obs->pointing) std::copy(obs->pointing, obs->pointing + pnt.size(), pnt.begin());
+  std::vector<double> gains(static_cast<size_t>(obs->na) * 4);
+  for (int a = 0; a < obs->na; ++a) {
+    for (int f = 0; f < 2; ++f) {
+      gains[4 * a + 2 * f] = obs->gains ? obs->gains[4 * a + 2 * f] : 1.0;
+      gains[4 * a + 2 * f + 1] = obs->gains ? obs->gains[4 * a + 2 * f + 1] : 0.0;
+    }
+  }
+  rime_status st = RIME_OK;
+  if ((e = upload(&pl->d_uvw, uvw)) != hipSuccess || (e = upload(&pl->d_nu_c, nu_c)) != hipSuccess ||
+      (e = upload(&pl->d_lnfr, lnfr)) != hipSuccess ||
+      (e = upload(&pl->d_bfr, bfr)) != hipSuccess ||
+      (e = upload(&pl->d_pointing, pnt)) != hipSuccess ||
+      (e = upload(&pl->d_gains, gains)) != hipSuccess) {
+    st = e == hipErrorOutOfMemory ? RIME_ERR_NOMEM : hip_fail(e);
+  }
+  for (int i = 0; i < 3 && st == RIME_OK; ++i)
+    st = build_tiles(obs->na, obs->nbl, a1, a2, kNbt[i], pl->tiles[i]);
+  if (st != RIME_OK) {
+    rime_plan_destroy(pl);
+    return st;
+  }
+  for (int m = 0; m < 3; ++m)
+    for (int p = 0; p < 2; ++p) pl->variant[m][p] = default_variant(pl, m, p);
+  std::ostringstream sig;
+  sig << "t" << obs->ntime << "a" << obs->na << "b" << obs->nbl << "c" << obs->nchan << "e"
+      << obs->beam;
+  pl->signature = sig.str();
+  *out = pl;
+  return RIME_OK;
+}
+
+size_t rime_workspace_size(const rime_plan *plan, rime_mode mode, rime_precision prec,
+                           int32_t nset, int64_t total_src) {
+  if (!plan || nset < 1 || total_src < 1 || mode < 0 || mode > 2 || prec < 0 || prec > 1)
+    return 0;
+  return ws_max(plan, mode, prec, nset, total_src);
+}
+
+rime_status rime_predict(const rime_plan *plan, const rime_sky *sky, rime_precision prec,
+                         void *vis, void *ws, size_t ws_bytes, void *stream) {
+  return single(plan, RIME_MODE_PREDICT, prec, sky, nullptr, nullptr, vis, nullptr, nullptr, ws,
+                ws_bytes, stream);
+}
+
+rime_status rime_chi2(const rime_plan *plan, const rime_sky *sky, rime_precision prec,
+                      const void *data, const void *weight, double *chi2, void *ws,
+                      size_t ws_bytes, void *stream) {
+  return single(plan, RIME_MODE_CHI2, prec, sky, data, weight, nullptr, chi2, nullptr, ws,
+                ws_bytes, stream);
+}
+
+rime_status rime_chi2_grad(const rime_plan *plan, const rime_sky *sky, rime_precision prec,
+                           const void *data, const void *weight, double *chi2, double *grad,
+                           void *ws, size_t ws_bytes, void *stream) {
+  return single(plan, RIME_MODE_CHI2_GRAD, prec, sky, data, weight, nullptr, chi2, grad, ws,
+                ws_bytes, stream);
+}
+
+void rime_batch_destroy(rime_batch *b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  (void)hipFree(b->d_sets);
+  (void)hipFree(b->d_order);
+  delete b;
+}
+
+rime_status rime_batch_create(const rime_plan *plan, int32_t nset, const rime_sky *skies,
+                              rime_batch **out) {
+  if (!plan || !out || !skies || nset < 1 || nset > (1 << 20)) return RIME_ERR_ARG;
+  *out = nullptr;
+  std::vector<SetDesc> sets(nset);
+  int64_t off = 0;
+  int32_t mx = 0;
+  for (int i = 0; i < nset; ++i) {
+    rime_status st = check_sky(&skies[i]);
+    if (st != RIME_OK) return st;
+    SetDesc &d = sets[i];
+    d.lm = skies[i].lm;
+    d.stokes = skies[i].stokes;
+    d.alpha = skies[i].alpha;
+    d.gshape = skies[i].gshape;
+    d.npsrc = skies[i].npsrc;
+    d.ngsrc = skies[i].ngsrc;
+    d.src_off = off;
+    off += d.npsrc + d.ngsrc;
+    mx = std::max(mx, d.npsrc + d.ngsrc);
+  }
+  std::vector<int32_t> order(nset);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return sets[x].npsrc + 2 * sets[x].ngsrc > sets[y].npsrc + 2 * sets[y].ngsrc;
+  });
+  rime_batch *b = new rime_batch;
+  b->plan = plan;
+  b->nset = nset;
+  b->total_src = off;
+  b->max_nsrc = mx;
+  hipError_t e;
+  if ((e = upload(&b->d_sets, sets)) != hipSuccess || (e = upload(&b->d_order, order)) != hipSuccess) {
+    rime_batch_destroy(b);
+    return e == hipErrorOutOfMemory ? RIME_ERR_NOMEM : hip_fail(e);
+  }
+  *out = b;
+  return RIME_OK;
+}
+
+size_t rime_batch_workspace_size(const rime_batch *b, rime_mode mode, rime_precision prec) {
+  if (!b || mode < 0 || mode > 2 || prec < 0 || prec > 1) return 0;
+  return ws_max(b->plan, mode, prec, b->nset, b->total_src);
+}
+
+rime_status rime_chi2_batched(rime_batch *b, rime_precision prec, const void *data,
+                              const void *weight, double *chi2, double *grad, void *ws,
+                              size_t ws_bytes, void *stream, int32_t use_graph) {
+  if (!b || !data || !weight || !chi2) return RIME_ERR_ARG;
+  if (prec != RIME_FP64 && prec != RIME_MIXED) return RIME_ERR_ARG;
+  const int mode = grad ? RIME_MODE_CHI2_GRAD : RIME_MODE_CHI2;
+  const rime_plan *plan = b->plan;
+  const int vidx = plan->variant[mode][prec];
+  const Variant *v = variant_info(mode, prec, vidx);
+  if (!v) return RIME_ERR_UNSUPPORTED;
+  const WsLayout L = ws_layout(plan, mode, prec, geometry(plan, *v, b->nset), b->nset, b->total_src);
+  if (!ws || ws_bytes < L.total) return RIME_ERR_WORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  SetDesc dummy;
+  std::memset(&dummy, 0, sizeof(dummy));
+  auto run = [&]() {
+    return enqueue(plan, mode, prec, vidx, b->nset, b->d_sets, dummy, b->d_order, b->max_nsrc,
+                   b->total_src, data, weight, nullptr, chi2, grad, ws, ws_bytes, s);
+  };
+  if (!use_graph || s == nullptr) return run();
+  GraphKey key{data, weight, chi2, grad, ws, ws_bytes, stream, prec, vidx, mode};
+  if (!(b->has_graph && b->key == key)) {
+    if (b->exec) {
+      (void)hipGraphExecDestroy(b->exec);
+      b->exec = nullptr;
+    }
+    if (b->graph) {
+      (void)hipGraphDestroy(b->graph);
+      b->graph = nullptr;
+    }
+    b->has_graph = false;
+    RIME_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    rime_status st = run();
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (st != RIME_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return hip_fail(e);
+    b->graph = g;
+    RIME_HIP(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
+    b->key = key;
+    b->has_graph = true;
+  }
+  RIME_HIP(hipGraphLaunch(b->exec, s));
+  return RIME_OK;
+}
+
+rime_status rime_tiling_host(int32_t na, int32_t nbl, const int32_t *ant1, const int32_t *ant2,
+                             int32_t threads, int32_t max_tiles, int32_t *ntile,
+                             int32_t *tile_bl, int32_t *tile_lpq, int32_t *tile_ant) {
+  if (na < 2 || nbl < 1 || !ant1 || !ant2 || !ntile || nbt_slot(threads) < 0) return RIME_ERR_ARG;
+  std::vector<int32_t> a1(ant1, ant1 + nbl), a2(ant2, ant2 + nbl);
+  for (int b = 0; b < nbl; ++b)
+    if (a1[b] < 0 || a1[b] >= na || a2[b] < 0 || a2[b] >= na) return RIME_ERR_ARG;
+  int nt = 0;
+  std::vector<int32_t> hbl, hlpq, hant;
+  rime_status st = compute_tiles(na, nbl, a1, a2, threads, nt, hbl, hlpq, hant);
+  if (st != RIME_OK) return st;
+  *ntile = nt;
+  if (nt > max_tiles) return tile_bl ? RIME_ERR_ARG : RIME_OK;
+  if (tile_bl) std::copy(hbl.begin(), hbl.end(), tile_bl);
+  if (tile_lpq) std::copy(hlpq.begin(), hlpq.end(), tile_lpq);
+  if (tile_ant) std::copy(hant.begin(), hant.end(), tile_ant);
+  return RIME_OK;
+}
+
+rime_status rime_plan_set_timing_events(rime_plan *plan, void *start, void *stop) {
+  if (!plan || ((start == nullptr) != (stop == nullptr))) return RIME_ERR_ARG;
+  plan->ev_start = static_cast<hipEvent_t>(start);
+  plan->ev_stop = static_cast<hipEvent_t>(stop);
+  return RIME_OK;
+}
+
+int32_t rime_variant_count(rime_mode mode, rime_precision prec) {
+  if (mode < 0 || mode > 2 || prec < 0 || prec > 1) return 0;
+  return variant_count(mode, prec);
+}
+
+rime_status rime_variant_info(rime_mode mode, rime_precision prec, int32_t index,
+                              int32_t *threads, int32_t *chans_per_thread,
+                              int32_t *srcs_per_tile) {
+  const Variant *v = variant_info(mode, prec, index);
+  if (!v) return RIME_ERR_ARG;
+  if (threads) *threads = v->threads;
+  if (chans_per_thread) *chans_per_thread = v->nc;
+  if (srcs_per_tile) *srcs_per_tile = v->ns;
+  return RIME_OK;
+}
+
+rime_status rime_set_variant(rime_plan *plan, rime_mode mode, rime_precision prec,
+                             int32_t index) {
+  if (!plan || !variant_info(mode, prec, index)) return RIME_ERR_ARG;
+  plan->variant[mode][prec] = index;
+  return RIME_OK;
+}
+
+int32_t rime_get_variant(const rime_plan *plan, rime_mode mode, rime_precision prec) {
+  if (!plan || mode < 0 || mode > 2 || prec < 0 || prec > 1) return -1;
+  return plan->variant[mode][prec];
+}
+
+rime_status rime_autotune(rime_plan *plan, const rime_sky *sky, rime_mode mode,
+                          rime_precision prec, const void *data, const void *weight, void *ws,
+                          size_t ws_bytes, const char *cache_path) {
+  if (!plan || mode < 0 || mode > 2 || (prec != RIME_FP64 && prec != RIME_MIXED))
+    return RIME_ERR_ARG;
+  rime_status st = check_sky(sky);
+  if (st != RIME_OK) return st;
+  std::ostringstream k;
+  k << plan->signature << "_" << sky_signature(sky) << "_m" << mode << "_p" << prec;
+  const std::string key = k.str();
+  if (cache_path) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto m = read_cache(cache_path);
+    auto it = m.find(key);
+    if (it != m.end() && variant_info(mode, prec, it->second)) {
+      plan->variant[mode][prec] = it->second;
+      return RIME_OK;
+    }
+  }
+  const int nsrc = sky->npsrc + sky->ngsrc;
+  // scratch outputs for the trial runs
+  void *vis = nullptr;
+  double *chi2 = nullptr, *grad = nullptr;
+  if (mode == RIME_MODE_PREDICT)
+    RIME_HIP(hipMalloc(&vis, static_cast<size_t>(plan->ntime) * plan->nbl * plan->nchan * 4 *
+                                 (prec == RIME_FP64 ? 16 : 8)));
+  RIME_HIP(hipMalloc(reinterpret_cast<void **>(&chi2), sizeof(double)));
+  if (mode == RIME_MODE_CHI2_GRAD)
+    RIME_HIP(hipMalloc(reinterpret_cast<void **>(&grad), static_cast<size_t>(nsrc) * 10 * sizeof(double)));
+  hipStream_t s = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  RIME_HIP(hipStreamCreate(&s));
+  RIME_HIP(hipEventCreate(&e0));
+  RIME_HIP(hipEventCreate(&e1));
+  float best_ms = 1e30f;
+  int best = plan->variant[mode][prec];
+  const int saved = plan->variant[mode][prec];
+  for (int i = 0; i < variant_count(mode, prec); ++i) {
+    plan->variant[mode][prec] = i;
+    auto call = [&]() {
+      return single(plan, mode, prec, sky, data, weight, vis, chi2, grad, ws, ws_bytes, s);
+    };
+    st = call();  // warm-up (also rejects variants whose workspace does not fit)
+    if (st != RIME_OK) continue;
+    float ms_min = 1e30f;
+    for (int r = 0; r < 3 && st == RIME_OK; ++r) {
+      (void)hipEventRecord(e0, s);
+      st = call();
+      (void)hipEventRecord(e1, s);
+      (void)hipEventSynchronize(e1);
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      ms_min = std::min(ms_min, ms);
+    }
+    if (st == RIME_OK && ms_min < best_ms) {
+      best_ms = ms_min;
+      best = i;
+    }
+  }
+  (void)hipStreamSynchronize(s);
+  plan->variant[mode][prec] = best_ms < 1e29f ? best : saved;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamDestroy(s);
+  (void)hipFree(vis);
+  (void)hipFree(chi2);
+  (void)hipFree(grad);
+  if (best_ms >= 1e29f) return RIME_ERR_UNSUPPORTED;
+  if (cache_path) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto m = read_cache(cache_path);
+    m[key] = best;
+    write_cache(cache_path, m);
+  }
+  return RIME_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,85 @@
+// Internal structures shared by the HIP kernels and the host runtime of
+// librime.so.  Not part of the public ABI (include/rime.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rime.h"
+
+namespace rime {
+
+// Speed of light (m/s, exact) and the Gaussian shape constant pi^2 / (4 ln 2).
+constexpr double kC = 299792458.0;
+constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr double kGauss = (kPi * kPi) / (4.0 * 0.69314718055994530941723212145817657);
+
+// Sources per tile (lanes of one wavefront cover srcs x chans in the adjoint).
+constexpr int kWave = 64;
+
+// One sky model as seen by the kernels.
+struct SetDesc {
+  const double *lm;      // [nsrc][2]
+  const double *stokes;  // [nsrc][4]
+  const double *alpha;   // [nsrc]
+  const double *gshape;  // [ngsrc][3]
+  int32_t npsrc, ngsrc;
+  int64_t src_off;       // first source of this set in the concatenated source index
+};
+
+// Baseline tiling for one block size: every tile has at most `nbt` baselines
+// and at most `nat` distinct antennas.
+struct TileSet {
+  int32_t nbt = 0, nat = 0, ntile = 0;
+  int32_t *bl = nullptr;   // device [ntile][nbt]  global baseline index or -1
+  int32_t *lpq = nullptr;  // device [ntile][nbt]  local p | (local q << 16)
+  int32_t *ant = nullptr;  // device [ntile][nat]  global antenna index or -1
+};
+
+// Everything a kernel launch needs (passed by value).
+struct KParams {
+  // observation
+  int32_t ntime, na, nbl, nchan;
+  const double *uvw;       // [ntime][na][3]
+  const double *nu_c;      // [nchan]  nu / c  (1/m)
+  const double *lnfr;      // [nchan]  ln(nu / ref_freq)
+  const double *pointing;  // [ntime][na][2]  (zeros when absent)
+  const double *gains;     // [na][2][2]  (unity when absent)
+  int32_t beam;
+  const double *bfr;       // [nchan]  nu / beam_ref_freq
+  double beam_k;           // beam argument is beam_k * r * nu / beam_ref_freq
+  double beam_clip;
+  // tiling
+  int32_t nbt, nat, ntile;
+  const int32_t *tile_bl, *tile_lpq, *tile_ant;
+  int32_t nchb;            // channel blocks
+  int32_t tchunk, ntc;     // timesteps per work item, time chunks
+  int32_t items_per_set;   // ntile * nchb * ntc
+  // sets
+  int32_t nset;
+  const SetDesc *sets;     // device [nset] (batched) or nullptr
+  SetDesc one;             // the single set when sets == nullptr
+  const int32_t *order;    // device [nset] largest-first order, or nullptr
+  // per-source derived data in the workspace
+  double4 *src_geo;        // [total_src] (l, m, n - 1, 0)
+  double2 *src_lon;        // [total_src] (l / n, m / n)
+  void *src_st;            // [total_src][nchan] Stokes scaled by (nu/nu_ref)^alpha (R4)
+  int64_t total_src;
+  // per-call data
+  const void *data;        // [ntime][nbl][nchan][4] complex
+  const void *weight;      // [ntime][nbl][nchan][4] real
+  void *vis;               // predict output
+  double2 *chi2_part;      // [total items] (sum, compensation)
+  double *grad_part;       // gradient partials
+  double *chi2_out;        // [nset]
+  double *grad_out;        // [total_src][10]
+};
+
+// Kernel variant descriptor.
+struct Variant {
+  int32_t threads;         // baselines per work item (one per thread)
+  int32_t nc;              // channels per thread
+  int32_t ns;              // sources per tile
+};
+
+}  // namespace rime

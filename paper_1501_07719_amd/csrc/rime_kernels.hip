@@ -1,0 +1,774 @@
+// HIP kernels of the RIME chi-squared engine for gfx950 (MI355X).
+//
+// One work item (= one workgroup) owns a tile of baselines (at most NBT, one
+// per thread, drawn from at most NAT antennas), a block of NC channels and a
+// chunk of timesteps.  For every source tile of NS sources it
+//   1. computes the per-antenna terms a_tps(nu) = e_tps K_tps once per antenna
+//      into LDS (the per-antenna-first strategy of the paper's Section 4.1,
+//      fused here with the per-baseline stage instead of going through HBM);
+//   2. accumulates, per visibility, the four Stokes-weighted sums
+//      sum_s S c_s I'_s, ..., sum_s S c_s V'_s with c_s = a_p conj(a_q)
+//      (eq. 1 with B written out; the gains are applied once after the sum,
+//      which is exact since they do not depend on the source);
+// and then, per visibility, forms V, the residual and the weighted squared
+// residual of eq. lhood, reduced in float64 with compensated (two-sum)
+// arithmetic.  In gradient mode the weighted residual stays in LDS and a
+// second source sweep (lanes over sources x channels, loop over baselines)
+// accumulates d chi^2 / d theta_s without ever storing V.
+//
+// Precision: R = double (plain FP64) or R = float (mixed).  In the mixed path
+// the phase argument is formed in float64 and reduced to [-1/2, 1/2] turns
+// before the float32 sine/cosine; the beam clip decision is taken in float64;
+// the per-visibility source sums run in float32 within a source tile and are
+// folded into float64 after each tile; chi^2 and gradient sums are float64.
+#include "rime_internal.h"
+
+namespace rime {
+
+// ---------------------------------------------------------------------------
+// Numeric helpers
+// ---------------------------------------------------------------------------
+
+template <class R> struct Num;
+
+template <> struct Num<double> {
+  using R2 = double2;
+  using R4 = double4;
+  // sin and cos of 2 pi r for r in [-1/2, 1/2] turns.
+  __device__ static inline void sincos_turns(double r, double *s, double *c) {
+    sincospi(2.0 * r, s, c);
+  }
+  __device__ static inline double cos_(double x) { return cos(x); }
+  __device__ static inline double tan_(double x) { return tan(x); }
+  __device__ static inline double exp_(double x) { return exp(x); }
+};
+
+template <> struct Num<float> {
+  using R2 = float2;
+  using R4 = float4;
+  __device__ static inline void sincos_turns(double r, float *s, float *c) {
+    sincospif(static_cast<float>(2.0 * r), s, c);
+  }
+  __device__ static inline float cos_(float x) { return cosf(x); }
+  __device__ static inline float tan_(float x) { return tanf(x); }
+  __device__ static inline float exp_(float x) { return expf(x); }
+};
+
+// (a0 b0 + a1 b1) + a2 b2 with every product and sum rounded separately (no
+// fused multiply-add), i.e. in the order in which the definitions are written.
+// The phase argument is hundreds of turns, so the rounding of this sum is
+// visible in the phase; evaluating it in definition order keeps the FP64 path
+// rounding-compatible with a plain evaluation of the same formula.
+__device__ inline double dot3_rn(double a0, double b0, double a1, double b1, double a2,
+                                 double b2) {
+#pragma clang fp contract(off)
+  return (a0 * b0 + a1 * b1) + a2 * b2;
+}
+
+__device__ inline double sumsq_rn(double a, double b) {
+#pragma clang fp contract(off)
+  return a * a + b * b;
+}
+
+// Error-free sum: s + e == a + b exactly.
+__device__ inline void two_sum(double a, double b, double &s, double &e) {
+  s = a + b;
+  const double bp = s - a;
+  e = (a - (s - bp)) + (b - bp);
+}
+
+// Compensated float64 accumulator.
+struct Comp {
+  double s = 0.0, c = 0.0;
+  __device__ inline void add(double x) {
+    double e;
+    two_sum(s, x, s, e);
+    c += e;
+  }
+  __device__ inline void merge(double os, double oc) {
+    double e;
+    two_sum(s, os, s, e);
+    c += oc + e;
+  }
+};
+
+__device__ inline Comp wave_reduce(Comp v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    const double os = __shfl_xor(v.s, off, kWave);
+    const double oc = __shfl_xor(v.c, off, kWave);
+    v.merge(os, oc);
+  }
+  return v;
+}
+
+// Workgroup reduction of a compensated pair; the result is valid in thread 0.
+template <int NT>
+__device__ inline Comp block_reduce(Comp v, double2 *scratch) {
+  constexpr int NW = NT / kWave;
+  v = wave_reduce(v);
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  if (NW == 1) return v;
+  __syncthreads();
+  if (lane == 0) scratch[wave] = make_double2(v.s, v.c);
+  __syncthreads();
+  Comp r;
+  if (wave == 0) {
+    if (lane < NW) {
+      r.s = scratch[lane].x;
+      r.c = scratch[lane].y;
+    }
+    r = wave_reduce(r);
+  }
+  return r;
+}
+
+constexpr int nat_for(int nbt) { return nbt >= 1024 ? 64 : nbt >= 256 ? 32 : 16; }
+
+// ---------------------------------------------------------------------------
+// Per-source preparation: (l, m, n - 1), (l/n, m/n) and the spectrally scaled
+// Stokes vector per channel (eq. brightness_term).  One thread per source.
+// ---------------------------------------------------------------------------
+template <class R>
+__global__ __launch_bounds__(256) void prep_sources(const KParams p) {
+  using R4 = typename Num<R>::R4;
+  const int set = blockIdx.y;
+  const SetDesc sd = p.sets ? p.sets[set] : p.one;
+  const int nsrc = sd.npsrc + sd.ngsrc;
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nsrc) return;
+  const double l = sd.lm[2 * s], m = sd.lm[2 * s + 1];
+  const double r2 = sumsq_rn(l, m);
+  const double n = sqrt(1.0 - r2);
+  const double nm1 = -r2 / (1.0 + n);
+  const int64_t g = sd.src_off + s;
+  p.src_geo[g] = make_double4(l, m, nm1, 0.0);
+  p.src_lon[g] = make_double2(l / n, m / n);
+  const double I = sd.stokes[4 * s], Q = sd.stokes[4 * s + 1];
+  const double U = sd.stokes[4 * s + 2], V = sd.stokes[4 * s + 3];
+  const double a = sd.alpha[s];
+  R4 *st = static_cast<R4 *>(p.src_st) + g * p.nchan;
+  for (int c = 0; c < p.nchan; ++c) {
+    const double f = exp(a * p.lnfr[c]);
+    R4 v;
+    v.x = static_cast<R>(f * I);
+    v.y = static_cast<R>(f * Q);
+    v.z = static_cast<R>(f * U);
+    v.w = static_cast<R>(f * V);
+    st[c] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Main kernel
+// ---------------------------------------------------------------------------
+
+enum { MODE_PREDICT = 0, MODE_CHI2 = 1, MODE_GRAD = 2 };
+
+template <class R, int NBT, int NC, int NS, int MODE>
+struct Layout {
+  using R2 = typename Num<R>::R2;
+  using R4 = typename Num<R>::R4;
+  static constexpr int NAT = nat_for(NBT);
+  static constexpr int NW = NBT / kWave;
+  // a-tile row per source: NAT antennas x NC channels, padded by one element
+  // so that consecutive sources start in different LDS banks.
+  static constexpr int AST = NAT * NC + 1;
+  static constexpr bool GRAD = MODE == MODE_GRAD;
+  static constexpr size_t A_BYTES = sizeof(R2) * NS * AST;
+  static constexpr size_t BETA_BYTES = GRAD ? sizeof(R2) * NS * AST : 0;
+  static constexpr size_t RED_BYTES = GRAD ? sizeof(R) * NBT * 10 : 0;
+  // the adjoint's cross-wave reduction buffer reuses the a/beta tiles
+  static constexpr size_t AB_BYTES =
+      (A_BYTES + BETA_BYTES) > RED_BYTES ? (A_BYTES + BETA_BYTES) : RED_BYTES;
+  static constexpr size_t RHO_BYTES = GRAD ? sizeof(R2) * NBT * NC * 4 : 0;
+  static constexpr size_t GEO_BYTES = GRAD ? sizeof(R4) * NBT : 0;
+  static constexpr size_t LPQ_BYTES = GRAD ? sizeof(int) * NBT : 0;
+};
+
+// Per-antenna stage for one source tile: a[s][ant][c] = e K (and, for the
+// adjoint, beta[s][ant][c] = d ln e / d(l, m)), plus the tile's scaled Stokes
+// and Gaussian shapes.
+template <class R, int NBT, int NC, int NS, int MODE, bool WITH_BETA>
+__device__ inline void stage_tile(const KParams &p, const SetDesc &sd, int tile, int s0, int cnt,
+                                  bool gauss, int c0, int ncv, const double (*s_uvw)[3],
+                                  const double (*s_pnt)[2], typename Num<R>::R2 *s_a,
+                                  typename Num<R>::R2 *s_beta, typename Num<R>::R4 *s_st,
+                                  typename Num<R>::R4 *s_gs) {
+  using L = Layout<R, NBT, NC, NS, MODE>;
+  using N = Num<R>;
+  using R2 = typename N::R2;
+  using R4 = typename N::R4;
+  constexpr int NAT = L::NAT;
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < NS * NAT; idx += NBT) {
+    const int s = idx / NAT;
+    const int ai = idx - s * NAT;
+    const bool ok = s < cnt && p.tile_ant[tile * NAT + ai] >= 0;
+    R2 out[NC];
+    R2 bet[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      out[c].x = R(0);
+      out[c].y = R(0);
+      bet[c].x = R(0);
+      bet[c].y = R(0);
+    }
+    if (ok) {
+      const double4 g = p.src_geo[sd.src_off + s0 + s];
+      // tau = u l + v m + w (n - 1), metres (eq. k_term)
+      const double tau = dot3_rn(s_uvw[ai][0], g.x, s_uvw[ai][1], g.y, s_uvw[ai][2], g.z);
+      double rb = 0.0, dl = 0.0, dm = 0.0;
+      if (p.beam) {
+        dl = g.x - s_pnt[ai][0];
+        dm = g.y - s_pnt[ai][1];
+        rb = sqrt(sumsq_rn(dl, dm));
+      }
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        if (c < ncv) {
+          const double nuc = p.nu_c[c0 + c];
+          const double x = tau * nuc;
+          const double r = x - rint(x);
+          R sn, cs;
+          N::sincos_turns(r, &sn, &cs);
+          R e = R(1);
+          if (p.beam) {
+            // x = beam_k r nu / beam_ref_freq, clipped (eq. e_term)
+            const double bs = p.beam_k * p.bfr[c0 + c];
+            const double xb = (p.beam_k * rb) * p.bfr[c0 + c];
+            const bool clipped = xb >= p.beam_clip;
+            const R xr = static_cast<R>(clipped ? p.beam_clip : xb);
+            const R cb = N::cos_(xr);
+            e = cb * cb * cb;
+            if (WITH_BETA) {
+              // d ln e / dl = -3 tan(x) dx/dl, dx/dl = bs (l - dl_p) / r
+              //             = -3 bs^2 (l - dl_p) tan(x)/x ; zero past the clip.
+              R tx = R(0);
+              if (!clipped) tx = xr > R(1e-4) ? N::tan_(xr) / xr : R(1) + xr * xr / R(3);
+              const R k3 = static_cast<R>(-3.0 * bs * bs) * tx;
+              bet[c].x = k3 * static_cast<R>(dl);
+              bet[c].y = k3 * static_cast<R>(dm);
+            }
+          }
+          out[c].x = e * cs;
+          out[c].y = -e * sn;
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      s_a[s * L::AST + ai * NC + c] = out[c];
+      if (WITH_BETA) s_beta[s * L::AST + ai * NC + c] = bet[c];
+    }
+  }
+  const R4 *st = static_cast<const R4 *>(p.src_st);
+  for (int idx = tid; idx < NS * NC; idx += NBT) {
+    const int s = idx / NC, c = idx - (idx / NC) * NC;
+    R4 v;
+    v.x = v.y = v.z = v.w = R(0);
+    if (s < cnt && c < ncv) v = st[(sd.src_off + s0 + s) * p.nchan + c0 + c];
+    s_st[idx] = v;
+  }
+  if (gauss) {
+    for (int s = tid; s < NS; s += NBT) {
+      R4 v;
+      v.x = v.y = v.z = v.w = R(0);
+      if (s < cnt) {
+        const int gi = s0 + s - sd.npsrc;
+        const double R_ = sd.gshape[3 * gi + 2];
+        v.x = static_cast<R>(sd.gshape[3 * gi]);
+        v.y = static_cast<R>(sd.gshape[3 * gi + 1]);
+        v.z = static_cast<R>(R_ * R_);
+        v.w = static_cast<R>(R_);
+      }
+      s_gs[s] = v;
+    }
+  }
+}
+
+template <class R, int NBT, int NC, int NS, int MODE>
+__global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
+  using L = Layout<R, NBT, NC, NS, MODE>;
+  using N = Num<R>;
+  using R2 = typename N::R2;
+  using R4 = typename N::R4;
+  constexpr int NAT = L::NAT;
+  constexpr int NW = L::NW;
+
+  __shared__ double s_uvw[NAT][3];
+  __shared__ double s_pnt[NAT][2];
+  __shared__ R4 s_st[NS * NC];
+  __shared__ R4 s_gs[NS];
+  __shared__ double2 s_scr[NW > 0 ? NW : 1];
+  __shared__ __attribute__((aligned(16))) char s_ab[L::AB_BYTES];
+  __shared__ __attribute__((aligned(16))) char s_rho_raw[L::RHO_BYTES > 0 ? L::RHO_BYTES : 16];
+  __shared__ __attribute__((aligned(16))) char s_geo_raw[L::GEO_BYTES > 0 ? L::GEO_BYTES : 16];
+  __shared__ int s_lpq[L::GRAD ? NBT : 1];
+  R2 *s_a = reinterpret_cast<R2 *>(s_ab);
+  R2 *s_beta = reinterpret_cast<R2 *>(s_ab + L::A_BYTES);
+  R *s_red = reinterpret_cast<R *>(s_ab);
+  R2 *s_rho = reinterpret_cast<R2 *>(s_rho_raw);
+  R4 *s_geo = reinterpret_cast<R4 *>(s_geo_raw);
+
+  // ---- work item ----------------------------------------------------------
+  const int item = blockIdx.x;
+  const int set_rank = item / p.items_per_set;
+  const int local_item = item - set_rank * p.items_per_set;
+  const int set = p.order ? p.order[set_rank] : set_rank;
+  const SetDesc sd = p.sets ? p.sets[set] : p.one;
+  int rem = local_item;
+  const int tile = rem % p.ntile;
+  rem /= p.ntile;
+  const int chb = rem % p.nchb;
+  const int tc = rem / p.nchb;
+
+  const int tid = threadIdx.x;
+  const int bl = p.tile_bl[tile * NBT + tid];
+  const int lpq = p.tile_lpq[tile * NBT + tid];
+  const int lp = lpq & 0xffff, lq = lpq >> 16;
+  const bool active = bl >= 0;
+  const int c0 = chb * NC;
+  const int ncv = min(NC, p.nchan - c0);
+  const int nsrc = sd.npsrc + sd.ngsrc;
+  const int t0 = tc * p.tchunk;
+  const int t1 = min(p.ntime, t0 + p.tchunk);
+  const int npt = (sd.npsrc + NS - 1) / NS;
+  const int ngt = (sd.ngsrc + NS - 1) / NS;
+  const int nst = npt + ngt;
+
+  // per-channel constants of this thread's channels
+  R gq[NC];  // -pi^2/(4 ln 2) (nu/c)^2
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const double nuc = c < ncv ? p.nu_c[c0 + c] : 0.0;
+    gq[c] = static_cast<R>(-kGauss * nuc * nuc);
+  }
+  // gains of this baseline's antennas
+  double2 gp0 = make_double2(1, 0), gp1 = gp0, gq0 = gp0, gq1 = gp0;
+  if (active) {
+    const int ap = p.tile_ant[tile * NAT + lp], aq = p.tile_ant[tile * NAT + lq];
+    gp0 = make_double2(p.gains[4 * ap + 0], p.gains[4 * ap + 1]);
+    gp1 = make_double2(p.gains[4 * ap + 2], p.gains[4 * ap + 3]);
+    gq0 = make_double2(p.gains[4 * aq + 0], p.gains[4 * aq + 1]);
+    gq1 = make_double2(p.gains[4 * aq + 2], p.gains[4 * aq + 3]);
+  }
+
+  Comp chi;
+
+  for (int t = t0; t < t1; ++t) {
+    __syncthreads();
+    for (int i = tid; i < NAT; i += NBT) {
+      const int a = p.tile_ant[tile * NAT + i];
+      double u = 0, v = 0, w = 0, pl = 0, pm = 0;
+      if (a >= 0) {
+        const double *x = p.uvw + (static_cast<int64_t>(t) * p.na + a) * 3;
+        u = x[0];
+        v = x[1];
+        w = x[2];
+        if (p.beam) {
+          const double *q = p.pointing + (static_cast<int64_t>(t) * p.na + a) * 2;
+          pl = q[0];
+          pm = q[1];
+        }
+      }
+      s_uvw[i][0] = u;
+      s_uvw[i][1] = v;
+      s_uvw[i][2] = w;
+      s_pnt[i][0] = pl;
+      s_pnt[i][1] = pm;
+    }
+    __syncthreads();
+    const R du = static_cast<R>(s_uvw[lp][0] - s_uvw[lq][0]);
+    const R dv = static_cast<R>(s_uvw[lp][1] - s_uvw[lq][1]);
+    const R dw = static_cast<R>(s_uvw[lp][2] - s_uvw[lq][2]);
+
+    // ---- pass 1: source sums ----------------------------------------------
+    double acc[NC][8];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int k = 0; k < 8; ++k) acc[c][k] = 0.0;
+
+    for (int k = 0; k < nst; ++k) {
+      const bool gauss = k >= npt;
+      const int s0 = gauss ? sd.npsrc + (k - npt) * NS : k * NS;
+      const int cnt = min(NS, (gauss ? nsrc : sd.npsrc) - s0);
+      __syncthreads();
+      stage_tile<R, NBT, NC, NS, MODE, false>(p, sd, tile, s0, cnt, gauss, c0, ncv, s_uvw,
+                                              s_pnt, s_a, s_beta, s_st, s_gs);
+      __syncthreads();
+      if (!active) continue;
+      R in[NC][8];
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) in[c][j] = R(0);
+      const R2 *ap_row = s_a + lp * NC;
+      const R2 *aq_row = s_a + lq * NC;
+      if (!gauss) {
+        for (int s = 0; s < cnt; ++s) {
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            const R2 ap = ap_row[s * L::AST + c];
+            const R2 aq = aq_row[s * L::AST + c];
+            const R4 st = s_st[s * NC + c];
+            const R cr = ap.x * aq.x + ap.y * aq.y;
+            const R ci = ap.y * aq.x - ap.x * aq.y;
+            in[c][0] += cr * st.x;
+            in[c][1] += ci * st.x;
+            in[c][2] += cr * st.y;
+            in[c][3] += ci * st.y;
+            in[c][4] += cr * st.z;
+            in[c][5] += ci * st.z;
+            in[c][6] += cr * st.w;
+            in[c][7] += ci * st.w;
+          }
+        }
+      } else {
+        for (int s = 0; s < cnt; ++s) {
+          const R4 g = s_gs[s];
+          const R A = du * g.x + dv * g.y;
+          const R B = du * g.y - dv * g.x;
+          const R Qf = A * A + g.z * B * B;
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            const R2 ap = ap_row[s * L::AST + c];
+            const R2 aq = aq_row[s * L::AST + c];
+            const R4 st = s_st[s * NC + c];
+            const R S = N::exp_(gq[c] * Qf);
+            const R cr = (ap.x * aq.x + ap.y * aq.y) * S;
+            const R ci = (ap.y * aq.x - ap.x * aq.y) * S;
+            in[c][0] += cr * st.x;
+            in[c][1] += ci * st.x;
+            in[c][2] += cr * st.y;
+            in[c][3] += ci * st.y;
+            in[c][4] += cr * st.z;
+            in[c][5] += ci * st.z;
+            in[c][6] += cr * st.w;
+            in[c][7] += ci * st.w;
+          }
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[c][j] += static_cast<double>(in[c][j]);
+    }
+
+    // ---- epilogue: V, residual, chi^2 --------------------------------------
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const bool ok = active && c < ncv;
+      // Stokes sums -> 2x2 coherency (eq. brightness_term)
+      const double SIr = acc[c][0], SIi = acc[c][1], SQr = acc[c][2], SQi = acc[c][3];
+      const double SUr = acc[c][4], SUi = acc[c][5], SVr = acc[c][6], SVi = acc[c][7];
+      double Vr[4], Vi[4];
+      Vr[0] = SIr + SQr;  // xx
+      Vi[0] = SIi + SQi;
+      Vr[1] = SUr - SVi;  // xy = S_U + i S_V
+      Vi[1] = SUi + SVr;
+      Vr[2] = SUr + SVi;  // yx = S_U - i S_V
+      Vi[2] = SUi - SVr;
+      Vr[3] = SIr - SQr;  // yy
+      Vi[3] = SIi - SQi;
+      // gains: V_ij *= g_pi conj(g_qj)
+      const double2 gpi[2] = {gp0, gp1};
+      const double2 gqj[2] = {gq0, gq1};
+      double2 gg[4];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const double2 a = gpi[i], b = gqj[j];
+          gg[2 * i + j] = make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+        }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double r = Vr[k] * gg[k].x - Vi[k] * gg[k].y;
+        const double i = Vr[k] * gg[k].y + Vi[k] * gg[k].x;
+        Vr[k] = r;
+        Vi[k] = i;
+      }
+      const int64_t vidx =
+          ((static_cast<int64_t>(t) * p.nbl + (active ? bl : 0)) * p.nchan + c0 + c) * 4;
+      if (MODE == MODE_PREDICT) {
+        if (ok) {
+          R2 *out = static_cast<R2 *>(p.vis) + vidx;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            R2 v;
+            v.x = static_cast<R>(Vr[k]);
+            v.y = static_cast<R>(Vi[k]);
+            out[k] = v;
+          }
+        }
+      } else {
+        double Yr[4] = {0, 0, 0, 0}, Yi[4] = {0, 0, 0, 0};
+        if (ok) {
+          const R2 *D = static_cast<const R2 *>(p.data) + vidx;
+          const R *W = static_cast<const R *>(p.weight) + vidx;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const R2 d = D[k];
+            const double w = static_cast<double>(W[k]);
+            const double rr = Vr[k] - static_cast<double>(d.x);
+            const double ri = Vi[k] - static_cast<double>(d.y);
+            chi.add(w * (rr * rr + ri * ri));
+            Yr[k] = w * rr;
+            Yi[k] = w * ri;
+          }
+        }
+        if (MODE == MODE_GRAD) {
+          // Z_ij = Y_ij conj(g_pi) g_qj, then rho_{I,Q,U,V} (see the adjoint)
+          double Zr[4], Zi[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            // conj(g_pi g_qj^*) = conj(gg)
+            Zr[k] = Yr[k] * gg[k].x + Yi[k] * gg[k].y;
+            Zi[k] = Yi[k] * gg[k].x - Yr[k] * gg[k].y;
+          }
+          // rho_I = conj(Zxx) + conj(Zyy), rho_Q = conj(Zxx) - conj(Zyy),
+          // rho_U = conj(Zxy) + conj(Zyx), rho_V = i (conj(Zxy) - conj(Zyx))
+          R2 *rho = s_rho + (tid * NC + c) * 4;
+          R2 v;
+          v.x = static_cast<R>(Zr[0] + Zr[3]);
+          v.y = static_cast<R>(-(Zi[0] + Zi[3]));
+          rho[0] = v;
+          v.x = static_cast<R>(Zr[0] - Zr[3]);
+          v.y = static_cast<R>(-(Zi[0] - Zi[3]));
+          rho[1] = v;
+          v.x = static_cast<R>(Zr[1] + Zr[2]);
+          v.y = static_cast<R>(-(Zi[1] + Zi[2]));
+          rho[2] = v;
+          // i (a - b) with a - b = conj(Zxy) - conj(Zyx) = (Zr1 - Zr2) - i (Zi1 - Zi2)
+          v.x = static_cast<R>(Zi[1] - Zi[2]);
+          v.y = static_cast<R>(Zr[1] - Zr[2]);
+          rho[3] = v;
+        }
+      }
+    }
+
+    // ---- pass 2: adjoint ----------------------------------------------------
+    if (MODE == MODE_GRAD) {
+      {
+        R4 g;
+        g.x = du;
+        g.y = dv;
+        g.z = dw;
+        g.w = R(0);
+        s_geo[tid] = g;
+        s_lpq[tid] = active ? lpq : -1;
+      }
+      const int lane = tid % kWave, wave = tid / kWave;
+      const int sl = lane / NC, cl = lane - (lane / NC) * NC;
+      const bool lane_ok_c = cl < ncv;
+      const double nuc_l = lane_ok_c ? p.nu_c[c0 + cl] : 0.0;
+      const R tpnc = static_cast<R>(2.0 * kPi * nuc_l);
+      const R gq_l = static_cast<R>(-kGauss * nuc_l * nuc_l);
+      const R lnfr_l = static_cast<R>(lane_ok_c ? p.lnfr[c0 + cl] : 0.0);
+      // gradient partials: [set][item][nsrc][10], sets laid out by src_off
+      double *gout = p.grad_part + sd.src_off * p.items_per_set * 10 +
+                     static_cast<int64_t>(local_item) * nsrc * 10;
+      for (int k = 0; k < nst; ++k) {
+        const bool gauss = k >= npt;
+        const int s0 = gauss ? sd.npsrc + (k - npt) * NS : k * NS;
+        const int cnt = min(NS, (gauss ? nsrc : sd.npsrc) - s0);
+        __syncthreads();
+        stage_tile<R, NBT, NC, NS, MODE, true>(p, sd, tile, s0, cnt, gauss, c0, ncv, s_uvw,
+                                               s_pnt, s_a, s_beta, s_st, s_gs);
+        __syncthreads();
+        R gl[10];
+#pragma unroll
+        for (int j = 0; j < 10; ++j) gl[j] = R(0);
+        if (sl < cnt && lane_ok_c) {
+          const R4 st = s_st[sl * NC + cl];
+          const double2 lo = p.src_lon[sd.src_off + s0 + sl];
+          const R lon = static_cast<R>(lo.x), mon = static_cast<R>(lo.y);
+          R4 gsh;
+          gsh.x = gsh.y = gsh.z = gsh.w = R(0);
+          if (gauss) gsh = s_gs[sl];
+          const R2 *arow = s_a + sl * L::AST + cl;
+          const R2 *brow = s_beta + sl * L::AST + cl;
+          for (int bi = wave; bi < NBT; bi += NW) {
+            const int q = s_lpq[bi];
+            if (q < 0) continue;
+            const int bp_ = q & 0xffff, bq_ = q >> 16;
+            const R4 geo = s_geo[bi];
+            const R2 ap = arow[bp_ * NC], aq = arow[bq_ * NC];
+            const R2 bp = brow[bp_ * NC], bq = brow[bq_ * NC];
+            const R2 *rho = s_rho + (bi * NC + cl) * 4;
+            const R2 r0 = rho[0], r1 = rho[1], r2 = rho[2], r3 = rho[3];
+            R cr = ap.x * aq.x + ap.y * aq.y;
+            R ci = ap.y * aq.x - ap.x * aq.y;
+            R A = R(0), B = R(0);
+            if (gauss) {
+              A = geo.x * gsh.x + geo.y * gsh.y;
+              B = geo.x * gsh.y - geo.y * gsh.x;
+              const R S = N::exp_(gq_l * (A * A + gsh.z * B * B));
+              cr *= S;
+              ci *= S;
+            }
+            // d/d(I,Q,U,V): Re(c rho_k)   (times the spectral factor later)
+            gl[2] += cr * r0.x - ci * r0.y;
+            gl[3] += cr * r1.x - ci * r1.y;
+            gl[4] += cr * r2.x - ci * r2.y;
+            gl[5] += cr * r3.x - ci * r3.y;
+            // P = c * Phi, Phi = sum_k St'_k rho_k
+            const R phr = st.x * r0.x + st.y * r1.x + st.z * r2.x + st.w * r3.x;
+            const R phi = st.x * r0.y + st.y * r1.y + st.z * r2.y + st.w * r3.y;
+            const R Pr = cr * phr - ci * phi;
+            const R Pi = cr * phi + ci * phr;
+            gl[6] += Pr;
+            const R kl = tpnc * (geo.x - geo.z * lon);
+            const R km = tpnc * (geo.y - geo.z * mon);
+            gl[0] += (bp.x + bq.x) * Pr + kl * Pi;
+            gl[1] += (bp.y + bq.y) * Pr + km * Pi;
+            if (gauss) {
+              gl[7] += (A * geo.x - gsh.z * B * geo.y) * Pr;
+              gl[8] += (A * geo.y + gsh.z * B * geo.x) * Pr;
+              gl[9] += (B * B) * Pr;
+            }
+          }
+          // scale: Stokes by the spectral factor, alpha by ln(nu/nu_ref),
+          // shape by 2 gq (and 2 R gq for R)
+          const double al = sd.alpha[s0 + sl];
+          const R f = static_cast<R>(exp(al * static_cast<double>(lnfr_l)));
+          gl[2] *= f;
+          gl[3] *= f;
+          gl[4] *= f;
+          gl[5] *= f;
+          gl[6] *= lnfr_l;
+          gl[7] *= R(2) * gq_l;
+          gl[8] *= R(2) * gq_l;
+          gl[9] *= R(2) * gsh.w * gq_l;
+        }
+        __syncthreads();  // the reduction buffer aliases the a/beta tiles
+#pragma unroll
+        for (int j = 0; j < 10; ++j) s_red[(wave * kWave + lane) * 10 + j] = gl[j];
+        __syncthreads();
+        for (int idx = tid; idx < NS * 10; idx += NBT) {
+          const int s = idx / 10, j = idx - (idx / 10) * 10;
+          if (s >= cnt) continue;
+          double sum = 0.0;
+          for (int w = 0; w < NW; ++w)
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+              sum += static_cast<double>(s_red[(w * kWave + s * NC + c) * 10 + j]);
+          double *dst = gout + static_cast<int64_t>(s0 + s) * 10 + j;
+          if (t == t0)
+            *dst = sum;
+          else
+            *dst += sum;
+        }
+      }
+    }
+  }
+
+  if (MODE != MODE_PREDICT) {
+    const Comp r = block_reduce<NBT>(chi, s_scr);
+    if (tid == 0)
+      p.chi2_part[static_cast<int64_t>(set) * p.items_per_set + local_item] =
+          make_double2(r.s, r.c);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Finalize: deterministic compensated sums of the per-item partials.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void finalize_chi2(const KParams p) {
+  __shared__ double2 scr[256 / kWave];
+  const int set = blockIdx.x;
+  const SetDesc sd = p.sets ? p.sets[set] : p.one;
+  Comp acc;
+  const double2 *part = p.chi2_part + static_cast<int64_t>(set) * p.items_per_set;
+  for (int i = threadIdx.x; i < p.items_per_set; i += 256) {
+    const double2 v = part[i];
+    acc.merge(v.x, v.y);
+  }
+  const Comp r = block_reduce<256>(acc, scr);
+  if (threadIdx.x == 0) p.chi2_out[set] = r.s + r.c;
+}
+
+__global__ __launch_bounds__(256) void finalize_grad(const KParams p) {
+  const int set = blockIdx.y;
+  const SetDesc sd = p.sets ? p.sets[set] : p.one;
+  const int nsrc = sd.npsrc + sd.ngsrc;
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx >= nsrc * 10) return;
+  const int64_t stride = static_cast<int64_t>(nsrc) * 10;
+  const double *src = p.grad_part + sd.src_off * p.items_per_set * 10 + idx;
+  Comp acc;
+  for (int i = 0; i < p.items_per_set; ++i) acc.add(src[i * stride]);
+  p.grad_out[sd.src_off * 10 + idx] = 2.0 * (acc.s + acc.c);
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+template <class R, int NBT, int NC, int NS, int MODE>
+static hipError_t launch_main(const KParams &p, int nitems, hipStream_t stream) {
+  hipLaunchKernelGGL((rime_main<R, NBT, NC, NS, MODE>), dim3(nitems), dim3(NBT), 0, stream, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep(const KParams &p, bool fp64, int max_nsrc, hipStream_t stream) {
+  dim3 grid((max_nsrc + 255) / 256, p.nset);
+  if (fp64)
+    hipLaunchKernelGGL(prep_sources<double>, grid, dim3(256), 0, stream, p);
+  else
+    hipLaunchKernelGGL(prep_sources<float>, grid, dim3(256), 0, stream, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const KParams &p, int mode, int max_nsrc, hipStream_t stream) {
+  if (mode == MODE_PREDICT) return hipSuccess;
+  hipLaunchKernelGGL(finalize_chi2, dim3(p.nset), dim3(256), 0, stream, p);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || mode != MODE_GRAD) return e;
+  dim3 grid((max_nsrc * 10 + 255) / 256, p.nset);
+  hipLaunchKernelGGL(finalize_grad, grid, dim3(256), 0, stream, p);
+  return hipGetLastError();
+}
+
+// Compiled variants, indexed per (mode, precision).
+struct VariantEntry {
+  Variant v;
+  hipError_t (*fn)(const KParams &, int, hipStream_t);
+};
+
+#define RIME_V(R, NBT, NC, NS, M) \
+  { {NBT, NC, NS}, &launch_main<R, NBT, NC, NS, M> }
+
+static const VariantEntry kVariants[3][2][4] = {
+    // MODE_PREDICT
+    {{RIME_V(double, 64, 2, 32, MODE_PREDICT), RIME_V(double, 256, 2, 32, MODE_PREDICT),
+      RIME_V(double, 1024, 2, 32, MODE_PREDICT), RIME_V(double, 256, 4, 16, MODE_PREDICT)},
+     {RIME_V(float, 64, 2, 32, MODE_PREDICT), RIME_V(float, 256, 2, 32, MODE_PREDICT),
+      RIME_V(float, 1024, 2, 32, MODE_PREDICT), RIME_V(float, 256, 4, 16, MODE_PREDICT)}},
+    // MODE_CHI2
+    {{RIME_V(double, 64, 2, 32, MODE_CHI2), RIME_V(double, 256, 2, 32, MODE_CHI2),
+      RIME_V(double, 1024, 2, 32, MODE_CHI2), RIME_V(double, 256, 4, 16, MODE_CHI2)},
+     {RIME_V(float, 64, 2, 32, MODE_CHI2), RIME_V(float, 256, 2, 32, MODE_CHI2),
+      RIME_V(float, 1024, 2, 32, MODE_CHI2), RIME_V(float, 256, 4, 16, MODE_CHI2)}},
+    // MODE_GRAD
+    {{RIME_V(double, 64, 2, 32, MODE_GRAD), RIME_V(double, 256, 2, 32, MODE_GRAD),
+      RIME_V(double, 256, 4, 16, MODE_GRAD), RIME_V(double, 64, 4, 16, MODE_GRAD)},
+     {RIME_V(float, 64, 2, 32, MODE_GRAD), RIME_V(float, 256, 2, 32, MODE_GRAD),
+      RIME_V(float, 1024, 2, 32, MODE_GRAD), RIME_V(float, 256, 4, 16, MODE_GRAD)}},
+};
+
+int variant_count(int /*mode*/, int /*prec*/) { return 4; }
+
+const Variant *variant_info(int mode, int prec, int index) {
+  if (mode < 0 || mode > 2 || prec < 0 || prec > 1 || index < 0 || index >= 4) return nullptr;
+  return &kVariants[mode][prec][index].v;
+}
+
+hipError_t launch_variant(int mode, int prec, int index, const KParams &p, int nitems,
+                          hipStream_t stream) {
+  return kVariants[mode][prec][index].fn(p, nitems, stream);
+}
+
+}  // namespace rime

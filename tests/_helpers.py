@@ -1,0 +1,67 @@
+"""Shared helpers for the GPU parity tests: problem construction (inputs from
+rime_synth, observed data from the oracle) and the error metrics."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle.rime_oracle as O
+from rime_synth import make_problem
+
+# Tolerances: FP64 path against the oracle, mixed path against the oracle.
+TOL = {0: 1e-12, 1: 1e-5}
+
+
+def round_inputs(D, W, prec):
+    """Mixed precision consumes complex64/float32 data; the oracle gets the
+    same rounded values so parity measures compute error only."""
+    if prec == 1:
+        return (D.astype(np.complex64).astype(np.complex128),
+                W.astype(np.float32).astype(np.float64))
+    return D, W
+
+
+def small_problem(name="c1", ntime=2, nchan=8, npsrc=40, ngsrc=20, na=None, key=None):
+    pr = make_problem(name, ntime=ntime, nchan=nchan, npsrc=npsrc, ngsrc=ngsrc, na=na, key=key)
+    D = O.model_vis(pr.obs, pr.truth) + pr.noise
+    return pr, D, pr.weight
+
+
+def vis_error(V, Vref, sky, obs):
+    """max over (t, baseline, corr) of |dV| / F_nu, maximised over channels."""
+    F = O.total_flux(sky, obs.freq, obs.ref_freq)          # [nchan]
+    err = np.abs(np.asarray(V) - np.asarray(Vref)).max(axis=(0, 1, 3))
+    return float((err / F).max())
+
+
+def rel(a, b):
+    return abs(a - b) / abs(b)
+
+
+def grad_errors(g, gref, npsrc):
+    """Per parameter type: ||dg||_2 / ||g||_2 (shape columns over Gaussians only)."""
+    out = {}
+    names = ["l", "m", "I", "Q", "U", "V", "alpha", "el", "em", "R"]
+    for k, nm in enumerate(names):
+        rows = slice(npsrc, None) if k >= 7 else slice(None)
+        a, b = np.asarray(g)[rows, k], np.asarray(gref)[rows, k]
+        if b.size == 0:
+            continue
+        nb = np.linalg.norm(b)
+        out[nm] = float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
+    return out
+
+
+def grad_component_worst(g, gref, npsrc):
+    """Largest |dg_i| / max(|g_i|, 1e-3 * max_type |g|) over all components."""
+    g, gref = np.asarray(g), np.asarray(gref)
+    worst = 0.0
+    for k in range(10):
+        rows = slice(npsrc, None) if k >= 7 else slice(None)
+        a, b = g[rows, k], gref[rows, k]
+        if b.size == 0:
+            continue
+        floor = 1e-3 * np.abs(b).max()
+        if floor == 0:
+            continue
+        worst = max(worst, float((np.abs(a - b) / np.maximum(np.abs(b), floor)).max()))
+    return worst

@@ -1,0 +1,411 @@
+"""Parity of the HIP path (through the C ABI) against the CPU oracle.
+
+FP64 path: visibilities within 1e-12 of the total flux F_nu, chi^2 and the
+gradient (per parameter type, 2-norm) within 1e-12 relative.  Mixed path:
+1e-5 for all three.  Inputs are seeded synthetic problems with the shapes of
+the benchmark configurations, shrunk in time, channels and sources so that the
+oracle finishes in seconds while still spanning several baseline tiles,
+channel blocks and source tiles with ragged tails.
+"""
+import numpy as np
+import pytest
+
+import oracle.rime_oracle as O
+from rime_synth import Observation, Sky, make_problem
+from tests._helpers import (TOL, grad_component_worst, grad_errors, rel, round_inputs,
+                            small_problem, vis_error)
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+R = pytest.importorskip("paper_1501_07719_amd")
+
+
+def say(*a):
+    print("[gpu]", *a, flush=True)
+
+
+def dev(x, dt):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dt, device="cuda")
+
+
+def run_all(obs, sky, D, W, prec, modes=("predict", "chi2", "grad"), variant=None):
+    """Run the requested entry points once; returns dict of numpy results."""
+    plan = R.Plan(obs)
+    dsky = R.DeviceSky.from_host(sky)
+    cdt = torch.complex128 if prec == R.FP64 else torch.complex64
+    rdt = torch.float64 if prec == R.FP64 else torch.float32
+    out = {}
+    shp = (obs.ntime, obs.nbl, obs.nchan, 4)
+    if "predict" in modes:
+        if variant is not None:
+            plan.set_variant(R.MODE_PREDICT, prec, variant)
+        vis = torch.empty(shp, dtype=cdt, device="cuda")
+        ws = R.workspace(plan, R.MODE_PREDICT, prec, 1, sky.nsrc)
+        R.rime_predict(plan, dsky, prec, vis, ws)
+        out["vis"] = vis.cpu().numpy().astype(np.complex128)
+    if "chi2" in modes or "grad" in modes:
+        Dd, Wd = dev(D, cdt), dev(W, rdt)
+        chi2 = torch.empty(1, dtype=torch.float64, device="cuda")
+        if "chi2" in modes:
+            if variant is not None:
+                plan.set_variant(R.MODE_CHI2, prec, variant)
+            ws = R.workspace(plan, R.MODE_CHI2, prec, 1, sky.nsrc)
+            R.rime_chi2(plan, dsky, prec, Dd, Wd, chi2, ws)
+            out["chi2"] = float(chi2.item())
+        if "grad" in modes:
+            if variant is not None:
+                plan.set_variant(R.MODE_CHI2_GRAD, prec, variant)
+            grad = torch.empty((sky.nsrc, 10), dtype=torch.float64, device="cuda")
+            ws = R.workspace(plan, R.MODE_CHI2_GRAD, prec, 1, sky.nsrc)
+            R.rime_chi2_grad(plan, dsky, prec, Dd, Wd, chi2, grad, ws)
+            out["chi2_g"] = float(chi2.item())
+            out["grad"] = grad.cpu().numpy()
+    torch.cuda.synchronize()
+    plan.close()
+    return out
+
+
+_ORACLE = {}
+
+
+def oracle_results(key, obs, sky, D, W, grad=True):
+    if key not in _ORACLE:
+        V = O.model_vis(obs, sky)
+        c, g = O.chi2_and_grad(obs, sky, D, W) if grad else (O.chi2(obs, sky, D, W), None)
+        _ORACLE[key] = (V, c, g)
+    return _ORACLE[key]
+
+
+def check(name, obs, sky, D, W, prec, res, ref, grad=True):
+    V, c, g = ref
+    tol = TOL[prec]
+    ev = vis_error(res["vis"], V, sky, obs) if "vis" in res else 0.0
+    ec = rel(res["chi2"], c) if "chi2" in res else 0.0
+    say(name, f"prec={prec} vis_err/F={ev:.3e} chi2_rel={ec:.3e}")
+    assert ev <= tol, (name, ev)
+    assert ec <= tol, (name, ec)
+    if grad and "grad" in res:
+        assert rel(res["chi2_g"], c) <= tol
+        ge = grad_errors(res["grad"], g, sky.npsrc)
+        say(name, "grad", {k: f"{v:.2e}" for k, v in ge.items()})
+        assert max(ge.values()) <= tol, (name, ge)
+        # per component, relative to max(|g_i|, 1e-3 of the largest of its type):
+        # components that nearly cancel lose digits in both implementations
+        wc = grad_component_worst(res["grad"], g, sky.npsrc)
+        say(name, f"worst component {wc:.2e}")
+        assert wc <= 100 * tol, (name, wc)
+        # point sources have zero shape gradient
+        assert np.all(res["grad"][:sky.npsrc, 7:] == 0.0)
+
+
+# --------------------------------------------------------------------------- #
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_c0_full(prec):
+    """Config c0 in full: 7 antennas, 10 timesteps, 16 channels, 20 points."""
+    pr = make_problem("c0")
+    D = O.model_vis(pr.obs, pr.truth) + pr.noise
+    D, W = round_inputs(D, pr.weight, prec)
+    ref = oracle_results(("c0", prec), pr.obs, pr.sky, D, W)
+    say("c0_full", prec)
+    res = run_all(pr.obs, pr.sky, D, W, prec)
+    check("c0_full", pr.obs, pr.sky, D, W, prec, res, ref)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_c1_subset(prec):
+    """c1 observation (64 antennas, beam, gains) at 2 timesteps x 8 channels
+    with 40 point + 20 Gaussian sources: two 1024-baseline tiles, several
+    channel blocks, ragged source tiles."""
+    pr, D, W = small_problem("c1", ntime=2, nchan=8, npsrc=40, ngsrc=20)
+    D, W = round_inputs(D, W, prec)
+    ref = oracle_results(("c1s", prec), pr.obs, pr.sky, D, W)
+    say("c1_subset", prec)
+    res = run_all(pr.obs, pr.sky, D, W, prec)
+    check("c1_subset", pr.obs, pr.sky, D, W, prec, res, ref)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_all_variants(prec):
+    """Every compiled kernel variant of every entry point matches the oracle."""
+    pr, D, W = small_problem("c1", ntime=1, nchan=5, npsrc=35, ngsrc=9, na=24, key=11)
+    D, W = round_inputs(D, W, prec)
+    ref = oracle_results(("var", prec), pr.obs, pr.sky, D, W)
+    for mode_name, mode in (("predict", R.MODE_PREDICT), ("chi2", R.MODE_CHI2),
+                            ("grad", R.MODE_CHI2_GRAD)):
+        for vi in range(R.rime_variant_count(mode, prec)):
+            say("variant", mode_name, prec, vi, R.rime_variant_info(mode, prec, vi))
+            res = run_all(pr.obs, pr.sky, D, W, prec, modes=(mode_name,), variant=vi)
+            check(f"variant{mode_name}{vi}", pr.obs, pr.sky, D, W, prec, res, ref)
+
+
+def _edge_problem(kind):
+    rng = np.random.default_rng(5)
+    pr = make_problem("c1", ntime=2, nchan=3, npsrc=3, ngsrc=2, na=9, key=21)
+    obs, sky = pr.obs, pr.sky
+    if kind == "gauss_only":
+        sky = Sky(lm=sky.lm[3:], stokes=sky.stokes[3:], alpha=sky.alpha[3:], gshape=sky.gshape)
+    elif kind == "single_point":
+        sky = sky.subset(1, 0)
+    elif kind == "one_channel":
+        obs = obs.chan_slice(1, 2)
+    elif kind == "two_antennas":
+        obs = Observation(ntime=obs.ntime, na=2, nchan=obs.nchan, ant1=np.array([0], np.int32),
+                          ant2=np.array([1], np.int32), uvw=obs.uvw[:, :2].copy(),
+                          freq=obs.freq, beam=True, pointing=obs.pointing[:, :2].copy(),
+                          gains=obs.gains[:2].copy())
+    elif kind == "shuffled_baselines":
+        # arbitrary order, swapped pairs, a duplicate and an autocorrelation
+        n = obs.nbl
+        perm = rng.permutation(n)
+        a1, a2 = obs.ant1[perm].copy(), obs.ant2[perm].copy()
+        sw = rng.random(n) < 0.5
+        a1[sw], a2[sw] = a2[sw], a1[sw].copy()
+        a1 = np.concatenate([a1, a1[:1], [4]]).astype(np.int32)
+        a2 = np.concatenate([a2, a2[:1], [4]]).astype(np.int32)
+        obs = Observation(**{**obs.__dict__, "ant1": a1, "ant2": a2})
+    elif kind == "no_beam_gains":
+        obs = Observation(**{**obs.__dict__, "beam": False, "pointing": None, "gains": None})
+    elif kind == "phase_centre":
+        sky = Sky(lm=np.zeros((1, 2)), stokes=np.array([[2.0, 0.3, -0.2, 0.1]]),
+                  alpha=np.array([-0.5]))
+        obs = Observation(**{**obs.__dict__, "pointing": np.zeros_like(obs.pointing)})
+    elif kind == "zero_width_gauss":
+        g = sky.gshape.copy()
+        g[:, :2] = 0
+        sky = Sky(lm=sky.lm, stokes=sky.stokes, alpha=sky.alpha, gshape=g)
+    # observed data follow the benchmark recipe: the model at the sky's
+    # parameters perturbed by 1 %, plus noise
+    nz = np.random.default_rng(3).normal(0, 0.01, (obs.ntime, obs.nbl, obs.nchan, 4, 2))
+    truth = Sky.from_params(sky.params() * (1 + 0.01 * np.random.default_rng(4).standard_normal(
+        (sky.nsrc, 10))), sky.ngsrc)
+    D = O.model_vis(obs, truth) + nz[..., 0] + 1j * nz[..., 1]
+    W = np.full(D.shape, 1e4)
+    return obs, sky, D, W
+
+
+EDGES = ["gauss_only", "single_point", "one_channel", "two_antennas", "shuffled_baselines",
+         "no_beam_gains", "phase_centre", "zero_width_gauss"]
+
+
+@pytest.mark.parametrize("kind", EDGES)
+@pytest.mark.parametrize("prec", [0, 1])
+def test_edge_cases(kind, prec):
+    obs, sky, D, W = _edge_problem(kind)
+    D, W = round_inputs(D, W, prec)
+    say("edge", kind, prec)
+    ref = oracle_results(("edge", kind, prec), obs, sky, D, W)
+    res = run_all(obs, sky, D, W, prec)
+    check("edge_" + kind, obs, sky, D, W, prec, res, ref,
+          grad=kind not in ("phase_centre",))
+
+
+def test_chi2_zero_at_model():
+    """chi^2 = 0 (to rounding) when the data equal the FP64 model."""
+    pr = make_problem("c0")
+    V = O.model_vis(pr.obs, pr.sky)
+    say("chi2_zero")
+    res = run_all(pr.obs, pr.sky, V, pr.weight, 0, modes=("chi2",))
+    scale = float(np.sum(pr.weight * np.abs(V) ** 2))
+    assert res["chi2"] <= 1e-24 * scale
+
+
+def test_grad_matches_central_fd_fp64():
+    """GPU FP64 gradient against central finite differences of the GPU FP64
+    chi^2 on 20 random (source, parameter) pairs, step 1e-6 max(|theta|, 1e-3)
+    (c2 recipe shrunk; data at the model plus noise so that chi^2, and with
+    it the rounding noise eps chi^2 / h of the difference quotient, is small)."""
+    pr = make_problem("c2", ntime=2, nchan=4, npsrc=12, ngsrc=8, key=2)
+    obs, sky = pr.obs, pr.sky
+    D = O.model_vis(obs, sky) + pr.noise
+    W = pr.weight
+    plan = R.Plan(obs)
+    Dd, Wd = dev(D, torch.complex128), dev(W, torch.float64)
+    chi2 = torch.empty(1, dtype=torch.float64, device="cuda")
+    grad = torch.empty((sky.nsrc, 10), dtype=torch.float64, device="cuda")
+    ws = R.workspace(plan, R.MODE_CHI2_GRAD, R.FP64, 1, sky.nsrc)
+    say("fd_fp64")
+    R.rime_chi2_grad(plan, R.DeviceSky.from_host(sky), R.FP64, Dd, Wd, chi2, grad, ws)
+    c0 = chi2.item()
+    g = grad.cpu().numpy()
+    rng = np.random.default_rng(7)
+    p0 = sky.params()
+    worst = 0.0
+    for _ in range(20):
+        s = int(rng.integers(sky.nsrc))
+        k = int(rng.integers(10 if s >= sky.npsrc else 7))
+        h = 1e-6 * max(abs(p0[s, k]), 1e-3)
+        vals = []
+        for sgn in (1, -1):
+            pp = p0.copy()
+            pp[s, k] += sgn * h
+            R.rime_chi2(plan, R.DeviceSky.from_host(Sky.from_params(pp, sky.ngsrc)), R.FP64, Dd,
+                        Wd, chi2, ws)
+            vals.append(chi2.item())
+        fd = (vals[0] - vals[1]) / (2 * h)
+        scale = np.abs(g[:, k]).max()
+        noise = 64 * 2.2e-16 * c0 / h
+        lim = 1e-5 * max(abs(g[s, k]), 1e-3 * scale) + noise
+        worst = max(worst, abs(fd - g[s, k]) / lim)
+        assert abs(fd - g[s, k]) <= lim, (s, k, fd, g[s, k], noise)
+    say(f"fd worst/limit {worst:.3f}")
+    plan.close()
+
+
+def test_converged_regime_mixed():
+    """Data = model + noise (a converged fit): the residual is at the noise
+    level, so the mixed-precision gradient error is set by the float32
+    visibility error relative to the residual.  The float32 error of V is
+    coherent with the source response while the residual is noise, so the
+    relative gradient error grows as sqrt(N_vis) |dV|_rms / |R|_rms (N_vis =
+    visibilities a source contributes to).  Checked: chi^2 to 1e-5; gradient
+    error (per type) within 3 sqrt(N_vis) |dV|_rms / |R|_rms; FP64 to 1e-12."""
+    pr = make_problem("c1", ntime=2, nchan=4, npsrc=20, ngsrc=10, na=16, key=51)
+    obs, sky = pr.obs, pr.sky
+    V = O.model_vis(obs, sky)
+    D = V + pr.noise
+    for prec in (0, 1):
+        Dr, Wr = round_inputs(D, pr.weight, prec)
+        c, g = O.chi2_and_grad(obs, sky, Dr, Wr)
+        say("converged", prec)
+        res = run_all(obs, sky, Dr, Wr, prec)
+        assert rel(res["chi2"], c) <= TOL[prec]
+        ge = max(grad_errors(res["grad"], g, sky.npsrc).values())
+        dv = np.sqrt(np.mean(np.abs(res["vis"] - V) ** 2))
+        rr = np.sqrt(np.mean(np.abs(Dr - V) ** 2))
+        nvis = obs.ntime * obs.nbl * obs.nchan
+        bound = max(TOL[prec], 3 * np.sqrt(nvis) * dv / rr)
+        say("converged", prec, f"grad_err={ge:.2e} dV/R={dv / rr:.2e} bound={bound:.2e}")
+        assert ge <= bound
+
+
+def test_autograd_function():
+    """RimeChi2 returns chi^2 and backpropagates the adjoint's gradient."""
+    from paper_1501_07719_amd.autograd import rime_chi2_autograd
+    pr, D, W = small_problem("c1", ntime=1, nchan=4, npsrc=10, ngsrc=5, na=16, key=31)
+    obs, sky = pr.obs, pr.sky
+    ref = oracle_results(("ag",), obs, sky, D, W)
+    plan = R.Plan(obs)
+    t = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda", requires_grad=True)
+    lm, st, al, gs = t(sky.lm), t(sky.stokes), t(sky.alpha), t(sky.gshape)
+    say("autograd")
+    c = rime_chi2_autograd(lm, st, al, gs, plan, dev(D, torch.complex128),
+                           dev(W, torch.float64), prec=R.FP64)
+    (2.0 * c).backward()
+    assert rel(c.item(), ref[1]) <= 1e-12
+    g = ref[2]
+    np.testing.assert_allclose(lm.grad.cpu().numpy(), 2 * g[:, 0:2], rtol=1e-9,
+                               atol=1e-9 * np.abs(g[:, 0:2]).max())
+    np.testing.assert_allclose(st.grad.cpu().numpy(), 2 * g[:, 2:6], rtol=1e-9,
+                               atol=1e-9 * np.abs(g[:, 2:6]).max())
+    np.testing.assert_allclose(gs.grad.cpu().numpy(), 2 * g[sky.npsrc:, 7:10], rtol=1e-9,
+                               atol=1e-9 * np.abs(g[sky.npsrc:, 7:10]).max())
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batched_matches_single_and_oracle(prec):
+    """Batched proposals with ragged source counts (1 .. 70) equal per-set
+    calls, and two of them equal the oracle."""
+    from rime_synth import make_batch_problem
+    bp = make_batch_problem(nset=7, ntime=2, nchan=4, nmin=1, nmax=70, key=41)
+    obs = bp.obs
+    Dm = O.model_vis(obs, bp.truth.subset(60, 20)) + bp.noise
+    D, W = round_inputs(Dm, bp.weight, prec)
+    cdt = torch.complex128 if prec == 0 else torch.complex64
+    rdt = torch.float64 if prec == 0 else torch.float32
+    Dd, Wd = dev(D, cdt), dev(W, rdt)
+    plan = R.Plan(obs)
+    skies = [R.DeviceSky.from_host(s) for s in bp.skies]
+    batch = R.rime_batch_create(plan, skies)
+    nset = len(skies)
+    chi2 = torch.empty(nset, dtype=torch.float64, device="cuda")
+    grad = torch.empty((batch.total_src, 10), dtype=torch.float64, device="cuda")
+    ws = torch.empty(batch.workspace_size(R.MODE_CHI2_GRAD, prec), dtype=torch.uint8,
+                     device="cuda")
+    say("batched", prec, [s.nsrc for s in skies])
+    R.rime_chi2_batched(batch, prec, Dd, Wd, chi2, grad, ws)
+    torch.cuda.synchronize()
+    cb, gb = chi2.cpu().numpy(), grad.cpu().numpy()
+    off = 0
+    c1 = torch.empty(1, dtype=torch.float64, device="cuda")
+    for i, s in enumerate(skies):
+        g1 = torch.empty((s.nsrc, 10), dtype=torch.float64, device="cuda")
+        ws1 = R.workspace(plan, R.MODE_CHI2_GRAD, prec, 1, s.nsrc)
+        R.rime_chi2_grad(plan, s, prec, Dd, Wd, c1, g1, ws1)
+        assert rel(cb[i], c1.item()) <= 1e-12
+        ge = grad_errors(gb[off:off + s.nsrc], g1.cpu().numpy(), s.npsrc)
+        assert max(ge.values()) <= 1e-10, (i, ge)
+        off += s.nsrc
+    off = 0
+    for i, s in enumerate(bp.skies[:2]):
+        c, g = O.chi2_and_grad(obs, s, D, W)
+        assert rel(cb[i], c) <= TOL[prec]
+        ge = grad_errors(gb[off:off + s.nsrc], g, s.npsrc)
+        assert max(ge.values()) <= TOL[prec], ge
+        off += s.nsrc
+    batch.close()
+    plan.close()
+
+
+def test_batched_graph_replays():
+    """hipGraph replay of the batched launch: every replay, with eager work
+    and parameter updates in between, equals the eager result."""
+    from rime_synth import make_batch_problem
+    bp = make_batch_problem(nset=5, ntime=2, nchan=4, nmin=3, nmax=40, key=43)
+    obs = bp.obs
+    D = O.model_vis(obs, bp.truth.subset(30, 10)) + bp.noise
+    Dd, Wd = dev(D, torch.complex64), dev(bp.weight, torch.float32)
+    plan = R.Plan(obs)
+    skies = [R.DeviceSky.from_host(s) for s in bp.skies]
+    batch = R.rime_batch_create(plan, skies)
+    nset = len(skies)
+    stream = torch.cuda.Stream()
+    chi2 = torch.empty(nset, dtype=torch.float64, device="cuda")
+    grad = torch.empty((batch.total_src, 10), dtype=torch.float64, device="cuda")
+    ws = torch.empty(batch.workspace_size(R.MODE_CHI2_GRAD, R.MIXED), dtype=torch.uint8,
+                     device="cuda")
+    say("graph")
+    rng = np.random.default_rng(0)
+    for rep in range(4):
+        # in-place parameter update between replays (the sampler's pattern)
+        for s in skies:
+            s.stokes.mul_(1.0 + 0.01 * rep)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            R.rime_chi2_batched(batch, R.MIXED, Dd, Wd, chi2, grad, ws, stream=stream,
+                                use_graph=True)
+        stream.synchronize()
+        cg, gg = chi2.cpu().numpy().copy(), grad.cpu().numpy().copy()
+        _ = torch.randn(1000, device="cuda").sum().item()  # eager work in between
+        with torch.cuda.stream(stream):
+            R.rime_chi2_batched(batch, R.MIXED, Dd, Wd, chi2, grad, ws, stream=stream,
+                                use_graph=False)
+        stream.synchronize()
+        np.testing.assert_array_equal(cg, chi2.cpu().numpy())
+        np.testing.assert_array_equal(gg, grad.cpu().numpy())
+        assert rng is not None
+    batch.close()
+    plan.close()
+
+
+def test_errors_are_reported():
+    """Invalid arguments return a status before anything is enqueued."""
+    pr = make_problem("c0")
+    plan = R.Plan(pr.obs)
+    dsky = R.DeviceSky.from_host(pr.sky)
+    vis = torch.empty((pr.obs.ntime, pr.obs.nbl, pr.obs.nchan, 4), dtype=torch.complex128,
+                      device="cuda")
+    small = torch.empty(16, dtype=torch.uint8, device="cuda")
+    say("errors")
+    with pytest.raises(R.RimeError) as e:
+        R.rime_predict(plan, dsky, R.FP64, vis, small)
+    assert e.value.status == 2
+    bad = R.DeviceSky(lm=dsky.lm, stokes=dsky.stokes, alpha=dsky.alpha, gshape=dsky.gshape,
+                      npsrc=0, ngsrc=0)
+    ws = R.workspace(plan, R.MODE_PREDICT, R.FP64, 1, pr.sky.nsrc)
+    with pytest.raises(R.RimeError) as e:
+        R.rime_predict(plan, bad, R.FP64, vis, ws)
+    assert e.value.status == 1
+    plan.close()

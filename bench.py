@@ -46,7 +46,9 @@ def parse():
     ap.add_argument("--config", default="c2", choices=["c1", "c2", "c4"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--only", default="", help="profile helper: 'grad-mixed' etc.")
+    ap.add_argument("--calib-copy", type=int, default=0,
+                    help="MiB copied device-to-device once before timing (a kernel of known "
+                         "traffic for calibrating HBM counters)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"))
     return ap.parse_args()
 
@@ -55,10 +57,11 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(name: str, seconds_target: float = 20.0):
+def cpu_baseline(name: str, seconds_target: float = 15.0):
     """Time the CPU oracle (chi^2 + autograd gradient) on a bounded sample of
-    the workload: the first timestep and first 8 channels, all baselines and
-    all sources.  Returns terms/s."""
+    the workload: the first timestep and the first nc channels, all baselines
+    and all sources, nc grown from 8 until the sample takes about
+    `seconds_target` seconds.  Returns terms/s."""
     import torch
 
     import oracle.rime_oracle as O
@@ -66,17 +69,28 @@ def cpu_baseline(name: str, seconds_target: float = 20.0):
 
     ncores = min(os.cpu_count() or 1, 16)
     torch.set_num_threads(ncores)
-    pr = make_problem(name, ntime=1, nchan=8)
-    obs, sky = pr.obs, pr.sky
-    D = O.model_vis(obs, pr.truth) + pr.noise
-    t0 = time.perf_counter()
-    O.chi2_and_grad(obs, sky, D, pr.weight, src_chunk=32)
-    dt = time.perf_counter() - t0
+    nc = 8
+    while True:
+        pr = make_problem(name, ntime=1, nchan=nc)
+        obs, sky = pr.obs, pr.sky
+        D = O.model_vis(obs, pr.truth) + pr.noise
+        t0 = time.perf_counter()
+        O.chi2_and_grad(obs, sky, D, pr.weight, src_chunk=32)
+        dt = time.perf_counter() - t0
+        full = make_problem_nchan(name)
+        if dt >= seconds_target / 3 or nc >= full:
+            break
+        nc = min(full, int(nc * seconds_target / max(dt, 1e-3)) + 1)
     terms = obs.ntime * obs.nbl * obs.nchan * sky.nsrc
     return {"value": terms / dt, "unit": "terms/s", "cores": torch.get_num_threads(),
             "kind": "oracle",
-            "sample": f"{name} restricted to 1 timestep x 8 channels (all {obs.nbl} baselines, "
-                      f"{sky.nsrc} sources): chi2 + autograd gradient, {dt:.1f} s"}
+            "sample": f"{name} restricted to 1 timestep x {nc} channels (all {obs.nbl} "
+                      f"baselines, {sky.nsrc} sources): chi2 + autograd gradient, {dt:.1f} s"}
+
+
+def make_problem_nchan(name):
+    from rime_synth import CONFIGS
+    return CONFIGS[name]["nchan"]
 
 
 def main():
@@ -108,6 +122,13 @@ def main():
     D32, W32 = D64.to(torch.complex64), W64.to(torch.float32)
     dsky = R.DeviceSky.from_host(sky)
     torch.cuda.synchronize()
+    if args.calib_copy:
+        # a plain device copy of known size: args.calib_copy MiB read + written
+        a = torch.ones(args.calib_copy * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     terms = obs.ntime * obs.nbl * obs.nchan * sky.nsrc
     tp = obs.ntime * obs.nbl * obs.nchan * sky.npsrc

@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--config", default="c2", choices=["c1", "c2", "c4"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="MiB copied device-to-device once before timing (a kernel of known "
                          "traffic for calibrating HBM counters)")
@@ -134,11 +135,17 @@ def main():
     tp = obs.ntime * obs.nbl * obs.nchan * sky.npsrc
     tg = obs.ntime * obs.nbl * obs.nchan * sky.ngsrc
 
+    tuned = {}
+
     def run(mode, prec, steps, warmup):
         D, W = (D64, W64) if prec == R.FP64 else (D32, W32)
         chi2 = torch.empty(1, dtype=torch.float64, device="cuda")
         grad = torch.empty((sky.nsrc, 10), dtype=torch.float64, device="cuda")
         wsp = R.workspace(plan, mode, prec, 1, sky.nsrc)
+        if not args.no_autotune:
+            # untimed: the library's autotuner picks the kernel variant
+            R.rime_autotune(plan, dsky, mode, prec, D, W, wsp)
+        tuned[(mode, prec)] = R.rime_variant_info(mode, prec, plan.get_variant(mode, prec))
 
         def call():
             if mode == R.MODE_CHI2_GRAD:
@@ -166,6 +173,7 @@ def main():
         ms = start.elapsed_time(stop) / steps
         kms = float(np.mean([ks[i].elapsed_time(ke[i]) for i in range(steps)]))
         return {"ms_per_step": ms, "kernel_ms": kms, "chi2": chi2.item(),
+                "variant": tuned[(mode, prec)],
                 "terms_per_s": terms / (ms * 1e-3), "evals_per_s": 1e3 / ms}
 
     out = {}
@@ -193,7 +201,8 @@ def main():
         traffic = None
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS["f32"],
                 "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS["f32"], "traffic": traffic,
-                "kernel": "rime_main<float,...,MODE_GRAD>", "kernel_ms": g["kernel_ms"],
+                "kernel": "rime_main<float, %d, %d, %d, chi2+grad>" % tuple(g["variant"]),
+                "kernel_ms": g["kernel_ms"],
                 "flops_per_launch": flops}
     rec = {
         "metric": "source x visibility terms/s (chi2+grad, FP32-mixed), 1 GPU",

@@ -227,7 +227,12 @@ rime_status build_tiles(int na, int nbl, const std::vector<int32_t> &a1,
   ts.nbt = nbt;
   ts.nat = nat;
   ts.ntile = ntile;
+  std::vector<int32_t> hnact(ntile, 0);
+  for (int t = 0; t < ntile; ++t)
+    for (int i = 0; i < nbt; ++i)
+      if (hbl[static_cast<size_t>(t) * nbt + i] >= 0) hnact[t] = i + 1;
   hipError_t e;
+  if ((e = upload(&ts.nact, hnact)) != hipSuccess) return hip_fail(e);
   if ((e = upload(&ts.bl, hbl)) != hipSuccess) return hip_fail(e);
   if ((e = upload(&ts.lpq, hlpq)) != hipSuccess) return hip_fail(e);
   if ((e = upload(&ts.ant, hant)) != hipSuccess) return hip_fail(e);
@@ -237,8 +242,11 @@ rime_status build_tiles(int na, int nbl, const std::vector<int32_t> &a1,
 // ---------------------------------------------------------------------------
 // Launch geometry and workspace layout
 // ---------------------------------------------------------------------------
+// Work items per second-level chunk of the gradient reduction.
+constexpr int kGradChunk = 32;
+
 struct Geometry {
-  int ntile = 0, nchb = 0, tchunk = 1, ntc = 1, items_per_set = 0;
+  int ntile = 0, nchb = 0, tchunk = 1, ntc = 1, items_per_set = 0, grad_nchunk = 1;
 };
 
 Geometry geometry(const rime_plan *plan, const Variant &v, int nset) {
@@ -251,11 +259,12 @@ Geometry geometry(const rime_plan *plan, const Variant &v, int nset) {
   g.tchunk = static_cast<int>(tc);
   g.ntc = (plan->ntime + g.tchunk - 1) / g.tchunk;
   g.items_per_set = g.ntile * g.nchb * g.ntc;
+  g.grad_nchunk = (g.items_per_set + kGradChunk - 1) / kGradChunk;
   return g;
 }
 
 struct WsLayout {
-  size_t geo = 0, lon = 0, st = 0, chi2 = 0, grad = 0, total = 0;
+  size_t geo = 0, lon = 0, st = 0, chi2 = 0, grad = 0, grad2 = 0, total = 0;
 };
 
 WsLayout ws_layout(const rime_plan *plan, int mode, int prec, const Geometry &g, int nset,
@@ -275,6 +284,9 @@ WsLayout ws_layout(const rime_plan *plan, int mode, int prec, const Geometry &g,
   L.grad = off;
   if (mode == RIME_MODE_CHI2_GRAD)
     off += align_up(static_cast<size_t>(g.items_per_set) * total_src * 10 * sizeof(double));
+  L.grad2 = off;
+  if (mode == RIME_MODE_CHI2_GRAD)
+    off += align_up(static_cast<size_t>(g.grad_nchunk) * total_src * 10 * sizeof(double2));
   L.total = off;
   return L;
 }
@@ -338,6 +350,7 @@ rime_status enqueue(const rime_plan *plan, int mode, int prec, int vidx, int nse
   p.tile_bl = ts.bl;
   p.tile_lpq = ts.lpq;
   p.tile_ant = ts.ant;
+  p.tile_nact = ts.nact;
   p.nchb = g.nchb;
   p.tchunk = g.tchunk;
   p.ntc = g.ntc;
@@ -356,6 +369,9 @@ rime_status enqueue(const rime_plan *plan, int mode, int prec, int vidx, int nse
   p.vis = vis;
   p.chi2_part = reinterpret_cast<double2 *>(w + L.chi2);
   p.grad_part = reinterpret_cast<double *>(w + L.grad);
+  p.grad_part2 = reinterpret_cast<double *>(w + L.grad2);
+  p.grad_chunks = kGradChunk;
+  p.grad_nchunk = g.grad_nchunk;
   p.chi2_out = chi2;
   p.grad_out = grad;
   RIME_HIP(launch_prep(p, prec == RIME_FP64, max_nsrc, stream));
@@ -489,6 +505,7 @@ void rime_plan_destroy(rime_plan *plan) {
     (void)hipFree(t.bl);
     (void)hipFree(t.lpq);
     (void)hipFree(t.ant);
+    (void)hipFree(t.nact);
   }
   if (have && cur != plan->device) (void)hipSetDevice(cur);
   delete plan;

@@ -34,6 +34,7 @@ struct TileSet {
   int32_t *bl = nullptr;   // device [ntile][nbt]  global baseline index or -1
   int32_t *lpq = nullptr;  // device [ntile][nbt]  local p | (local q << 16)
   int32_t *ant = nullptr;  // device [ntile][nat]  global antenna index or -1
+  int32_t *nact = nullptr; // device [ntile]       active baselines (slots 0..nact-1)
 };
 
 // Everything a kernel launch needs (passed by value).
@@ -51,7 +52,7 @@ struct KParams {
   double beam_clip;
   // tiling
   int32_t nbt, nat, ntile;
-  const int32_t *tile_bl, *tile_lpq, *tile_ant;
+  const int32_t *tile_bl, *tile_lpq, *tile_ant, *tile_nact;
   int32_t nchb;            // channel blocks
   int32_t tchunk, ntc;     // timesteps per work item, time chunks
   int32_t items_per_set;   // ntile * nchb * ntc
@@ -70,7 +71,10 @@ struct KParams {
   const void *weight;      // [ntime][nbl][nchan][4] real
   void *vis;               // predict output
   double2 *chi2_part;      // [total items] (sum, compensation)
-  double *grad_part;       // gradient partials
+  double *grad_part;       // gradient partials [set][item][nsrc][10]
+  double *grad_part2;      // second-level partials [set][chunk][nsrc][10]
+  int32_t grad_chunks;     // items per second-level chunk, and chunk count
+  int32_t grad_nchunk;
   double *chi2_out;        // [nset]
   double *grad_out;        // [total_src][10]
 };

@@ -4,7 +4,7 @@
 // per thread, drawn from at most NAT antennas), a block of NC channels and a
 // chunk of timesteps.  For every source tile of NS sources it
 //   1. computes the per-antenna terms a_tps(nu) = e_tps K_tps once per antenna
-//      into LDS (the per-antenna-first strategy of the paper's Section 4.1,
+//      into LDS (the per-antenna-first strategy of the paper, Section 4,
 //      fused here with the per-baseline stage instead of going through HBM);
 //   2. accumulates, per visibility, the four Stokes-weighted sums
 //      sum_s S c_s I'_s, ..., sum_s S c_s V'_s with c_s = a_p conj(a_q)
@@ -18,9 +18,10 @@
 //
 // Precision: R = double (plain FP64) or R = float (mixed).  In the mixed path
 // the phase argument is formed in float64 and reduced to [-1/2, 1/2] turns
-// before the float32 sine/cosine; the beam clip decision is taken in float64;
-// the per-visibility source sums run in float32 within a source tile and are
-// folded into float64 after each tile; chi^2 and gradient sums are float64.
+// before the float32 hardware sine/cosine; the beam clip decision is taken in
+// float64; the per-visibility source sums run in float32 within a source tile
+// and are folded into float64 after each tile; chi^2 and gradient sums are
+// float64.
 #include "rime_internal.h"
 
 namespace rime {
@@ -28,6 +29,9 @@ namespace rime {
 // ---------------------------------------------------------------------------
 // Numeric helpers
 // ---------------------------------------------------------------------------
+
+constexpr double kInvTwoPi = 0.15915494309189533576888376337251436;
+constexpr double kLog2e = 1.44269504088896340735992468100189214;
 
 template <class R> struct Num;
 
@@ -38,20 +42,29 @@ template <> struct Num<double> {
   __device__ static inline void sincos_turns(double r, double *s, double *c) {
     sincospi(2.0 * r, s, c);
   }
-  __device__ static inline double cos_(double x) { return cos(x); }
-  __device__ static inline double tan_(double x) { return tan(x); }
-  __device__ static inline double exp_(double x) { return exp(x); }
+  // sin and cos of x radians, |x| <= 1.1.
+  __device__ static inline void sincos_rad(double x, double *s, double *c) { sincos(x, s, c); }
+  // exp(y) for y <= 0; y2 = y log2(e) is used by the float version.
+  __device__ static inline double exp_neg(double y, double /*y2*/) { return exp(y); }
 };
 
 template <> struct Num<float> {
   using R2 = float2;
   using R4 = float4;
+  // v_sin_f32 / v_cos_f32 take the angle in turns.
   __device__ static inline void sincos_turns(double r, float *s, float *c) {
-    sincospif(static_cast<float>(2.0 * r), s, c);
+    const float rf = static_cast<float>(r);
+    *s = __builtin_amdgcn_sinf(rf);
+    *c = __builtin_amdgcn_cosf(rf);
   }
-  __device__ static inline float cos_(float x) { return cosf(x); }
-  __device__ static inline float tan_(float x) { return tanf(x); }
-  __device__ static inline float exp_(float x) { return expf(x); }
+  __device__ static inline void sincos_rad(double x, float *s, float *c) {
+    const float t = static_cast<float>(x * kInvTwoPi);
+    *s = __builtin_amdgcn_sinf(t);
+    *c = __builtin_amdgcn_cosf(t);
+  }
+  __device__ static inline float exp_neg(float /*y*/, float y2) {
+    return __builtin_amdgcn_exp2f(y2);
+  }
 };
 
 // (a0 b0 + a1 b1) + a2 b2 with every product and sum rounded separately (no
@@ -171,9 +184,9 @@ struct Layout {
   using R4 = typename Num<R>::R4;
   static constexpr int NAT = nat_for(NBT);
   static constexpr int NW = NBT / kWave;
-  // a-tile row per source: NAT antennas x NC channels, padded by one element
-  // so that consecutive sources start in different LDS banks.
-  static constexpr int AST = NAT * NC + 1;
+  // a-tile row per source: NAT antennas x NC channels, padded by two
+  // elements so that the adjoint's lanes (source x channel) hit distinct banks.
+  static constexpr int AST = NAT * NC + 2;
   static constexpr bool GRAD = MODE == MODE_GRAD;
   static constexpr size_t A_BYTES = sizeof(R2) * NS * AST;
   static constexpr size_t BETA_BYTES = GRAD ? sizeof(R2) * NS * AST : 0;
@@ -183,7 +196,7 @@ struct Layout {
       (A_BYTES + BETA_BYTES) > RED_BYTES ? (A_BYTES + BETA_BYTES) : RED_BYTES;
   static constexpr size_t RHO_BYTES = GRAD ? sizeof(R2) * NBT * NC * 4 : 0;
   static constexpr size_t GEO_BYTES = GRAD ? sizeof(R4) * NBT : 0;
-  static constexpr size_t LPQ_BYTES = GRAD ? sizeof(int) * NBT : 0;
+  static_assert(!GRAD || NS * NC == kWave, "the adjoint maps one wavefront to NS x NC");
 };
 
 // Per-antenna stage for one source tile: a[s][ant][c] = e K (and, for the
@@ -227,25 +240,29 @@ __device__ inline void stage_tile(const KParams &p, const SetDesc &sd, int tile,
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         if (c < ncv) {
-          const double nuc = p.nu_c[c0 + c];
-          const double x = tau * nuc;
+          const double x = tau * p.nu_c[c0 + c];
           const double r = x - rint(x);
           R sn, cs;
           N::sincos_turns(r, &sn, &cs);
           R e = R(1);
           if (p.beam) {
-            // x = beam_k r nu / beam_ref_freq, clipped (eq. e_term)
-            const double bs = p.beam_k * p.bfr[c0 + c];
-            const double xb = (p.beam_k * rb) * p.bfr[c0 + c];
+            // x_b = beam_k r nu / beam_ref_freq, clipped (eq. e_term)
+            const double bfr = p.bfr[c0 + c];
+            const double xb = (p.beam_k * rb) * bfr;
             const bool clipped = xb >= p.beam_clip;
-            const R xr = static_cast<R>(clipped ? p.beam_clip : xb);
-            const R cb = N::cos_(xr);
+            const double xc = clipped ? p.beam_clip : xb;
+            R sb, cb;
+            N::sincos_rad(xc, &sb, &cb);
             e = cb * cb * cb;
             if (WITH_BETA) {
-              // d ln e / dl = -3 tan(x) dx/dl, dx/dl = bs (l - dl_p) / r
+              // d ln e / dl = -3 tan(x) dx/dl, dx/dl = bs (l - dl_p) / r, bs = beam_k nu/nu_b
               //             = -3 bs^2 (l - dl_p) tan(x)/x ; zero past the clip.
               R tx = R(0);
-              if (!clipped) tx = xr > R(1e-4) ? N::tan_(xr) / xr : R(1) + xr * xr / R(3);
+              if (!clipped) {
+                const R xr = static_cast<R>(xc);
+                tx = xr > R(1e-4) ? sb / (cb * xr) : R(1) + xr * xr / R(3);
+              }
+              const double bs = p.beam_k * bfr;
               const R k3 = static_cast<R>(-3.0 * bs * bs) * tx;
               bet[c].x = k3 * static_cast<R>(dl);
               bet[c].y = k3 * static_cast<R>(dm);
@@ -287,6 +304,118 @@ __device__ inline void stage_tile(const KParams &p, const SetDesc &sd, int tile,
   }
 }
 
+// Pass 1 inner loop over the sources of one staged tile: adds
+// sum_s S c_s (I', Q', U', V')_s to the 8 accumulators of each channel.
+template <class R, int NC, int AST, bool GAUSS>
+__device__ inline void accumulate(int cnt, const typename Num<R>::R2 *ap_row,
+                                  const typename Num<R>::R2 *aq_row,
+                                  const typename Num<R>::R4 *s_st,
+                                  const typename Num<R>::R4 *s_gs, R du, R dv, const R *gq,
+                                  const R *gq2, R (&in)[NC][8]) {
+  using N = Num<R>;
+  using R2 = typename N::R2;
+  using R4 = typename N::R4;
+#pragma unroll 2
+  for (int s = 0; s < cnt; ++s) {
+    R Qf = R(0);
+    if (GAUSS) {
+      const R4 g = s_gs[s];
+      const R A = du * g.x + dv * g.y;
+      const R B = du * g.y - dv * g.x;
+      Qf = A * A + g.z * B * B;
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const R2 ap = ap_row[s * AST + c];
+      const R2 aq = aq_row[s * AST + c];
+      const R4 st = s_st[s * NC + c];
+      R cr = ap.x * aq.x + ap.y * aq.y;
+      R ci = ap.y * aq.x - ap.x * aq.y;
+      if (GAUSS) {
+        const R S = N::exp_neg(gq[c] * Qf, gq2[c] * Qf);
+        cr *= S;
+        ci *= S;
+      }
+      in[c][0] += cr * st.x;
+      in[c][1] += ci * st.x;
+      in[c][2] += cr * st.y;
+      in[c][3] += ci * st.y;
+      in[c][4] += cr * st.z;
+      in[c][5] += ci * st.z;
+      in[c][6] += cr * st.w;
+      in[c][7] += ci * st.w;
+    }
+  }
+}
+
+// Pass 2 inner loop over the tile's active baselines, for this lane's
+// (source, channel).  Accumulators:
+//   g[0..3]  sum Re(c rho_k)                      (Stokes, times f later)
+//   g[4]     sum Re P                              (alpha, times ln(nu/nu_ref))
+//   g[5], g[6]   sum (beta_p + beta_q)_{l,m} Re P  (beam part of l, m)
+//   g[7], g[8], g[9]  sum (du, dv, dw) Im P        (phase part of l, m)
+//   g[10..14]  Gaussian: sum du A ReP, sum dv B ReP, sum dv A ReP, sum du B ReP,
+//              sum B^2 ReP
+// with P = c Phi, Phi = sum_k St'_k rho_k.
+template <class R, int NC, bool GAUSS, bool BEAM>
+__device__ inline void adjoint_loop(int wave, int nw, int nact, const int *s_lpq,
+                                    const typename Num<R>::R4 *s_geo,
+                                    const typename Num<R>::R2 *s_rho,
+                                    const typename Num<R>::R2 *arow,
+                                    const typename Num<R>::R2 *brow,
+                                    const typename Num<R>::R4 st,
+                                    const typename Num<R>::R4 gsh, R gq, R gq2, int cl,
+                                    R (&g)[15]) {
+  using N = Num<R>;
+  using R2 = typename N::R2;
+  using R4 = typename N::R4;
+#pragma unroll 2
+  for (int bi = wave; bi < nact; bi += nw) {
+    const int q = s_lpq[bi];
+    const int bp_ = q & 0xffff, bq_ = q >> 16;
+    const R4 geo = s_geo[bi];
+    const R2 ap = arow[bp_ * NC], aq = arow[bq_ * NC];
+    const R2 *rho = s_rho + (bi * NC + cl) * 4;
+    const R2 r0 = rho[0], r1 = rho[1], r2 = rho[2], r3 = rho[3];
+    R cr = ap.x * aq.x + ap.y * aq.y;
+    R ci = ap.y * aq.x - ap.x * aq.y;
+    R A = R(0), B = R(0);
+    if (GAUSS) {
+      A = geo.x * gsh.x + geo.y * gsh.y;
+      B = geo.x * gsh.y - geo.y * gsh.x;
+      const R Qf = A * A + gsh.z * B * B;
+      const R S = N::exp_neg(gq * Qf, gq2 * Qf);
+      cr *= S;
+      ci *= S;
+    }
+    g[0] += cr * r0.x - ci * r0.y;
+    g[1] += cr * r1.x - ci * r1.y;
+    g[2] += cr * r2.x - ci * r2.y;
+    g[3] += cr * r3.x - ci * r3.y;
+    const R phr = st.x * r0.x + st.y * r1.x + st.z * r2.x + st.w * r3.x;
+    const R phi = st.x * r0.y + st.y * r1.y + st.z * r2.y + st.w * r3.y;
+    const R Pr = cr * phr - ci * phi;
+    const R Pi = cr * phi + ci * phr;
+    g[4] += Pr;
+    if (BEAM) {
+      const R2 bp = brow[bp_ * NC], bq = brow[bq_ * NC];
+      g[5] += (bp.x + bq.x) * Pr;
+      g[6] += (bp.y + bq.y) * Pr;
+    }
+    g[7] += geo.x * Pi;
+    g[8] += geo.y * Pi;
+    g[9] += geo.z * Pi;
+    if (GAUSS) {
+      const R t1 = A * Pr, t2 = B * Pr;
+      g[10] += geo.x * t1;
+      g[11] += geo.y * t2;
+      g[12] += geo.y * t1;
+      g[13] += geo.x * t2;
+      g[14] += B * t2;
+    }
+  }
+}
+
 template <class R, int NBT, int NC, int NS, int MODE>
 __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
   using L = Layout<R, NBT, NC, NS, MODE>;
@@ -324,10 +453,11 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
   const int tc = rem / p.nchb;
 
   const int tid = threadIdx.x;
+  const int nact = p.tile_nact[tile];
   const int bl = p.tile_bl[tile * NBT + tid];
-  const int lpq = p.tile_lpq[tile * NBT + tid];
-  const int lp = lpq & 0xffff, lq = lpq >> 16;
   const bool active = bl >= 0;
+  const int lpq = active ? p.tile_lpq[tile * NBT + tid] : 0;
+  const int lp = lpq & 0xffff, lq = lpq >> 16;
   const int c0 = chb * NC;
   const int ncv = min(NC, p.nchan - c0);
   const int nsrc = sd.npsrc + sd.ngsrc;
@@ -337,21 +467,13 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
   const int ngt = (sd.ngsrc + NS - 1) / NS;
   const int nst = npt + ngt;
 
-  // per-channel constants of this thread's channels
-  R gq[NC];  // -pi^2/(4 ln 2) (nu/c)^2
+  // per-channel constants of this thread's channels: -pi^2/(4 ln 2) (nu/c)^2
+  R gq[NC], gq2[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     const double nuc = c < ncv ? p.nu_c[c0 + c] : 0.0;
     gq[c] = static_cast<R>(-kGauss * nuc * nuc);
-  }
-  // gains of this baseline's antennas
-  double2 gp0 = make_double2(1, 0), gp1 = gp0, gq0 = gp0, gq1 = gp0;
-  if (active) {
-    const int ap = p.tile_ant[tile * NAT + lp], aq = p.tile_ant[tile * NAT + lq];
-    gp0 = make_double2(p.gains[4 * ap + 0], p.gains[4 * ap + 1]);
-    gp1 = make_double2(p.gains[4 * ap + 2], p.gains[4 * ap + 3]);
-    gq0 = make_double2(p.gains[4 * aq + 0], p.gains[4 * aq + 1]);
-    gq1 = make_double2(p.gains[4 * aq + 2], p.gains[4 * aq + 3]);
+    gq2[c] = static_cast<R>(-kGauss * kLog2e * nuc * nuc);
   }
 
   Comp chi;
@@ -398,58 +520,17 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
       stage_tile<R, NBT, NC, NS, MODE, false>(p, sd, tile, s0, cnt, gauss, c0, ncv, s_uvw,
                                               s_pnt, s_a, s_beta, s_st, s_gs);
       __syncthreads();
-      if (!active) continue;
       R in[NC][8];
 #pragma unroll
       for (int c = 0; c < NC; ++c)
 #pragma unroll
         for (int j = 0; j < 8; ++j) in[c][j] = R(0);
-      const R2 *ap_row = s_a + lp * NC;
-      const R2 *aq_row = s_a + lq * NC;
-      if (!gauss) {
-        for (int s = 0; s < cnt; ++s) {
-#pragma unroll
-          for (int c = 0; c < NC; ++c) {
-            const R2 ap = ap_row[s * L::AST + c];
-            const R2 aq = aq_row[s * L::AST + c];
-            const R4 st = s_st[s * NC + c];
-            const R cr = ap.x * aq.x + ap.y * aq.y;
-            const R ci = ap.y * aq.x - ap.x * aq.y;
-            in[c][0] += cr * st.x;
-            in[c][1] += ci * st.x;
-            in[c][2] += cr * st.y;
-            in[c][3] += ci * st.y;
-            in[c][4] += cr * st.z;
-            in[c][5] += ci * st.z;
-            in[c][6] += cr * st.w;
-            in[c][7] += ci * st.w;
-          }
-        }
-      } else {
-        for (int s = 0; s < cnt; ++s) {
-          const R4 g = s_gs[s];
-          const R A = du * g.x + dv * g.y;
-          const R B = du * g.y - dv * g.x;
-          const R Qf = A * A + g.z * B * B;
-#pragma unroll
-          for (int c = 0; c < NC; ++c) {
-            const R2 ap = ap_row[s * L::AST + c];
-            const R2 aq = aq_row[s * L::AST + c];
-            const R4 st = s_st[s * NC + c];
-            const R S = N::exp_(gq[c] * Qf);
-            const R cr = (ap.x * aq.x + ap.y * aq.y) * S;
-            const R ci = (ap.y * aq.x - ap.x * aq.y) * S;
-            in[c][0] += cr * st.x;
-            in[c][1] += ci * st.x;
-            in[c][2] += cr * st.y;
-            in[c][3] += ci * st.y;
-            in[c][4] += cr * st.z;
-            in[c][5] += ci * st.z;
-            in[c][6] += cr * st.w;
-            in[c][7] += ci * st.w;
-          }
-        }
-      }
+      if (gauss)
+        accumulate<R, NC, L::AST, true>(cnt, s_a + lp * NC, s_a + lq * NC, s_st, s_gs, du, dv,
+                                        gq, gq2, in);
+      else
+        accumulate<R, NC, L::AST, false>(cnt, s_a + lp * NC, s_a + lq * NC, s_st, s_gs, du, dv,
+                                         gq, gq2, in);
 #pragma unroll
       for (int c = 0; c < NC; ++c)
 #pragma unroll
@@ -457,24 +538,13 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
     }
 
     // ---- epilogue: V, residual, chi^2 --------------------------------------
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      const bool ok = active && c < ncv;
-      // Stokes sums -> 2x2 coherency (eq. brightness_term)
-      const double SIr = acc[c][0], SIi = acc[c][1], SQr = acc[c][2], SQi = acc[c][3];
-      const double SUr = acc[c][4], SUi = acc[c][5], SVr = acc[c][6], SVi = acc[c][7];
-      double Vr[4], Vi[4];
-      Vr[0] = SIr + SQr;  // xx
-      Vi[0] = SIi + SQi;
-      Vr[1] = SUr - SVi;  // xy = S_U + i S_V
-      Vi[1] = SUi + SVr;
-      Vr[2] = SUr + SVi;  // yx = S_U - i S_V
-      Vi[2] = SUi - SVr;
-      Vr[3] = SIr - SQr;  // yy
-      Vi[3] = SIi - SQi;
-      // gains: V_ij *= g_pi conj(g_qj)
-      const double2 gpi[2] = {gp0, gp1};
-      const double2 gqj[2] = {gq0, gq1};
+    if (active) {
+      // gains of this baseline's antennas: V_ij *= g_pi conj(g_qj)
+      const int gap = p.tile_ant[tile * NAT + lp], gaq = p.tile_ant[tile * NAT + lq];
+      const double2 gpi[2] = {make_double2(p.gains[4 * gap + 0], p.gains[4 * gap + 1]),
+                              make_double2(p.gains[4 * gap + 2], p.gains[4 * gap + 3])};
+      const double2 gqj[2] = {make_double2(p.gains[4 * gaq + 0], p.gains[4 * gaq + 1]),
+                              make_double2(p.gains[4 * gaq + 2], p.gains[4 * gaq + 3])};
       double2 gg[4];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
@@ -484,67 +554,80 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
           gg[2 * i + j] = make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
         }
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const double r = Vr[k] * gg[k].x - Vi[k] * gg[k].y;
-        const double i = Vr[k] * gg[k].y + Vi[k] * gg[k].x;
-        Vr[k] = r;
-        Vi[k] = i;
-      }
-      const int64_t vidx =
-          ((static_cast<int64_t>(t) * p.nbl + (active ? bl : 0)) * p.nchan + c0 + c) * 4;
-      if (MODE == MODE_PREDICT) {
-        if (ok) {
-          R2 *out = static_cast<R2 *>(p.vis) + vidx;
+      for (int c = 0; c < NC; ++c) {
+        const bool ok = c < ncv;
+        // Stokes sums -> 2x2 coherency (eq. brightness_term)
+        const double SIr = acc[c][0], SIi = acc[c][1], SQr = acc[c][2], SQi = acc[c][3];
+        const double SUr = acc[c][4], SUi = acc[c][5], SVr = acc[c][6], SVi = acc[c][7];
+        double Vr[4], Vi[4];
+        Vr[0] = SIr + SQr;  // xx
+        Vi[0] = SIi + SQi;
+        Vr[1] = SUr - SVi;  // xy = S_U + i S_V
+        Vi[1] = SUi + SVr;
+        Vr[2] = SUr + SVi;  // yx = S_U - i S_V
+        Vi[2] = SUi - SVr;
+        Vr[3] = SIr - SQr;  // yy
+        Vi[3] = SIi - SQi;
 #pragma unroll
-          for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < 4; ++k) {
+          const double r = Vr[k] * gg[k].x - Vi[k] * gg[k].y;
+          const double i = Vr[k] * gg[k].y + Vi[k] * gg[k].x;
+          Vr[k] = r;
+          Vi[k] = i;
+        }
+        const int64_t vidx = ((static_cast<int64_t>(t) * p.nbl + bl) * p.nchan + c0 + c) * 4;
+        if (MODE == MODE_PREDICT) {
+          if (ok) {
+            R2 *out = static_cast<R2 *>(p.vis) + vidx;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              R2 v;
+              v.x = static_cast<R>(Vr[k]);
+              v.y = static_cast<R>(Vi[k]);
+              out[k] = v;
+            }
+          }
+        } else {
+          double Yr[4] = {0, 0, 0, 0}, Yi[4] = {0, 0, 0, 0};
+          if (ok) {
+            const R2 *D = static_cast<const R2 *>(p.data) + vidx;
+            const R *W = static_cast<const R *>(p.weight) + vidx;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              const R2 d = D[k];
+              const double w = static_cast<double>(W[k]);
+              const double rr = Vr[k] - static_cast<double>(d.x);
+              const double ri = Vi[k] - static_cast<double>(d.y);
+              chi.add(w * (rr * rr + ri * ri));
+              Yr[k] = w * rr;
+              Yi[k] = w * ri;
+            }
+          }
+          if (MODE == MODE_GRAD) {
+            // Z_ij = Y_ij conj(g_pi) g_qj = Y_ij conj(gg_ij); then
+            // rho_I = conj(Zxx) + conj(Zyy), rho_Q = conj(Zxx) - conj(Zyy),
+            // rho_U = conj(Zxy) + conj(Zyx), rho_V = i (conj(Zxy) - conj(Zyx))
+            double Zr[4], Zi[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              Zr[k] = Yr[k] * gg[k].x + Yi[k] * gg[k].y;
+              Zi[k] = Yi[k] * gg[k].x - Yr[k] * gg[k].y;
+            }
+            R2 *rho = s_rho + (tid * NC + c) * 4;
             R2 v;
-            v.x = static_cast<R>(Vr[k]);
-            v.y = static_cast<R>(Vi[k]);
-            out[k] = v;
+            v.x = static_cast<R>(Zr[0] + Zr[3]);
+            v.y = static_cast<R>(-(Zi[0] + Zi[3]));
+            rho[0] = v;
+            v.x = static_cast<R>(Zr[0] - Zr[3]);
+            v.y = static_cast<R>(-(Zi[0] - Zi[3]));
+            rho[1] = v;
+            v.x = static_cast<R>(Zr[1] + Zr[2]);
+            v.y = static_cast<R>(-(Zi[1] + Zi[2]));
+            rho[2] = v;
+            v.x = static_cast<R>(Zi[1] - Zi[2]);
+            v.y = static_cast<R>(Zr[1] - Zr[2]);
+            rho[3] = v;
           }
-        }
-      } else {
-        double Yr[4] = {0, 0, 0, 0}, Yi[4] = {0, 0, 0, 0};
-        if (ok) {
-          const R2 *D = static_cast<const R2 *>(p.data) + vidx;
-          const R *W = static_cast<const R *>(p.weight) + vidx;
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            const R2 d = D[k];
-            const double w = static_cast<double>(W[k]);
-            const double rr = Vr[k] - static_cast<double>(d.x);
-            const double ri = Vi[k] - static_cast<double>(d.y);
-            chi.add(w * (rr * rr + ri * ri));
-            Yr[k] = w * rr;
-            Yi[k] = w * ri;
-          }
-        }
-        if (MODE == MODE_GRAD) {
-          // Z_ij = Y_ij conj(g_pi) g_qj, then rho_{I,Q,U,V} (see the adjoint)
-          double Zr[4], Zi[4];
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            // conj(g_pi g_qj^*) = conj(gg)
-            Zr[k] = Yr[k] * gg[k].x + Yi[k] * gg[k].y;
-            Zi[k] = Yi[k] * gg[k].x - Yr[k] * gg[k].y;
-          }
-          // rho_I = conj(Zxx) + conj(Zyy), rho_Q = conj(Zxx) - conj(Zyy),
-          // rho_U = conj(Zxy) + conj(Zyx), rho_V = i (conj(Zxy) - conj(Zyx))
-          R2 *rho = s_rho + (tid * NC + c) * 4;
-          R2 v;
-          v.x = static_cast<R>(Zr[0] + Zr[3]);
-          v.y = static_cast<R>(-(Zi[0] + Zi[3]));
-          rho[0] = v;
-          v.x = static_cast<R>(Zr[0] - Zr[3]);
-          v.y = static_cast<R>(-(Zi[0] - Zi[3]));
-          rho[1] = v;
-          v.x = static_cast<R>(Zr[1] + Zr[2]);
-          v.y = static_cast<R>(-(Zi[1] + Zi[2]));
-          rho[2] = v;
-          // i (a - b) with a - b = conj(Zxy) - conj(Zyx) = (Zr1 - Zr2) - i (Zi1 - Zi2)
-          v.x = static_cast<R>(Zi[1] - Zi[2]);
-          v.y = static_cast<R>(Zr[1] - Zr[2]);
-          rho[3] = v;
         }
       }
     }
@@ -558,7 +641,7 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
         g.z = dw;
         g.w = R(0);
         s_geo[tid] = g;
-        s_lpq[tid] = active ? lpq : -1;
+        s_lpq[tid] = lpq;
       }
       const int lane = tid % kWave, wave = tid / kWave;
       const int sl = lane / NC, cl = lane - (lane / NC) * NC;
@@ -566,7 +649,8 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
       const double nuc_l = lane_ok_c ? p.nu_c[c0 + cl] : 0.0;
       const R tpnc = static_cast<R>(2.0 * kPi * nuc_l);
       const R gq_l = static_cast<R>(-kGauss * nuc_l * nuc_l);
-      const R lnfr_l = static_cast<R>(lane_ok_c ? p.lnfr[c0 + cl] : 0.0);
+      const R gq2_l = static_cast<R>(-kGauss * kLog2e * nuc_l * nuc_l);
+      const double lnfr_l = lane_ok_c ? p.lnfr[c0 + cl] : 0.0;
       // gradient partials: [set][item][nsrc][10], sets laid out by src_off
       double *gout = p.grad_part + sd.src_off * p.items_per_set * 10 +
                      static_cast<int64_t>(local_item) * nsrc * 10;
@@ -584,64 +668,46 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
         if (sl < cnt && lane_ok_c) {
           const R4 st = s_st[sl * NC + cl];
           const double2 lo = p.src_lon[sd.src_off + s0 + sl];
-          const R lon = static_cast<R>(lo.x), mon = static_cast<R>(lo.y);
           R4 gsh;
           gsh.x = gsh.y = gsh.z = gsh.w = R(0);
           if (gauss) gsh = s_gs[sl];
           const R2 *arow = s_a + sl * L::AST + cl;
           const R2 *brow = s_beta + sl * L::AST + cl;
-          for (int bi = wave; bi < NBT; bi += NW) {
-            const int q = s_lpq[bi];
-            if (q < 0) continue;
-            const int bp_ = q & 0xffff, bq_ = q >> 16;
-            const R4 geo = s_geo[bi];
-            const R2 ap = arow[bp_ * NC], aq = arow[bq_ * NC];
-            const R2 bp = brow[bp_ * NC], bq = brow[bq_ * NC];
-            const R2 *rho = s_rho + (bi * NC + cl) * 4;
-            const R2 r0 = rho[0], r1 = rho[1], r2 = rho[2], r3 = rho[3];
-            R cr = ap.x * aq.x + ap.y * aq.y;
-            R ci = ap.y * aq.x - ap.x * aq.y;
-            R A = R(0), B = R(0);
-            if (gauss) {
-              A = geo.x * gsh.x + geo.y * gsh.y;
-              B = geo.x * gsh.y - geo.y * gsh.x;
-              const R S = N::exp_(gq_l * (A * A + gsh.z * B * B));
-              cr *= S;
-              ci *= S;
-            }
-            // d/d(I,Q,U,V): Re(c rho_k)   (times the spectral factor later)
-            gl[2] += cr * r0.x - ci * r0.y;
-            gl[3] += cr * r1.x - ci * r1.y;
-            gl[4] += cr * r2.x - ci * r2.y;
-            gl[5] += cr * r3.x - ci * r3.y;
-            // P = c * Phi, Phi = sum_k St'_k rho_k
-            const R phr = st.x * r0.x + st.y * r1.x + st.z * r2.x + st.w * r3.x;
-            const R phi = st.x * r0.y + st.y * r1.y + st.z * r2.y + st.w * r3.y;
-            const R Pr = cr * phr - ci * phi;
-            const R Pi = cr * phi + ci * phr;
-            gl[6] += Pr;
-            const R kl = tpnc * (geo.x - geo.z * lon);
-            const R km = tpnc * (geo.y - geo.z * mon);
-            gl[0] += (bp.x + bq.x) * Pr + kl * Pi;
-            gl[1] += (bp.y + bq.y) * Pr + km * Pi;
-            if (gauss) {
-              gl[7] += (A * geo.x - gsh.z * B * geo.y) * Pr;
-              gl[8] += (A * geo.y + gsh.z * B * geo.x) * Pr;
-              gl[9] += (B * B) * Pr;
-            }
+          R g[15];
+#pragma unroll
+          for (int j = 0; j < 15; ++j) g[j] = R(0);
+          if (p.beam) {
+            if (gauss)
+              adjoint_loop<R, NC, true, true>(wave, NW, nact, s_lpq, s_geo, s_rho, arow, brow,
+                                              st, gsh, gq_l, gq2_l, cl, g);
+            else
+              adjoint_loop<R, NC, false, true>(wave, NW, nact, s_lpq, s_geo, s_rho, arow, brow,
+                                               st, gsh, gq_l, gq2_l, cl, g);
+          } else {
+            if (gauss)
+              adjoint_loop<R, NC, true, false>(wave, NW, nact, s_lpq, s_geo, s_rho, arow, brow,
+                                               st, gsh, gq_l, gq2_l, cl, g);
+            else
+              adjoint_loop<R, NC, false, false>(wave, NW, nact, s_lpq, s_geo, s_rho, arow,
+                                                brow, st, gsh, gq_l, gq2_l, cl, g);
           }
-          // scale: Stokes by the spectral factor, alpha by ln(nu/nu_ref),
-          // shape by 2 gq (and 2 R gq for R)
+          // assemble: Stokes by the spectral factor, alpha by ln(nu/nu_ref),
+          // l and m from their beam and phase parts, shape by 2 gq.
           const double al = sd.alpha[s0 + sl];
-          const R f = static_cast<R>(exp(al * static_cast<double>(lnfr_l)));
-          gl[2] *= f;
-          gl[3] *= f;
-          gl[4] *= f;
-          gl[5] *= f;
-          gl[6] *= lnfr_l;
-          gl[7] *= R(2) * gq_l;
-          gl[8] *= R(2) * gq_l;
-          gl[9] *= R(2) * gsh.w * gq_l;
+          const R f = static_cast<R>(exp(al * lnfr_l));
+          const R lon = static_cast<R>(lo.x), mon = static_cast<R>(lo.y);
+          gl[0] = g[5] + tpnc * (g[7] - lon * g[9]);
+          gl[1] = g[6] + tpnc * (g[8] - mon * g[9]);
+          gl[2] = g[0] * f;
+          gl[3] = g[1] * f;
+          gl[4] = g[2] * f;
+          gl[5] = g[3] * f;
+          gl[6] = g[4] * static_cast<R>(lnfr_l);
+          if (gauss) {
+            gl[7] = R(2) * gq_l * (g[10] - gsh.z * g[11]);
+            gl[8] = R(2) * gq_l * (g[12] + gsh.z * g[13]);
+            gl[9] = R(2) * gq_l * gsh.w * g[14];
+          }
         }
         __syncthreads();  // the reduction buffer aliases the a/beta tiles
 #pragma unroll
@@ -679,7 +745,6 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
 __global__ __launch_bounds__(256) void finalize_chi2(const KParams p) {
   __shared__ double2 scr[256 / kWave];
   const int set = blockIdx.x;
-  const SetDesc sd = p.sets ? p.sets[set] : p.one;
   Comp acc;
   const double2 *part = p.chi2_part + static_cast<int64_t>(set) * p.items_per_set;
   for (int i = threadIdx.x; i < p.items_per_set; i += 256) {
@@ -690,16 +755,41 @@ __global__ __launch_bounds__(256) void finalize_chi2(const KParams p) {
   if (threadIdx.x == 0) p.chi2_out[set] = r.s + r.c;
 }
 
-__global__ __launch_bounds__(256) void finalize_grad(const KParams p) {
+// Level 1: grid (source-parameter blocks, item chunks, sets); each thread
+// sums `grad_chunks` consecutive items of one (source, parameter).
+__global__ __launch_bounds__(256) void finalize_grad1(const KParams p) {
+  const int set = blockIdx.z;
+  const SetDesc sd = p.sets ? p.sets[set] : p.one;
+  const int nsrc = sd.npsrc + sd.ngsrc;
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx >= nsrc * 10) return;
+  const int chunk = blockIdx.y;
+  const int i0 = chunk * p.grad_chunks;
+  const int i1 = min(p.items_per_set, i0 + p.grad_chunks);
+  const int64_t stride = static_cast<int64_t>(nsrc) * 10;
+  const double *src = p.grad_part + sd.src_off * p.items_per_set * 10 + idx;
+  Comp acc;
+  for (int i = i0; i < i1; ++i) acc.add(src[i * stride]);
+  double2 *dst = reinterpret_cast<double2 *>(p.grad_part2) +
+                 sd.src_off * p.grad_nchunk * 10 + static_cast<int64_t>(chunk) * stride + idx;
+  *dst = make_double2(acc.s, acc.c);
+}
+
+// Level 2: one thread per (set, source, parameter) sums the chunks.
+__global__ __launch_bounds__(256) void finalize_grad2(const KParams p) {
   const int set = blockIdx.y;
   const SetDesc sd = p.sets ? p.sets[set] : p.one;
   const int nsrc = sd.npsrc + sd.ngsrc;
   const int idx = blockIdx.x * 256 + threadIdx.x;
   if (idx >= nsrc * 10) return;
   const int64_t stride = static_cast<int64_t>(nsrc) * 10;
-  const double *src = p.grad_part + sd.src_off * p.items_per_set * 10 + idx;
+  const double2 *src = reinterpret_cast<const double2 *>(p.grad_part2) +
+                       sd.src_off * p.grad_nchunk * 10 + idx;
   Comp acc;
-  for (int i = 0; i < p.items_per_set; ++i) acc.add(src[i * stride]);
+  for (int j = 0; j < p.grad_nchunk; ++j) {
+    const double2 v = src[j * stride];
+    acc.merge(v.x, v.y);
+  }
   p.grad_out[sd.src_off * 10 + idx] = 2.0 * (acc.s + acc.c);
 }
 
@@ -727,8 +817,11 @@ hipError_t launch_finalize(const KParams &p, int mode, int max_nsrc, hipStream_t
   hipLaunchKernelGGL(finalize_chi2, dim3(p.nset), dim3(256), 0, stream, p);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || mode != MODE_GRAD) return e;
-  dim3 grid((max_nsrc * 10 + 255) / 256, p.nset);
-  hipLaunchKernelGGL(finalize_grad, grid, dim3(256), 0, stream, p);
+  const int nblk = (max_nsrc * 10 + 255) / 256;
+  hipLaunchKernelGGL(finalize_grad1, dim3(nblk, p.grad_nchunk, p.nset), dim3(256), 0, stream, p);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(finalize_grad2, dim3(nblk, p.nset), dim3(256), 0, stream, p);
   return hipGetLastError();
 }
 

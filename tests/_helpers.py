@@ -65,3 +65,24 @@ def grad_component_worst(g, gref, npsrc):
             continue
         worst = max(worst, float((np.abs(a - b) / np.maximum(np.abs(b), floor)).max()))
     return worst
+
+
+def contribution_scale(obs, sky, D, W):
+    """Per (source, parameter): sum over visibilities of |d(w |V - D|^2)/d theta|,
+    by central differences of the oracle's per-visibility terms.  A summation
+    error bound scales with this, not with the (possibly cancelling) sum."""
+    from rime_synth import Sky
+    p0 = sky.params()
+    out = np.zeros_like(p0)
+    for s in range(sky.nsrc):
+        for k in range(10):
+            if k >= 7 and s < sky.npsrc:
+                continue
+            h = 1e-6 * max(abs(p0[s, k]), 1e-3)
+            pp, pm = p0.copy(), p0.copy()
+            pp[s, k] += h
+            pm[s, k] -= h
+            tp = W * np.abs(O.model_vis(obs, Sky.from_params(pp, sky.ngsrc)) - D) ** 2
+            tm = W * np.abs(O.model_vis(obs, Sky.from_params(pm, sky.ngsrc)) - D) ** 2
+            out[s, k] = np.abs((tp - tm) / (2 * h)).sum()
+    return out

@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--modes", default="grad_mixed,grad_fp64,chi2_mixed,chi2_fp64",
+                    help="comma list of timed evaluations (the first must be grad_mixed)")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="MiB copied device-to-device once before timing (a kernel of known "
                          "traffic for calibrating HBM counters)")
@@ -87,6 +89,31 @@ def cpu_baseline(name: str, seconds_target: float = 15.0):
             "kind": "oracle",
             "sample": f"{name} restricted to 1 timestep x {nc} channels (all {obs.nbl} "
                       f"baselines, {sky.nsrc} sources): chi2 + autograd gradient, {dt:.1f} s"}
+
+
+def kernel_source_digest():
+    """sha256 over the kernel sources: the HBM counters below are only valid
+    for the exact code they were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("rime_kernels.hip", "rime_internal.h"):
+        with open(os.path.join(ROOT, "paper_1501_07719_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(path, variant):
+    """HBM bytes per launch of the timed kernel, from the committed
+    FETCH_SIZE + WRITE_SIZE counter summary; None when that summary was taken
+    on other kernel sources or another variant."""
+    try:
+        with open(path) as f:
+            tr = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if tr.get("kernel_source_sha256") != kernel_source_digest() or tr.get("variant") != variant:
+        return None
+    return tr.get("grad_mixed_bytes_per_launch")
 
 
 def make_problem_nchan(name):
@@ -177,28 +204,22 @@ def main():
                 "terms_per_s": terms / (ms * 1e-3), "evals_per_s": 1e3 / ms}
 
     out = {}
-    log("timing chi2+grad mixed")
-    out["grad_mixed"] = run(R.MODE_CHI2_GRAD, R.MIXED, args.steps, args.warmup)
-    log(out["grad_mixed"])
-    if not args.no_fp64:
-        log("timing chi2+grad fp64")
-        out["grad_fp64"] = run(R.MODE_CHI2_GRAD, R.FP64, max(2, args.steps // 2), 1)
-        log(out["grad_fp64"])
-        log("timing chi2 mixed / fp64")
-        out["chi2_mixed"] = run(R.MODE_CHI2, R.MIXED, args.steps, 1)
-        out["chi2_fp64"] = run(R.MODE_CHI2, R.FP64, max(2, args.steps // 2), 1)
-        log(out["chi2_mixed"], out["chi2_fp64"])
+    modes = [m for m in args.modes.split(",") if m]
+    if args.no_fp64:
+        modes = [m for m in modes if not m.endswith("fp64")]
+    spec = {"grad_mixed": (R.MODE_CHI2_GRAD, R.MIXED, args.steps, args.warmup),
+            "grad_fp64": (R.MODE_CHI2_GRAD, R.FP64, max(2, args.steps // 2), 1),
+            "chi2_mixed": (R.MODE_CHI2, R.MIXED, args.steps, 1),
+            "chi2_fp64": (R.MODE_CHI2, R.FP64, max(2, args.steps // 2), 1)}
+    for m in modes:
+        log("timing", m)
+        out[m] = run(*spec[m])
+        log(m, out[m])
 
     g = out["grad_mixed"]
     flops = tp * (FLOPS_FWD["p"] + FLOPS_ADJ["p"]) + tg * (FLOPS_FWD["g"] + FLOPS_ADJ["g"])
     achieved = flops / (g["kernel_ms"] * 1e-3) / 1e12
-    traffic = None
-    try:
-        with open(args.traffic) as f:
-            tr = json.load(f)
-        traffic = tr.get("grad_mixed_bytes_per_launch")
-    except (OSError, ValueError):
-        traffic = None
+    traffic = measured_traffic(args.traffic, list(g["variant"]))
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS["f32"],
                 "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS["f32"], "traffic": traffic,
                 "kernel": "rime_main<float, %d, %d, %d, chi2+grad>" % tuple(g["variant"]),
@@ -229,6 +250,7 @@ def main():
                        "ms_per_step": out["grad_fp64"]["ms_per_step"],
                        "evals_per_s": out["grad_fp64"]["evals_per_s"]}
         rec["speedup_mixed_vs_fp64"] = out["grad_fp64"]["ms_per_step"] / g["ms_per_step"]
+    if "chi2_mixed" in out and "chi2_fp64" in out:
         rec["chi2_only"] = {
             "mixed_terms_per_s": out["chi2_mixed"]["terms_per_s"],
             "fp64_terms_per_s": out["chi2_fp64"]["terms_per_s"],

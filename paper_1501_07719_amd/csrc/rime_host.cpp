@@ -73,6 +73,7 @@ struct rime_plan {
   int32_t beam = 0;
   double ref_freq = 0, beam_k = 0, beam_clip = 0;
   double *d_uvw = nullptr, *d_nu_c = nullptr, *d_lnfr = nullptr, *d_bfr = nullptr;
+  double *d_clip_r2 = nullptr;
   double *d_pointing = nullptr, *d_gains = nullptr;
   TileSet tiles[3];
   int32_t variant[3][2] = {{0, 0}, {0, 0}, {0, 0}};
@@ -324,6 +325,7 @@ KParams base_params(const rime_plan *plan) {
   p.gains = plan->d_gains;
   p.beam = plan->beam;
   p.bfr = plan->d_bfr;
+  p.clip_r2 = plan->d_clip_r2;
   p.beam_k = plan->beam_k;
   p.beam_clip = plan->beam_clip;
   return p;
@@ -411,9 +413,9 @@ rime_status single(const rime_plan *plan, int mode, rime_precision prec, const r
 
 int default_variant(const rime_plan *plan, int mode, int prec) {
   // index layout of the compiled variants: 0 -> 64 threads, 1 -> 256, 2 -> 1024
-  // (FP64 adjoint: 2 -> 256 threads x 4 channels)
+  // (FP64 adjoint: 2 -> 256 threads x 4 channels, the fastest on 64 antennas)
   if (plan->nbl <= 96) return 0;
-  if (mode == RIME_MODE_CHI2_GRAD && prec == RIME_FP64) return 1;
+  if (mode == RIME_MODE_CHI2_GRAD && prec == RIME_FP64) return 2;
   if (plan->nbl >= 1024 && prec == RIME_MIXED) return 2;
   return 1;
 }
@@ -499,6 +501,7 @@ void rime_plan_destroy(rime_plan *plan) {
   (void)hipFree(plan->d_nu_c);
   (void)hipFree(plan->d_lnfr);
   (void)hipFree(plan->d_bfr);
+  (void)hipFree(plan->d_clip_r2);
   (void)hipFree(plan->d_pointing);
   (void)hipFree(plan->d_gains);
   for (auto &t : plan->tiles) {
@@ -562,11 +565,17 @@ rime_status rime_plan_create(const rime_obs_desc *obs, rime_plan **out) {
   pl->beam_clip = obs->beam == 1 ? obs->beam_clip : 0.0;
   const size_t nuvw = static_cast<size_t>(obs->ntime) * obs->na * 3;
   std::vector<double> uvw(obs->uvw, obs->uvw + nuvw);
-  std::vector<double> nu_c(obs->nchan), lnfr(obs->nchan), bfr(obs->nchan, 0.0);
+  std::vector<double> nu_c(obs->nchan), lnfr(obs->nchan), bfr(obs->nchan, 0.0),
+      clip_r2(obs->nchan, 0.0);
   for (int c = 0; c < obs->nchan; ++c) {
     nu_c[c] = obs->freq[c] / kC;
     lnfr[c] = std::log(obs->freq[c] / obs->ref_freq);
-    if (obs->beam == 1) bfr[c] = obs->freq[c] / obs->beam_ref_freq;
+    if (obs->beam == 1) {
+      bfr[c] = obs->freq[c] / obs->beam_ref_freq;
+      // radius at which beam_k r nu / beam_ref_freq reaches the clip
+      const double rc = obs->beam_k > 0 ? obs->beam_clip / (obs->beam_k * bfr[c]) : 1e300;
+      clip_r2[c] = rc * rc;
+    }
   }
   std::vector<double> pnt(static_cast<size_t>(obs->ntime) * obs->na * 2, 0.0);
   if (obs->beam == 1 && obs->pointing) std::copy(obs->pointing, obs->pointing + pnt.size(), pnt.begin());
@@ -581,6 +590,7 @@ rime_status rime_plan_create(const rime_obs_desc *obs, rime_plan **out) {
   if ((e = upload(&pl->d_uvw, uvw)) != hipSuccess || (e = upload(&pl->d_nu_c, nu_c)) != hipSuccess ||
       (e = upload(&pl->d_lnfr, lnfr)) != hipSuccess ||
       (e = upload(&pl->d_bfr, bfr)) != hipSuccess ||
+      (e = upload(&pl->d_clip_r2, clip_r2)) != hipSuccess ||
       (e = upload(&pl->d_pointing, pnt)) != hipSuccess ||
       (e = upload(&pl->d_gains, gains)) != hipSuccess) {
     st = e == hipErrorOutOfMemory ? RIME_ERR_NOMEM : hip_fail(e);

@@ -48,6 +48,7 @@ struct KParams {
   const double *gains;     // [na][2][2]  (unity when absent)
   int32_t beam;
   const double *bfr;       // [nchan]  nu / beam_ref_freq
+  const double *clip_r2;   // [nchan]  (beam_clip / (beam_k nu / beam_ref_freq))^2
   double beam_k;           // beam argument is beam_k * r * nu / beam_ref_freq
   double beam_clip;
   // tiling

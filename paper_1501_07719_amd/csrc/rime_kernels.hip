@@ -46,6 +46,8 @@ template <> struct Num<double> {
   __device__ static inline void sincos_rad(double x, double *s, double *c) { sincos(x, s, c); }
   // exp(y) for y <= 0; y2 = y log2(e) is used by the float version.
   __device__ static inline double exp_neg(double y, double /*y2*/) { return exp(y); }
+  __device__ static inline double sqrt_(double x) { return sqrt(x); }
+  __device__ static inline double rcp(double x) { return 1.0 / x; }
 };
 
 template <> struct Num<float> {
@@ -57,14 +59,18 @@ template <> struct Num<float> {
     *s = __builtin_amdgcn_sinf(rf);
     *c = __builtin_amdgcn_cosf(rf);
   }
-  __device__ static inline void sincos_rad(double x, float *s, float *c) {
-    const float t = static_cast<float>(x * kInvTwoPi);
+  __device__ static inline void sincos_rad(float x, float *s, float *c) {
+    const float t = x * static_cast<float>(kInvTwoPi);
     *s = __builtin_amdgcn_sinf(t);
     *c = __builtin_amdgcn_cosf(t);
   }
   __device__ static inline float exp_neg(float /*y*/, float y2) {
     return __builtin_amdgcn_exp2f(y2);
   }
+  __device__ static inline float sqrt_(double x) {
+    return __builtin_amdgcn_sqrtf(static_cast<float>(x));
+  }
+  __device__ static inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 };
 
 // (a0 b0 + a1 b1) + a2 b2 with every product and sum rounded separately (no
@@ -231,11 +237,13 @@ __device__ inline void stage_tile(const KParams &p, const SetDesc &sd, int tile,
       const double4 g = p.src_geo[sd.src_off + s0 + s];
       // tau = u l + v m + w (n - 1), metres (eq. k_term)
       const double tau = dot3_rn(s_uvw[ai][0], g.x, s_uvw[ai][1], g.y, s_uvw[ai][2], g.z);
-      double rb = 0.0, dl = 0.0, dm = 0.0;
+      double r2b = 0.0, dl = 0.0, dm = 0.0;
+      R rb = R(0);
       if (p.beam) {
         dl = g.x - s_pnt[ai][0];
         dm = g.y - s_pnt[ai][1];
-        rb = sqrt(sumsq_rn(dl, dm));
+        r2b = sumsq_rn(dl, dm);
+        rb = N::sqrt_(r2b);
       }
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
@@ -246,23 +254,20 @@ __device__ inline void stage_tile(const KParams &p, const SetDesc &sd, int tile,
           N::sincos_turns(r, &sn, &cs);
           R e = R(1);
           if (p.beam) {
-            // x_b = beam_k r nu / beam_ref_freq, clipped (eq. e_term)
-            const double bfr = p.bfr[c0 + c];
-            const double xb = (p.beam_k * rb) * bfr;
-            const bool clipped = xb >= p.beam_clip;
-            const double xc = clipped ? p.beam_clip : xb;
+            // x_b = bs r, bs = beam_k nu / beam_ref_freq, clipped at beam_clip
+            // (eq. e_term); the clip is decided in float64 on r^2 against the
+            // per-channel threshold (beam_clip / bs)^2.
+            const double bs = p.beam_k * p.bfr[c0 + c];
+            const bool clipped = r2b >= p.clip_r2[c0 + c];
+            const R xr = clipped ? static_cast<R>(p.beam_clip) : static_cast<R>(bs) * rb;
             R sb, cb;
-            N::sincos_rad(xc, &sb, &cb);
+            N::sincos_rad(xr, &sb, &cb);
             e = cb * cb * cb;
             if (WITH_BETA) {
-              // d ln e / dl = -3 tan(x) dx/dl, dx/dl = bs (l - dl_p) / r, bs = beam_k nu/nu_b
+              // d ln e / dl = -3 tan(x) dx/dl, dx/dl = bs (l - dl_p) / r
               //             = -3 bs^2 (l - dl_p) tan(x)/x ; zero past the clip.
               R tx = R(0);
-              if (!clipped) {
-                const R xr = static_cast<R>(xc);
-                tx = xr > R(1e-4) ? sb / (cb * xr) : R(1) + xr * xr / R(3);
-              }
-              const double bs = p.beam_k * bfr;
+              if (!clipped) tx = xr > R(1e-4) ? sb * N::rcp(cb * xr) : R(1) + xr * xr / R(3);
               const R k3 = static_cast<R>(-3.0 * bs * bs) * tx;
               bet[c].x = k3 * static_cast<R>(dl);
               bet[c].y = k3 * static_cast<R>(dm);
@@ -350,19 +355,19 @@ __device__ inline void accumulate(int cnt, const typename Num<R>::R2 *ap_row,
 
 // Pass 2 inner loop over the tile's active baselines, for this lane's
 // (source, channel).  Accumulators:
-//   g[0..3]  sum Re(c rho_k)                      (Stokes, times f later)
-//   g[4]     sum Re P                              (alpha, times ln(nu/nu_ref))
+//   g[0..3]  sum Re(c rho_k)                      (Stokes, times f later; also
+//            give sum Re P = sum_k St'_k g[k] for alpha)
 //   g[5], g[6]   sum (beta_p + beta_q)_{l,m} Re P  (beam part of l, m)
 //   g[7], g[8], g[9]  sum (du, dv, dw) Im P        (phase part of l, m)
 //   g[10..14]  Gaussian: sum du A ReP, sum dv B ReP, sum dv A ReP, sum du B ReP,
 //              sum B^2 ReP
-// with P = c Phi, Phi = sum_k St'_k rho_k.
-template <class R, int NC, bool GAUSS, bool BEAM>
-__device__ inline void adjoint_loop(int wave, int nw, int nact, const int *s_lpq,
+// with P = c Phi, Phi = sum_k St'_k rho_k.  `s_off` holds, per baseline, the
+// byte offsets of a_p and a_q within a source row of the a-tile; the beta row
+// of the same source lies BETA_OFF bytes further.
+template <class R, int NC, bool GAUSS, bool BEAM, int BETA_OFF>
+__device__ inline void adjoint_loop(int wave, int nw, int nact, const int2 *s_off,
                                     const typename Num<R>::R4 *s_geo,
-                                    const typename Num<R>::R2 *s_rho,
-                                    const typename Num<R>::R2 *arow,
-                                    const typename Num<R>::R2 *brow,
+                                    const typename Num<R>::R2 *s_rho, const char *arow,
                                     const typename Num<R>::R4 st,
                                     const typename Num<R>::R4 gsh, R gq, R gq2, int cl,
                                     R (&g)[15]) {
@@ -371,10 +376,12 @@ __device__ inline void adjoint_loop(int wave, int nw, int nact, const int *s_lpq
   using R4 = typename N::R4;
 #pragma unroll 2
   for (int bi = wave; bi < nact; bi += nw) {
-    const int q = s_lpq[bi];
-    const int bp_ = q & 0xffff, bq_ = q >> 16;
+    const int2 o = s_off[bi];
     const R4 geo = s_geo[bi];
-    const R2 ap = arow[bp_ * NC], aq = arow[bq_ * NC];
+    const char *pa = arow + o.x;
+    const char *qa = arow + o.y;
+    const R2 ap = *reinterpret_cast<const R2 *>(pa);
+    const R2 aq = *reinterpret_cast<const R2 *>(qa);
     const R2 *rho = s_rho + (bi * NC + cl) * 4;
     const R2 r0 = rho[0], r1 = rho[1], r2 = rho[2], r3 = rho[3];
     R cr = ap.x * aq.x + ap.y * aq.y;
@@ -388,17 +395,22 @@ __device__ inline void adjoint_loop(int wave, int nw, int nact, const int *s_lpq
       cr *= S;
       ci *= S;
     }
-    g[0] += cr * r0.x - ci * r0.y;
-    g[1] += cr * r1.x - ci * r1.y;
-    g[2] += cr * r2.x - ci * r2.y;
-    g[3] += cr * r3.x - ci * r3.y;
+    // Re(c rho_k) as two fused multiply-adds each
+    g[0] += cr * r0.x;
+    g[0] -= ci * r0.y;
+    g[1] += cr * r1.x;
+    g[1] -= ci * r1.y;
+    g[2] += cr * r2.x;
+    g[2] -= ci * r2.y;
+    g[3] += cr * r3.x;
+    g[3] -= ci * r3.y;
     const R phr = st.x * r0.x + st.y * r1.x + st.z * r2.x + st.w * r3.x;
     const R phi = st.x * r0.y + st.y * r1.y + st.z * r2.y + st.w * r3.y;
     const R Pr = cr * phr - ci * phi;
     const R Pi = cr * phi + ci * phr;
-    g[4] += Pr;
     if (BEAM) {
-      const R2 bp = brow[bp_ * NC], bq = brow[bq_ * NC];
+      const R2 bp = *reinterpret_cast<const R2 *>(pa + BETA_OFF);
+      const R2 bq = *reinterpret_cast<const R2 *>(qa + BETA_OFF);
       g[5] += (bp.x + bq.x) * Pr;
       g[6] += (bp.y + bq.y) * Pr;
     }
@@ -433,7 +445,7 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
   __shared__ __attribute__((aligned(16))) char s_ab[L::AB_BYTES];
   __shared__ __attribute__((aligned(16))) char s_rho_raw[L::RHO_BYTES > 0 ? L::RHO_BYTES : 16];
   __shared__ __attribute__((aligned(16))) char s_geo_raw[L::GEO_BYTES > 0 ? L::GEO_BYTES : 16];
-  __shared__ int s_lpq[L::GRAD ? NBT : 1];
+  __shared__ int2 s_off[L::GRAD ? NBT : 1];  // a-tile offsets of (p, q)
   R2 *s_a = reinterpret_cast<R2 *>(s_ab);
   R2 *s_beta = reinterpret_cast<R2 *>(s_ab + L::A_BYTES);
   R *s_red = reinterpret_cast<R *>(s_ab);
@@ -505,47 +517,15 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
     const R dv = static_cast<R>(s_uvw[lp][1] - s_uvw[lq][1]);
     const R dw = static_cast<R>(s_uvw[lp][2] - s_uvw[lq][2]);
 
-    // ---- pass 1: source sums ----------------------------------------------
-    double acc[NC][8];
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
-#pragma unroll
-      for (int k = 0; k < 8; ++k) acc[c][k] = 0.0;
-
-    for (int k = 0; k < nst; ++k) {
-      const bool gauss = k >= npt;
-      const int s0 = gauss ? sd.npsrc + (k - npt) * NS : k * NS;
-      const int cnt = min(NS, (gauss ? nsrc : sd.npsrc) - s0);
-      __syncthreads();
-      stage_tile<R, NBT, NC, NS, MODE, false>(p, sd, tile, s0, cnt, gauss, c0, ncv, s_uvw,
-                                              s_pnt, s_a, s_beta, s_st, s_gs);
-      __syncthreads();
-      R in[NC][8];
-#pragma unroll
-      for (int c = 0; c < NC; ++c)
-#pragma unroll
-        for (int j = 0; j < 8; ++j) in[c][j] = R(0);
-      if (gauss)
-        accumulate<R, NC, L::AST, true>(cnt, s_a + lp * NC, s_a + lq * NC, s_st, s_gs, du, dv,
-                                        gq, gq2, in);
-      else
-        accumulate<R, NC, L::AST, false>(cnt, s_a + lp * NC, s_a + lq * NC, s_st, s_gs, du, dv,
-                                         gq, gq2, in);
-#pragma unroll
-      for (int c = 0; c < NC; ++c)
-#pragma unroll
-        for (int j = 0; j < 8; ++j) acc[c][j] += static_cast<double>(in[c][j]);
-    }
-
-    // ---- epilogue: V, residual, chi^2 --------------------------------------
-    if (active) {
-      // gains of this baseline's antennas: V_ij *= g_pi conj(g_qj)
+    // ---- epilogue for one channel: V, residual, chi^2 (and rho) ---------------
+    // S = the four Stokes sums (re, im) of this thread's baseline.
+    auto gains = [&](double2 (&gg)[4]) {
+      // V_ij *= g_pi conj(g_qj)
       const int gap = p.tile_ant[tile * NAT + lp], gaq = p.tile_ant[tile * NAT + lq];
       const double2 gpi[2] = {make_double2(p.gains[4 * gap + 0], p.gains[4 * gap + 1]),
                               make_double2(p.gains[4 * gap + 2], p.gains[4 * gap + 3])};
       const double2 gqj[2] = {make_double2(p.gains[4 * gaq + 0], p.gains[4 * gaq + 1]),
                               make_double2(p.gains[4 * gaq + 2], p.gains[4 * gaq + 3])};
-      double2 gg[4];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -553,82 +533,123 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
           const double2 a = gpi[i], b = gqj[j];
           gg[2 * i + j] = make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
         }
+    };
+    auto epilogue = [&](int c, const double (&S)[8], const double2 (&gg)[4]) {
+      const bool ok = c < ncv;
+      // Stokes sums -> 2x2 coherency (eq. brightness_term)
+      const double SIr = S[0], SIi = S[1], SQr = S[2], SQi = S[3];
+      const double SUr = S[4], SUi = S[5], SVr = S[6], SVi = S[7];
+      double Vr[4], Vi[4];
+      Vr[0] = SIr + SQr;  // xx
+      Vi[0] = SIi + SQi;
+      Vr[1] = SUr - SVi;  // xy = S_U + i S_V
+      Vi[1] = SUi + SVr;
+      Vr[2] = SUr + SVi;  // yx = S_U - i S_V
+      Vi[2] = SUi - SVr;
+      Vr[3] = SIr - SQr;  // yy
+      Vi[3] = SIi - SQi;
 #pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        const bool ok = c < ncv;
-        // Stokes sums -> 2x2 coherency (eq. brightness_term)
-        const double SIr = acc[c][0], SIi = acc[c][1], SQr = acc[c][2], SQi = acc[c][3];
-        const double SUr = acc[c][4], SUi = acc[c][5], SVr = acc[c][6], SVi = acc[c][7];
-        double Vr[4], Vi[4];
-        Vr[0] = SIr + SQr;  // xx
-        Vi[0] = SIi + SQi;
-        Vr[1] = SUr - SVi;  // xy = S_U + i S_V
-        Vi[1] = SUi + SVr;
-        Vr[2] = SUr + SVi;  // yx = S_U - i S_V
-        Vi[2] = SUi - SVr;
-        Vr[3] = SIr - SQr;  // yy
-        Vi[3] = SIi - SQi;
+      for (int k = 0; k < 4; ++k) {
+        const double r = Vr[k] * gg[k].x - Vi[k] * gg[k].y;
+        const double i = Vr[k] * gg[k].y + Vi[k] * gg[k].x;
+        Vr[k] = r;
+        Vi[k] = i;
+      }
+      const int64_t vidx = ((static_cast<int64_t>(t) * p.nbl + bl) * p.nchan + c0 + c) * 4;
+      if (MODE == MODE_PREDICT) {
+        if (ok) {
+          R2 *out = static_cast<R2 *>(p.vis) + vidx;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const double r = Vr[k] * gg[k].x - Vi[k] * gg[k].y;
-          const double i = Vr[k] * gg[k].y + Vi[k] * gg[k].x;
-          Vr[k] = r;
-          Vi[k] = i;
-        }
-        const int64_t vidx = ((static_cast<int64_t>(t) * p.nbl + bl) * p.nchan + c0 + c) * 4;
-        if (MODE == MODE_PREDICT) {
-          if (ok) {
-            R2 *out = static_cast<R2 *>(p.vis) + vidx;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-              R2 v;
-              v.x = static_cast<R>(Vr[k]);
-              v.y = static_cast<R>(Vi[k]);
-              out[k] = v;
-            }
-          }
-        } else {
-          double Yr[4] = {0, 0, 0, 0}, Yi[4] = {0, 0, 0, 0};
-          if (ok) {
-            const R2 *D = static_cast<const R2 *>(p.data) + vidx;
-            const R *W = static_cast<const R *>(p.weight) + vidx;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-              const R2 d = D[k];
-              const double w = static_cast<double>(W[k]);
-              const double rr = Vr[k] - static_cast<double>(d.x);
-              const double ri = Vi[k] - static_cast<double>(d.y);
-              chi.add(w * (rr * rr + ri * ri));
-              Yr[k] = w * rr;
-              Yi[k] = w * ri;
-            }
-          }
-          if (MODE == MODE_GRAD) {
-            // Z_ij = Y_ij conj(g_pi) g_qj = Y_ij conj(gg_ij); then
-            // rho_I = conj(Zxx) + conj(Zyy), rho_Q = conj(Zxx) - conj(Zyy),
-            // rho_U = conj(Zxy) + conj(Zyx), rho_V = i (conj(Zxy) - conj(Zyx))
-            double Zr[4], Zi[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-              Zr[k] = Yr[k] * gg[k].x + Yi[k] * gg[k].y;
-              Zi[k] = Yi[k] * gg[k].x - Yr[k] * gg[k].y;
-            }
-            R2 *rho = s_rho + (tid * NC + c) * 4;
+          for (int k = 0; k < 4; ++k) {
             R2 v;
-            v.x = static_cast<R>(Zr[0] + Zr[3]);
-            v.y = static_cast<R>(-(Zi[0] + Zi[3]));
-            rho[0] = v;
-            v.x = static_cast<R>(Zr[0] - Zr[3]);
-            v.y = static_cast<R>(-(Zi[0] - Zi[3]));
-            rho[1] = v;
-            v.x = static_cast<R>(Zr[1] + Zr[2]);
-            v.y = static_cast<R>(-(Zi[1] + Zi[2]));
-            rho[2] = v;
-            v.x = static_cast<R>(Zi[1] - Zi[2]);
-            v.y = static_cast<R>(Zr[1] - Zr[2]);
-            rho[3] = v;
+            v.x = static_cast<R>(Vr[k]);
+            v.y = static_cast<R>(Vi[k]);
+            out[k] = v;
           }
         }
+      } else {
+        double Yr[4] = {0, 0, 0, 0}, Yi[4] = {0, 0, 0, 0};
+        if (ok) {
+          const R2 *D = static_cast<const R2 *>(p.data) + vidx;
+          const R *W = static_cast<const R *>(p.weight) + vidx;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const R2 d = D[k];
+            const double w = static_cast<double>(W[k]);
+            const double rr = Vr[k] - static_cast<double>(d.x);
+            const double ri = Vi[k] - static_cast<double>(d.y);
+            chi.add(w * (rr * rr + ri * ri));
+            Yr[k] = w * rr;
+            Yi[k] = w * ri;
+          }
+        }
+        if (MODE == MODE_GRAD) {
+          // Z_ij = Y_ij conj(g_pi) g_qj = Y_ij conj(gg_ij); then
+          // rho_I = conj(Zxx) + conj(Zyy), rho_Q = conj(Zxx) - conj(Zyy),
+          // rho_U = conj(Zxy) + conj(Zyx), rho_V = i (conj(Zxy) - conj(Zyx))
+          double Zr[4], Zi[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            Zr[k] = Yr[k] * gg[k].x + Yi[k] * gg[k].y;
+            Zi[k] = Yi[k] * gg[k].x - Yr[k] * gg[k].y;
+          }
+          R2 *rho = s_rho + (tid * NC + c) * 4;
+          R2 v;
+          v.x = static_cast<R>(Zr[0] + Zr[3]);
+          v.y = static_cast<R>(-(Zi[0] + Zi[3]));
+          rho[0] = v;
+          v.x = static_cast<R>(Zr[0] - Zr[3]);
+          v.y = static_cast<R>(-(Zi[0] - Zi[3]));
+          rho[1] = v;
+          v.x = static_cast<R>(Zr[1] + Zr[2]);
+          v.y = static_cast<R>(-(Zi[1] + Zi[2]));
+          rho[2] = v;
+          v.x = static_cast<R>(Zi[1] - Zi[2]);
+          v.y = static_cast<R>(Zr[1] - Zr[2]);
+          rho[3] = v;
+        }
+      }
+    };
+
+    {
+      // ---- pass 1: source sums ----------------------------------------------
+      double acc[NC][8];
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc[c][k] = 0.0;
+
+      for (int k = 0; k < nst; ++k) {
+        const bool gauss = k >= npt;
+        const int s0 = gauss ? sd.npsrc + (k - npt) * NS : k * NS;
+        const int cnt = min(NS, (gauss ? nsrc : sd.npsrc) - s0);
+        __syncthreads();
+        stage_tile<R, NBT, NC, NS, MODE, false>(p, sd, tile, s0, cnt, gauss, c0, ncv, s_uvw,
+                                                s_pnt, s_a, s_beta, s_st, s_gs);
+        __syncthreads();
+        R in[NC][8];
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+          for (int j = 0; j < 8; ++j) in[c][j] = R(0);
+        if (gauss)
+          accumulate<R, NC, L::AST, true>(cnt, s_a + lp * NC, s_a + lq * NC, s_st, s_gs, du,
+                                          dv, gq, gq2, in);
+        else
+          accumulate<R, NC, L::AST, false>(cnt, s_a + lp * NC, s_a + lq * NC, s_st, s_gs, du,
+                                           dv, gq, gq2, in);
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+          for (int j = 0; j < 8; ++j) acc[c][j] += static_cast<double>(in[c][j]);
+      }
+
+      // ---- epilogue ------------------------------------------------------------
+      if (active) {
+        double2 gg[4];
+        gains(gg);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) epilogue(c, acc[c], gg);
       }
     }
 
@@ -641,9 +662,12 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
         g.z = dw;
         g.w = R(0);
         s_geo[tid] = g;
-        s_lpq[tid] = lpq;
+        s_off[tid] = make_int2(lp * NC * static_cast<int>(sizeof(R2)),
+                               lq * NC * static_cast<int>(sizeof(R2)));
       }
-      const int lane = tid % kWave, wave = tid / kWave;
+      const int lane = tid % kWave;
+      // wavefront index, uniform across the wavefront (scalar loop counters)
+      const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
       const int sl = lane / NC, cl = lane - (lane / NC) * NC;
       const bool lane_ok_c = cl < ncv;
       const double nuc_l = lane_ok_c ? p.nu_c[c0 + cl] : 0.0;
@@ -671,26 +695,27 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
           R4 gsh;
           gsh.x = gsh.y = gsh.z = gsh.w = R(0);
           if (gauss) gsh = s_gs[sl];
-          const R2 *arow = s_a + sl * L::AST + cl;
-          const R2 *brow = s_beta + sl * L::AST + cl;
+          const char *arow = reinterpret_cast<const char *>(s_a + sl * L::AST + cl);
+          constexpr int BO = static_cast<int>(L::A_BYTES);
           R g[15];
 #pragma unroll
           for (int j = 0; j < 15; ++j) g[j] = R(0);
           if (p.beam) {
             if (gauss)
-              adjoint_loop<R, NC, true, true>(wave, NW, nact, s_lpq, s_geo, s_rho, arow, brow,
-                                              st, gsh, gq_l, gq2_l, cl, g);
+              adjoint_loop<R, NC, true, true, BO>(wave, NW, nact, s_off, s_geo, s_rho, arow, st,
+                                                  gsh, gq_l, gq2_l, cl, g);
             else
-              adjoint_loop<R, NC, false, true>(wave, NW, nact, s_lpq, s_geo, s_rho, arow, brow,
-                                               st, gsh, gq_l, gq2_l, cl, g);
+              adjoint_loop<R, NC, false, true, BO>(wave, NW, nact, s_off, s_geo, s_rho, arow, st,
+                                                   gsh, gq_l, gq2_l, cl, g);
           } else {
             if (gauss)
-              adjoint_loop<R, NC, true, false>(wave, NW, nact, s_lpq, s_geo, s_rho, arow, brow,
-                                               st, gsh, gq_l, gq2_l, cl, g);
+              adjoint_loop<R, NC, true, false, BO>(wave, NW, nact, s_off, s_geo, s_rho, arow,
+                                                   st, gsh, gq_l, gq2_l, cl, g);
             else
-              adjoint_loop<R, NC, false, false>(wave, NW, nact, s_lpq, s_geo, s_rho, arow,
-                                                brow, st, gsh, gq_l, gq2_l, cl, g);
+              adjoint_loop<R, NC, false, false, BO>(wave, NW, nact, s_off, s_geo, s_rho, arow,
+                                                    st, gsh, gq_l, gq2_l, cl, g);
           }
+          g[4] = st.x * g[0] + st.y * g[1] + st.z * g[2] + st.w * g[3];
           // assemble: Stokes by the spectral factor, alpha by ln(nu/nu_ref),
           // l and m from their beam and phase parts, shape by 2 gq.
           const double al = sd.alpha[s0 + sl];
@@ -709,19 +734,25 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
             gl[9] = R(2) * gq_l * gsh.w * g[14];
           }
         }
-        __syncthreads();  // the reduction buffer aliases the a/beta tiles
+        // sum the NC channel lanes of each source (adjacent lanes), then
+        // across wavefronts through LDS in a fixed order
 #pragma unroll
-        for (int j = 0; j < 10; ++j) s_red[(wave * kWave + lane) * 10 + j] = gl[j];
+        for (int j = 0; j < 10; ++j)
+#pragma unroll
+          for (int d = 1; d < NC; d <<= 1) gl[j] += __shfl_xor(gl[j], d, kWave);
+        __syncthreads();  // the reduction buffer aliases the a/beta tiles
+        if (cl == 0) {
+#pragma unroll
+          for (int j = 0; j < 10; ++j) s_red[(wave * NS + sl) * 10 + j] = gl[j];
+        }
         __syncthreads();
         for (int idx = tid; idx < NS * 10; idx += NBT) {
-          const int s = idx / 10, j = idx - (idx / 10) * 10;
+          const int s = idx / 10;
           if (s >= cnt) continue;
           double sum = 0.0;
-          for (int w = 0; w < NW; ++w)
-#pragma unroll
-            for (int c = 0; c < NC; ++c)
-              sum += static_cast<double>(s_red[(w * kWave + s * NC + c) * 10 + j]);
-          double *dst = gout + static_cast<int64_t>(s0 + s) * 10 + j;
+#pragma unroll 4
+          for (int w = 0; w < NW; ++w) sum += static_cast<double>(s_red[w * NS * 10 + idx]);
+          double *dst = gout + static_cast<int64_t>(s0) * 10 + idx;
           if (t == t0)
             *dst = sum;
           else
@@ -834,7 +865,9 @@ struct VariantEntry {
 #define RIME_V(R, NBT, NC, NS, M) \
   { {NBT, NC, NS}, &launch_main<R, NBT, NC, NS, M> }
 
-static const VariantEntry kVariants[3][2][4] = {
+constexpr int kNumVariants = 4;
+
+static const VariantEntry kVariants[3][2][kNumVariants] = {
     // MODE_PREDICT
     {{RIME_V(double, 64, 2, 32, MODE_PREDICT), RIME_V(double, 256, 2, 32, MODE_PREDICT),
       RIME_V(double, 1024, 2, 32, MODE_PREDICT), RIME_V(double, 256, 4, 16, MODE_PREDICT)},
@@ -852,10 +885,11 @@ static const VariantEntry kVariants[3][2][4] = {
       RIME_V(float, 1024, 2, 32, MODE_GRAD), RIME_V(float, 256, 4, 16, MODE_GRAD)}},
 };
 
-int variant_count(int /*mode*/, int /*prec*/) { return 4; }
+int variant_count(int /*mode*/, int /*prec*/) { return kNumVariants; }
 
 const Variant *variant_info(int mode, int prec, int index) {
-  if (mode < 0 || mode > 2 || prec < 0 || prec > 1 || index < 0 || index >= 4) return nullptr;
+  if (mode < 0 || mode > 2 || prec < 0 || prec > 1 || index < 0 || index >= kNumVariants)
+    return nullptr;
   return &kVariants[mode][prec][index].v;
 }
 

@@ -1,17 +1,34 @@
 """Benchmark: chi^2 + gradient evaluations of the full RIME on one MI355X.
 
-Workload (default): 64 antennas (2016 baselines), 100 timesteps, 64 channels
-over 0.9-1.7 GHz, 1000 point + 500 Gaussian sources, cos^3 beam with pointing
-errors and diagonal gains; observed data = model at 1 %-perturbed parameters
-plus complex Gaussian noise (sigma 0.01 Jy), weights 1/sigma^2.  All inputs are
-seeded synthetic data resident in HBM before the timed region.
+Default workload (c2): 64 antennas (2016 baselines), 100 timesteps, 64
+channels over 0.9-1.7 GHz, 1000 point + 500 Gaussian sources, cos^3 beam with
+pointing errors and diagonal gains.  The observed data is the model at
+1 %-perturbed parameters plus complex Gaussian noise (sigma 0.01 Jy), with
+weights 1/sigma^2.  All inputs are seeded synthetic data, resident in HBM
+before the timed region.
 
-One step = one chi^2 + gradient evaluation (every stage of the path: per-source
-preparation, per-antenna phase/beam, brightness, Gaussian shape, source-summed
-accumulation, fused chi^2 and the adjoint) in FP32-mixed precision.  The JSON
-line also carries the FP64 figures on the same workload, the chi^2-only
-figures, the roofline of the dominant kernel (timed live with HIP events on its
-stream) and the CPU oracle timed on a bounded sample of the same workload.
+One step is one chi^2 + gradient evaluation in FP32-mixed precision.  It runs
+every stage of the path:
+- per-source preparation;
+- per-antenna phase and beam;
+- brightness and Gaussian shape;
+- the source-summed accumulation;
+- the fused chi^2;
+- the adjoint.
+
+The JSON line also carries:
+- the FP64 figures and the chi^2-only figures on the same workload;
+- the roofline of the dominant kernel, timed live with HIP events on its stream;
+- the CPU oracle, timed on a bounded sample of the same workload.
+
+Other workloads (`--config`), which give the same JSON line for their own
+shape:
+- c0: 7 antennas, 10 t, 16 ch, 20 points, no beam, FP64.  Latency of one
+  graph-launched chi^2 + gradient.
+- c3: 256 proposals of 10..2000 sources over one 64-antenna observation
+  (50 t, 32 ch).  Batched in one graph launch, compared with a per-set loop
+  and with the default kernel variant.
+- c4: 197 antennas (19306 baselines), 20 t, 256 ch, 1500 P + 500 G, beam.
 """
 from __future__ import annotations
 
@@ -37,13 +54,15 @@ PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
 FLOPS_FWD = {"p": 22, "g": 25}
 FLOPS_ADJ = {"p": 61, "g": 89}
 
+DEFAULT_STEPS = {"c0": 200, "c2": 10, "c3": 3, "c4": 3}
+
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c4"])
+    ap.add_argument("--config", default="c2", choices=["c0", "c1", "c2", "c3", "c4"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
@@ -53,43 +72,73 @@ def parse():
                     help="MiB copied device-to-device once before timing (a kernel of known "
                          "traffic for calibrating HBM counters)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"))
-    return ap.parse_args()
+    a = ap.parse_args()
+    if a.config == "c1":
+        a.config = "c2"
+    if a.steps is None:
+        a.steps = DEFAULT_STEPS[a.config]
+    return a
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(name: str, seconds_target: float = 15.0):
-    """Time the CPU oracle (chi^2 + autograd gradient) on a bounded sample of
-    the workload: the first timestep and the first nc channels, all baselines
-    and all sources, nc grown from 8 until the sample takes about
-    `seconds_target` seconds.  Returns terms/s."""
+# --------------------------------------------------------------------------- #
+# CPU oracle baseline (the only part of this file that runs the oracle)
+# --------------------------------------------------------------------------- #
+
+def cpu_baseline(sample_fn, seconds_target: float = 15.0):
+    """Time the CPU oracle (chi^2 + autograd gradient) on a bounded sample:
+    `sample_fn(nc)` returns (obs, sky, D, W, description, nchan of the full
+    workload) restricted to nc channels of one timestep; nc grows from 8 until
+    the sample takes about `seconds_target` seconds.  Returns the cpu_baseline
+    record in terms/s."""
     import torch
 
     import oracle.rime_oracle as O
-    from rime_synth import make_problem
 
     ncores = min(os.cpu_count() or 1, 16)
     torch.set_num_threads(ncores)
     nc = 8
     while True:
-        pr = make_problem(name, ntime=1, nchan=nc)
-        obs, sky = pr.obs, pr.sky
-        D = O.model_vis(obs, pr.truth) + pr.noise
+        obs, sky, D, W, desc, full = sample_fn(nc)
         t0 = time.perf_counter()
-        O.chi2_and_grad(obs, sky, D, pr.weight, src_chunk=32)
+        O.chi2_and_grad(obs, sky, D, W, src_chunk=32)
         dt = time.perf_counter() - t0
-        full = make_problem_nchan(name)
         if dt >= seconds_target / 3 or nc >= full:
             break
         nc = min(full, int(nc * seconds_target / max(dt, 1e-3)) + 1)
     terms = obs.ntime * obs.nbl * obs.nchan * sky.nsrc
     return {"value": terms / dt, "unit": "terms/s", "cores": torch.get_num_threads(),
             "kind": "oracle",
-            "sample": f"{name} restricted to 1 timestep x {nc} channels (all {obs.nbl} "
+            "sample": f"{desc} restricted to 1 timestep x {nc} channels (all {obs.nbl} "
                       f"baselines, {sky.nsrc} sources): chi2 + autograd gradient, {dt:.1f} s"}
 
+
+def problem_sample(name):
+    def fn(nc):
+        import oracle.rime_oracle as O
+        from rime_synth import CONFIGS, make_problem
+        pr = make_problem(name, ntime=1, nchan=nc)
+        D = O.model_vis(pr.obs, pr.truth) + pr.noise
+        return pr.obs, pr.sky, D, pr.weight, name, CONFIGS[name]["nchan"]
+    return fn
+
+
+def batch_sample(pb, set_index):
+    def fn(nc):
+        import oracle.rime_oracle as O
+        obs = pb.obs.time_slice(0, 1).chan_slice(0, nc)
+        D = O.model_vis(obs, pb.truth) + pb.noise[:1, :, :nc]
+        W = pb.weight[:1, :, :nc]
+        return obs, pb.skies[set_index], D, W, f"c3 proposal {set_index}", pb.obs.nchan
+    return fn
+
+
+# --------------------------------------------------------------------------- #
+# helpers
+# --------------------------------------------------------------------------- #
 
 def kernel_source_digest():
     """sha256 over the kernel sources: the HBM counters below are only valid
@@ -102,23 +151,365 @@ def kernel_source_digest():
     return h.hexdigest()
 
 
-def measured_traffic(path, variant):
+def measured_traffic(path, variant, workload):
     """HBM bytes per launch of the timed kernel, from the committed
     FETCH_SIZE + WRITE_SIZE counter summary; None when that summary was taken
-    on other kernel sources or another variant."""
+    on other kernel sources, another variant or another workload."""
     try:
         with open(path) as f:
             tr = json.load(f)
     except (OSError, ValueError):
         return None
-    if tr.get("kernel_source_sha256") != kernel_source_digest() or tr.get("variant") != variant:
+    if (tr.get("kernel_source_sha256") != kernel_source_digest() or tr.get("variant") != variant
+            or tr.get("workload", "c2") != workload):
         return None
     return tr.get("grad_mixed_bytes_per_launch")
 
 
-def make_problem_nchan(name):
-    from rime_synth import CONFIGS
-    return CONFIGS[name]["nchan"]
+def alg_flops(tp, tg):
+    return tp * (FLOPS_FWD["p"] + FLOPS_ADJ["p"]) + tg * (FLOPS_FWD["g"] + FLOPS_ADJ["g"])
+
+
+def roofline(flops, kernel_ms, variant, traffic):
+    achieved = flops / (kernel_ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS["f32"],
+            "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS["f32"], "traffic": traffic,
+            "kernel": "rime_main<float, %d, %d, %d, chi2+grad>" % tuple(variant),
+            "kernel_ms": kernel_ms, "flops_per_launch": flops}
+
+
+def timed(call, steps, warmup, events_fn=None):
+    """Mean ms per call over `steps` timed calls after `warmup` untimed ones.
+    `events_fn(start, stop)` installs per-call kernel timing events (or
+    removes them with None, None); returns (ms, kernel_ms or None)."""
+    import torch
+    for _ in range(warmup):
+        call()
+    torch.cuda.synchronize()
+    ks = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ke = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    # torch creates the underlying hipEvent on first record: record each once
+    # so that the handles passed to the library are valid
+    for e in ks + ke:
+        e.record()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for i in range(steps):
+        if events_fn:
+            events_fn(ks[i], ke[i])
+        call()
+    stop.record()
+    torch.cuda.synchronize()
+    if events_fn:
+        events_fn(None, None)
+    ms = start.elapsed_time(stop) / steps
+    kms = float(np.mean([ks[i].elapsed_time(ke[i]) for i in range(steps)])) if events_fn else None
+    return ms, kms
+
+
+def upload_data(R, plan, truth, noise, weight):
+    """D = FP64 model at the truth parameters (GPU predict) + noise, in both
+    precisions, resident on the device."""
+    import torch
+    shp = (plan.ntime, plan.nbl, plan.nchan, 4)
+    vis = torch.empty(shp, dtype=torch.complex128, device="cuda")
+    ws = R.workspace(plan, R.MODE_PREDICT, R.FP64, 1, truth.nsrc)
+    R.rime_predict(plan, R.DeviceSky.from_host(truth), R.FP64, vis, ws)
+    vis += torch.as_tensor(noise, device="cuda")
+    del ws
+    W64 = torch.as_tensor(weight, device="cuda")
+    D32, W32 = vis.to(torch.complex64), W64.to(torch.float32)
+    torch.cuda.synchronize()
+    return vis, W64, D32, W32
+
+
+def calib_copy(mib):
+    import torch
+    if mib:
+        # a plain device copy of known size: mib MiB read + written
+        a = torch.ones(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+
+def base_record(args, metric, value, ms, dtype, workload, extra_cfg):
+    cfg = {"workload": workload}
+    cfg.update(extra_cfg)
+    return {"metric": metric, "value": value, "unit": "terms/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": dtype, "data": "synthetic", "config": cfg}
+
+
+# --------------------------------------------------------------------------- #
+# single-sky workloads: c2 (default) and c4
+# --------------------------------------------------------------------------- #
+
+def bench_single(args):
+    import torch
+
+    import paper_1501_07719_amd as R
+    from rime_synth import make_problem
+
+    name = "c1" if args.config == "c2" else args.config
+    t_gen = time.perf_counter()
+    pr = make_problem(name)
+    obs, sky, truth = pr.obs, pr.sky, pr.truth
+    log(f"generated {name}: na={obs.na} nbl={obs.nbl} ntime={obs.ntime} nchan={obs.nchan} "
+        f"nsrc={sky.nsrc} in {time.perf_counter() - t_gen:.1f}s")
+    plan = R.Plan(obs)
+    D64, W64, D32, W32 = upload_data(R, plan, truth, pr.noise, pr.weight)
+    del pr
+    dsky = R.DeviceSky.from_host(sky)
+    calib_copy(args.calib_copy)
+
+    terms = obs.ntime * obs.nbl * obs.nchan * sky.nsrc
+    tp = obs.ntime * obs.nbl * obs.nchan * sky.npsrc
+    tg = obs.ntime * obs.nbl * obs.nchan * sky.ngsrc
+    # FP64 autotuning at the large array would take longer than the timing
+    tune_fp64 = args.config != "c4"
+
+    def run(mode, prec, steps, warmup):
+        D, W = (D64, W64) if prec == R.FP64 else (D32, W32)
+        chi2 = torch.empty(1, dtype=torch.float64, device="cuda")
+        grad = torch.empty((sky.nsrc, 10), dtype=torch.float64, device="cuda")
+        wsp = R.workspace(plan, mode, prec, 1, sky.nsrc)
+        if not args.no_autotune and (prec == R.MIXED or tune_fp64):
+            # untimed: the library's autotuner picks the kernel variant
+            R.rime_autotune(plan, dsky, mode, prec, D, W, wsp)
+        variant = R.rime_variant_info(mode, prec, plan.get_variant(mode, prec))
+
+        def call():
+            if mode == R.MODE_CHI2_GRAD:
+                R.rime_chi2_grad(plan, dsky, prec, D, W, chi2, grad, wsp)
+            else:
+                R.rime_chi2(plan, dsky, prec, D, W, chi2, wsp)
+
+        ms, kms = timed(call, steps, warmup, plan.set_timing_events)
+        return {"ms_per_step": ms, "kernel_ms": kms, "chi2": chi2.item(), "variant": variant,
+                "terms_per_s": terms / (ms * 1e-3), "evals_per_s": 1e3 / ms}
+
+    out = {}
+    modes = [m for m in args.modes.split(",") if m]
+    if args.no_fp64:
+        modes = [m for m in modes if not m.endswith("fp64")]
+    fp_steps = max(2, args.steps // 2)
+    spec = {"grad_mixed": (R.MODE_CHI2_GRAD, R.MIXED, args.steps, args.warmup),
+            "grad_fp64": (R.MODE_CHI2_GRAD, R.FP64, fp_steps, 1),
+            "chi2_mixed": (R.MODE_CHI2, R.MIXED, args.steps, 1),
+            "chi2_fp64": (R.MODE_CHI2, R.FP64, fp_steps, 1)}
+    for m in modes:
+        log("timing", m)
+        out[m] = run(*spec[m])
+        log(m, out[m])
+
+    g = out["grad_mixed"]
+    traffic = measured_traffic(args.traffic, list(g["variant"]), args.config)
+    rec = base_record(
+        args, "source x visibility terms/s (chi2+grad, FP32-mixed), 1 GPU", g["terms_per_s"],
+        g["ms_per_step"], "f32",
+        f"{args.config}: RIME chi2+grad, {obs.na} antennas ({obs.nbl} baselines), "
+        f"{obs.ntime} timesteps, {obs.nchan} channels, {sky.npsrc} point + {sky.ngsrc} "
+        f"Gaussian sources, beam",
+        {"terms_per_eval": terms, "precision": "mixed (FP64 phase and sums)"})
+    rec["evals_per_s"] = g["evals_per_s"]
+    rec["roofline"] = roofline(alg_flops(tp, tg), g["kernel_ms"], g["variant"], traffic)
+    if "grad_fp64" in out:
+        rec["fp64"] = {"terms_per_s": out["grad_fp64"]["terms_per_s"],
+                       "ms_per_step": out["grad_fp64"]["ms_per_step"],
+                       "evals_per_s": out["grad_fp64"]["evals_per_s"],
+                       "variant": out["grad_fp64"]["variant"]}
+        rec["speedup_mixed_vs_fp64"] = out["grad_fp64"]["ms_per_step"] / g["ms_per_step"]
+    if "chi2_mixed" in out and "chi2_fp64" in out:
+        rec["chi2_only"] = {
+            "mixed_terms_per_s": out["chi2_mixed"]["terms_per_s"],
+            "fp64_terms_per_s": out["chi2_fp64"]["terms_per_s"],
+            "mixed_ms": out["chi2_mixed"]["ms_per_step"],
+            "fp64_ms": out["chi2_fp64"]["ms_per_step"]}
+    plan.close()
+    if not args.no_cpu_baseline:
+        log("cpu baseline")
+        rec["cpu_baseline"] = cpu_baseline(problem_sample(name))
+    return rec
+
+
+# --------------------------------------------------------------------------- #
+# c3: batched proposals
+# --------------------------------------------------------------------------- #
+
+def bench_batch(args):
+    import torch
+
+    import paper_1501_07719_amd as R
+    from rime_synth import make_batch_problem
+
+    t_gen = time.perf_counter()
+    pb = make_batch_problem()
+    obs = pb.obs
+    nset = len(pb.skies)
+    nsrc = np.array([s.nsrc for s in pb.skies])
+    npsrc = np.array([s.npsrc for s in pb.skies])
+    log(f"generated c3: {nset} sets, {nsrc.sum()} sources (mean {nsrc.mean():.0f}) in "
+        f"{time.perf_counter() - t_gen:.1f}s")
+    plan = R.Plan(obs)
+    D64, W64, D32, W32 = upload_data(R, plan, pb.truth, pb.noise, pb.weight)
+    skies = [R.DeviceSky.from_host(s) for s in pb.skies]
+    batch = R.Batch(plan, skies)
+    per_vis = obs.ntime * obs.nbl * obs.nchan
+    terms = per_vis * int(nsrc.sum())
+    tp = per_vis * int(npsrc.sum())
+    tg = terms - tp
+    chi2 = torch.empty(nset, dtype=torch.float64, device="cuda")
+    grad = torch.empty((batch.total_src, 10), dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def batched(prec, graph):
+        D, W = (D64, W64) if prec == R.FP64 else (D32, W32)
+        ws = torch.empty(batch.workspace_size(R.MODE_CHI2_GRAD, prec), dtype=torch.uint8,
+                         device="cuda")
+
+        def call():
+            R.rime_chi2_batched(batch, prec, D, W, chi2, grad, ws, stream=stream,
+                                use_graph=graph)
+        return call, ws
+
+    res = {}
+    # default variant, one graph launch for all sets
+    v_default = R.rime_batch_get_variant(batch, R.MODE_CHI2_GRAD, R.MIXED)
+    call, ws = batched(R.MIXED, True)
+    res["graph_default"] = timed(call, args.steps, 1)[0]
+    log("graph default", R.rime_variant_info(R.MODE_CHI2_GRAD, R.MIXED, v_default),
+        res["graph_default"])
+    if not args.no_autotune:
+        R.rime_batch_autotune(batch, R.MODE_CHI2_GRAD, R.MIXED, D32, W32, ws)
+    v_tuned = R.rime_batch_get_variant(batch, R.MODE_CHI2_GRAD, R.MIXED)
+    variant = R.rime_variant_info(R.MODE_CHI2_GRAD, R.MIXED, v_tuned)
+    call, ws = batched(R.MIXED, True)
+    res["graph_tuned"] = timed(call, args.steps, 1)[0]
+    log("graph tuned", variant, res["graph_tuned"])
+    # the same launches without the graph, with the main kernel timed alone
+    call, ws = batched(R.MIXED, False)
+    res["stream_tuned"], kms = timed(call, args.steps, 1, plan.set_timing_events)
+    log("stream tuned", res["stream_tuned"], "kernel", kms)
+    del ws, call
+    # per-set loop: one rime_chi2_grad call per proposal, same variant
+    plan.set_variant(R.MODE_CHI2_GRAD, R.MIXED, v_tuned)
+    wsl = R.workspace(plan, R.MODE_CHI2_GRAD, R.MIXED, 1, int(nsrc.max()))
+    offs = np.concatenate([[0], np.cumsum(nsrc)[:-1]])
+    grads = [grad[int(o):int(o) + int(n)] for o, n in zip(offs, nsrc)]
+
+    def loop():
+        for i in range(nset):
+            R.rime_chi2_grad(plan, skies[i], R.MIXED, D32, W32, chi2[i:i + 1], grads[i], wsl)
+    res["loop_tuned"] = timed(loop, args.steps, 1)[0]
+    log("per-set loop", res["loop_tuned"])
+    del wsl
+    if not args.no_fp64:
+        call, ws = batched(R.FP64, True)
+        res["graph_fp64"] = timed(call, max(1, args.steps // 2), 1)[0]
+        log("graph fp64", res["graph_fp64"])
+        del ws, call
+
+    ms = res["graph_tuned"]
+    rec = base_record(
+        args, "source x visibility terms/s (chi2+grad, FP32-mixed), 1 GPU", terms / (ms * 1e-3),
+        ms, "f32",
+        f"c3: {nset} batched proposals of {nsrc.min()}..{nsrc.max()} sources "
+        f"(sum {nsrc.sum()}, 30 % Gaussian) over {obs.na} antennas ({obs.nbl} baselines), "
+        f"{obs.ntime} timesteps, {obs.nchan} channels, beam; one hipGraph launch",
+        {"terms_per_eval": terms, "sets": nset, "precision": "mixed (FP64 phase and sums)"})
+    rec["evals_per_s"] = nset * 1e3 / ms
+    rec["roofline"] = roofline(alg_flops(tp, tg), kms, variant, None)
+    rec["batched"] = {
+        "graph_tuned_ms": ms, "graph_default_ms": res["graph_default"],
+        "stream_tuned_ms": res["stream_tuned"], "per_set_loop_ms": res["loop_tuned"],
+        "default_variant": R.rime_variant_info(R.MODE_CHI2_GRAD, R.MIXED, v_default),
+        "tuned_variant": variant,
+        "speedup_graph_vs_loop": res["loop_tuned"] / ms,
+        "speedup_tuned_vs_default": res["graph_default"] / ms}
+    if "graph_fp64" in res:
+        rec["fp64"] = {"ms_per_step": res["graph_fp64"],
+                       "terms_per_s": terms / (res["graph_fp64"] * 1e-3),
+                       "evals_per_s": nset * 1e3 / res["graph_fp64"]}
+        rec["speedup_mixed_vs_fp64"] = res["graph_fp64"] / ms
+    batch.close()
+    plan.close()
+    if not args.no_cpu_baseline:
+        log("cpu baseline")
+        mid = int(np.argsort(nsrc)[nset // 2])
+        rec["cpu_baseline"] = cpu_baseline(batch_sample(pb, mid))
+    return rec
+
+
+# --------------------------------------------------------------------------- #
+# c0: latency of one small FP64 evaluation
+# --------------------------------------------------------------------------- #
+
+def bench_latency(args):
+    import torch
+
+    import paper_1501_07719_amd as R
+    from rime_synth import make_problem
+
+    pr = make_problem("c0")
+    obs, sky = pr.obs, pr.sky
+    plan = R.Plan(obs)
+    D64, W64, _, _ = upload_data(R, plan, pr.truth, pr.noise, pr.weight)
+    dsky = R.DeviceSky.from_host(sky)
+    batch = R.Batch(plan, [dsky])
+    chi2 = torch.empty(1, dtype=torch.float64, device="cuda")
+    grad = torch.empty((sky.nsrc, 10), dtype=torch.float64, device="cuda")
+    ws = torch.empty(batch.workspace_size(R.MODE_CHI2_GRAD, R.FP64), dtype=torch.uint8,
+                     device="cuda")
+    stream = torch.cuda.current_stream()
+    terms = obs.ntime * obs.nbl * obs.nchan * sky.nsrc
+
+    def graph_call():
+        R.rime_chi2_batched(batch, R.FP64, D64, W64, chi2, grad, ws, stream=stream,
+                            use_graph=True)
+
+    def plain_call():
+        R.rime_chi2_grad(plan, dsky, R.FP64, D64, W64, chi2, grad, ws)
+
+    ms_graph, _ = timed(graph_call, args.steps, args.warmup)
+    ms_plain, kms = timed(plain_call, args.steps, args.warmup, plan.set_timing_events)
+    variant = R.rime_variant_info(R.MODE_CHI2_GRAD, R.FP64,
+                                  plan.get_variant(R.MODE_CHI2_GRAD, R.FP64))
+    rec = base_record(
+        args, "source x visibility terms/s (chi2+grad, FP64), 1 GPU", terms / (ms_graph * 1e-3),
+        ms_graph, "f64",
+        f"c0: RIME chi2+grad, {obs.na} antennas ({obs.nbl} baselines), {obs.ntime} timesteps, "
+        f"{obs.nchan} channels, {sky.npsrc} point sources, no beam; one hipGraph launch",
+        {"terms_per_eval": terms, "precision": "fp64"})
+    rec["evals_per_s"] = 1e3 / ms_graph
+    rec["latency_us"] = {"graph": ms_graph * 1e3, "stream": ms_plain * 1e3,
+                         "main_kernel": kms * 1e3}
+    flops = alg_flops(terms, 0)
+    achieved = flops / (kms * 1e-3) / 1e12
+    rec["roofline"] = {"bound": "latency", "achieved": achieved, "peak": PEAK_TFLOPS["f64"],
+                       "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS["f64"],
+                       "traffic": None,
+                       "kernel": "rime_main<double, %d, %d, %d, chi2+grad>" % tuple(variant),
+                       "kernel_ms": kms, "flops_per_launch": flops}
+    batch.close()
+    plan.close()
+    if not args.no_cpu_baseline:
+        import oracle.rime_oracle as O
+        D = O.model_vis(obs, pr.truth) + pr.noise
+        n = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < 10.0:
+            O.chi2_and_grad(obs, sky, D, pr.weight)
+            n += 1
+        dt = (time.perf_counter() - t0) / n
+        rec["cpu_baseline"] = {"value": terms / dt, "unit": "terms/s",
+                               "cores": torch.get_num_threads(), "kind": "oracle",
+                               "sample": f"the whole c0 workload, {n} evaluations, "
+                                         f"{dt * 1e3:.1f} ms each"}
+    return rec
 
 
 def main():
@@ -127,139 +518,16 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     import torch
-
-    import paper_1501_07719_amd as R
-    from rime_synth import make_problem
-
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    name = "c1" if args.config == "c2" else args.config
-    t_gen = time.perf_counter()
-    pr = make_problem(name)
-    obs, sky, truth = pr.obs, pr.sky, pr.truth
-    log(f"generated {name}: na={obs.na} nbl={obs.nbl} ntime={obs.ntime} nchan={obs.nchan} "
-        f"nsrc={sky.nsrc} in {time.perf_counter() - t_gen:.1f}s")
-    plan = R.Plan(obs)
-    shp = (obs.ntime, obs.nbl, obs.nchan, 4)
-    # observed data: FP64 model at the truth parameters (GPU predict) + noise
-    vis = torch.empty(shp, dtype=torch.complex128, device="cuda")
-    ws = R.workspace(plan, R.MODE_PREDICT, R.FP64, 1, truth.nsrc)
-    R.rime_predict(plan, R.DeviceSky.from_host(truth), R.FP64, vis, ws)
-    D64 = vis + torch.as_tensor(pr.noise, device="cuda")
-    del vis, ws
-    W64 = torch.as_tensor(pr.weight, device="cuda")
-    D32, W32 = D64.to(torch.complex64), W64.to(torch.float32)
-    dsky = R.DeviceSky.from_host(sky)
-    torch.cuda.synchronize()
-    if args.calib_copy:
-        # a plain device copy of known size: args.calib_copy MiB read + written
-        a = torch.ones(args.calib_copy * (1 << 20) // 4, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
-
-    terms = obs.ntime * obs.nbl * obs.nchan * sky.nsrc
-    tp = obs.ntime * obs.nbl * obs.nchan * sky.npsrc
-    tg = obs.ntime * obs.nbl * obs.nchan * sky.ngsrc
-
-    tuned = {}
-
-    def run(mode, prec, steps, warmup):
-        D, W = (D64, W64) if prec == R.FP64 else (D32, W32)
-        chi2 = torch.empty(1, dtype=torch.float64, device="cuda")
-        grad = torch.empty((sky.nsrc, 10), dtype=torch.float64, device="cuda")
-        wsp = R.workspace(plan, mode, prec, 1, sky.nsrc)
-        if not args.no_autotune:
-            # untimed: the library's autotuner picks the kernel variant
-            R.rime_autotune(plan, dsky, mode, prec, D, W, wsp)
-        tuned[(mode, prec)] = R.rime_variant_info(mode, prec, plan.get_variant(mode, prec))
-
-        def call():
-            if mode == R.MODE_CHI2_GRAD:
-                R.rime_chi2_grad(plan, dsky, prec, D, W, chi2, grad, wsp)
-            else:
-                R.rime_chi2(plan, dsky, prec, D, W, chi2, wsp)
-
-        for _ in range(warmup):
-            call()
-        torch.cuda.synchronize()
-        ks = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
-        ke = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
-        for e in ks + ke:
-            e.record()
-        torch.cuda.synchronize()
-        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        start.record()
-        for i in range(steps):
-            plan.set_timing_events(ks[i], ke[i])
-            call()
-        stop.record()
-        torch.cuda.synchronize()
-        plan.set_timing_events(None, None)
-        ms = start.elapsed_time(stop) / steps
-        kms = float(np.mean([ks[i].elapsed_time(ke[i]) for i in range(steps)]))
-        return {"ms_per_step": ms, "kernel_ms": kms, "chi2": chi2.item(),
-                "variant": tuned[(mode, prec)],
-                "terms_per_s": terms / (ms * 1e-3), "evals_per_s": 1e3 / ms}
-
-    out = {}
-    modes = [m for m in args.modes.split(",") if m]
-    if args.no_fp64:
-        modes = [m for m in modes if not m.endswith("fp64")]
-    spec = {"grad_mixed": (R.MODE_CHI2_GRAD, R.MIXED, args.steps, args.warmup),
-            "grad_fp64": (R.MODE_CHI2_GRAD, R.FP64, max(2, args.steps // 2), 1),
-            "chi2_mixed": (R.MODE_CHI2, R.MIXED, args.steps, 1),
-            "chi2_fp64": (R.MODE_CHI2, R.FP64, max(2, args.steps // 2), 1)}
-    for m in modes:
-        log("timing", m)
-        out[m] = run(*spec[m])
-        log(m, out[m])
-
-    g = out["grad_mixed"]
-    flops = tp * (FLOPS_FWD["p"] + FLOPS_ADJ["p"]) + tg * (FLOPS_FWD["g"] + FLOPS_ADJ["g"])
-    achieved = flops / (g["kernel_ms"] * 1e-3) / 1e12
-    traffic = measured_traffic(args.traffic, list(g["variant"]))
-    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS["f32"],
-                "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS["f32"], "traffic": traffic,
-                "kernel": "rime_main<float, %d, %d, %d, chi2+grad>" % tuple(g["variant"]),
-                "kernel_ms": g["kernel_ms"],
-                "flops_per_launch": flops}
-    rec = {
-        "metric": "source x visibility terms/s (chi2+grad, FP32-mixed), 1 GPU",
-        "value": g["terms_per_s"],
-        "unit": "terms/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": g["ms_per_step"],
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": f"{args.config}: RIME chi2+grad, {obs.na} antennas ({obs.nbl} "
-                               f"baselines), {obs.ntime} timesteps, {obs.nchan} channels, "
-                               f"{sky.npsrc} point + {sky.ngsrc} Gaussian sources, beam",
-                   "terms_per_eval": terms, "precision": "mixed (FP64 phase and sums)"},
-        "evals_per_s": g["evals_per_s"],
-        "roofline": roofline,
-    }
-    if "grad_fp64" in out:
-        rec["fp64"] = {"terms_per_s": out["grad_fp64"]["terms_per_s"],
-                       "ms_per_step": out["grad_fp64"]["ms_per_step"],
-                       "evals_per_s": out["grad_fp64"]["evals_per_s"]}
-        rec["speedup_mixed_vs_fp64"] = out["grad_fp64"]["ms_per_step"] / g["ms_per_step"]
-    if "chi2_mixed" in out and "chi2_fp64" in out:
-        rec["chi2_only"] = {
-            "mixed_terms_per_s": out["chi2_mixed"]["terms_per_s"],
-            "fp64_terms_per_s": out["chi2_fp64"]["terms_per_s"],
-            "mixed_ms": out["chi2_mixed"]["ms_per_step"],
-            "fp64_ms": out["chi2_fp64"]["ms_per_step"]}
-    if not args.no_cpu_baseline:
-        log("cpu baseline")
-        rec["cpu_baseline"] = cpu_baseline(name)
-    plan.close()
+    # all work on one non-default stream (default priority): hipGraph capture
+    # needs a stream other than the null stream
+    with torch.cuda.stream(torch.cuda.Stream()):
+        if args.config == "c3":
+            rec = bench_batch(args)
+        elif args.config == "c0":
+            rec = bench_latency(args)
+        else:
+            rec = bench_single(args)
     print(json.dumps(rec))
 
 

@@ -157,6 +157,19 @@ rime_status rime_chi2_batched(rime_batch *batch, rime_precision prec, const void
 size_t rime_batch_workspace_size(const rime_batch *batch, rime_mode mode,
                                  rime_precision prec);
 
+/* Variant choice of a batch (mode RIME_MODE_CHI2 or RIME_MODE_CHI2_GRAD):
+ * until rime_batch_autotune or rime_batch_set_variant sets one, a batch uses
+ * its plan's variant.  rime_batch_autotune times every compiled variant on
+ * the batch itself (one untimed and one timed rime_chi2_batched call each,
+ * on a private stream; ws as for rime_chi2_batched) and keeps the fastest.
+ * Synchronous.  rime_batch_get_variant returns the index in use. */
+rime_status rime_batch_autotune(rime_batch *batch, rime_mode mode, rime_precision prec,
+                                const void *data, const void *weight, void *ws,
+                                size_t ws_bytes);
+rime_status rime_batch_set_variant(rime_batch *batch, rime_mode mode, rime_precision prec,
+                                   int32_t index);
+int32_t rime_batch_get_variant(const rime_batch *batch, rime_mode mode, rime_precision prec);
+
 /* Sum over all weights of ln(2 pi / w): the constant of eq. lhood, so that
  * -2 ln L = chi^2 + rime_loglike_const.  HOST array, n entries. */
 double rime_loglike_const(const double *weight, size_t n);

@@ -5,7 +5,8 @@
 """
 from .rime import (  # noqa: F401
     FP64, MIXED, MODE_CHI2, MODE_CHI2_GRAD, MODE_PREDICT, Batch, DeviceSky, Plan, RimeError,
-    load_library, rime_autotune, rime_batch_create, rime_chi2, rime_chi2_batched,
+    load_library, rime_autotune, rime_batch_autotune, rime_batch_create, rime_batch_get_variant,
+    rime_batch_set_variant, rime_chi2, rime_chi2_batched,
     rime_chi2_grad, rime_loglike_const, rime_predict, rime_tiling_host, rime_variant_count,
     rime_variant_info, rime_workspace_size, workspace,
 )

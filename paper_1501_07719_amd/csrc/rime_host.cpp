@@ -106,6 +106,7 @@ struct rime_batch {
   GraphKey key{};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  int32_t variant[3][2] = {{-1, -1}, {-1, -1}, {-1, -1}};  // -1: the plan's
 };
 
 namespace {
@@ -699,7 +700,7 @@ rime_status rime_chi2_batched(rime_batch *b, rime_precision prec, const void *da
   if (prec != RIME_FP64 && prec != RIME_MIXED) return RIME_ERR_ARG;
   const int mode = grad ? RIME_MODE_CHI2_GRAD : RIME_MODE_CHI2;
   const rime_plan *plan = b->plan;
-  const int vidx = plan->variant[mode][prec];
+  const int vidx = b->variant[mode][prec] >= 0 ? b->variant[mode][prec] : plan->variant[mode][prec];
   const Variant *v = variant_info(mode, prec, vidx);
   if (!v) return RIME_ERR_UNSUPPORTED;
   const WsLayout L = ws_layout(plan, mode, prec, geometry(plan, *v, b->nset), b->nset, b->total_src);
@@ -739,6 +740,70 @@ rime_status rime_chi2_batched(rime_batch *b, rime_precision prec, const void *da
   }
   RIME_HIP(hipGraphLaunch(b->exec, s));
   return RIME_OK;
+}
+
+rime_status rime_batch_set_variant(rime_batch *b, rime_mode mode, rime_precision prec,
+                                   int32_t index) {
+  if (!b || (mode != RIME_MODE_CHI2 && mode != RIME_MODE_CHI2_GRAD) ||
+      (prec != RIME_FP64 && prec != RIME_MIXED) || !variant_info(mode, prec, index))
+    return RIME_ERR_ARG;
+  b->variant[mode][prec] = index;
+  return RIME_OK;
+}
+
+int32_t rime_batch_get_variant(const rime_batch *b, rime_mode mode, rime_precision prec) {
+  if (!b || mode < 0 || mode > 2 || prec < 0 || prec > 1) return -1;
+  return b->variant[mode][prec] >= 0 ? b->variant[mode][prec] : b->plan->variant[mode][prec];
+}
+
+rime_status rime_batch_autotune(rime_batch *b, rime_mode mode, rime_precision prec,
+                                const void *data, const void *weight, void *ws,
+                                size_t ws_bytes) {
+  if (!b || !data || !weight || (mode != RIME_MODE_CHI2 && mode != RIME_MODE_CHI2_GRAD) ||
+      (prec != RIME_FP64 && prec != RIME_MIXED))
+    return RIME_ERR_ARG;
+  double *chi2 = nullptr, *grad = nullptr;
+  hipStream_t s = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto cleanup = [&]() {
+    if (s) (void)hipStreamSynchronize(s);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (s) (void)hipStreamDestroy(s);
+    (void)hipFree(chi2);
+    (void)hipFree(grad);
+  };
+  hipError_t e = hipMalloc(reinterpret_cast<void **>(&chi2), sizeof(double) * b->nset);
+  if (e == hipSuccess && mode == RIME_MODE_CHI2_GRAD)
+    e = hipMalloc(reinterpret_cast<void **>(&grad), sizeof(double) * 10 * b->total_src);
+  if (e == hipSuccess) e = hipStreamCreate(&s);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    cleanup();
+    return e == hipErrorOutOfMemory ? RIME_ERR_NOMEM : hip_fail(e);
+  }
+  const int32_t saved = b->variant[mode][prec];
+  float best_ms = 1e30f;
+  int best = -1;
+  for (int i = 0; i < variant_count(mode, prec); ++i) {
+    b->variant[mode][prec] = i;
+    rime_status st = rime_chi2_batched(b, prec, data, weight, chi2, grad, ws, ws_bytes, s, 0);
+    if (st != RIME_OK) continue;
+    (void)hipEventRecord(e0, s);
+    st = rime_chi2_batched(b, prec, data, weight, chi2, grad, ws, ws_bytes, s, 0);
+    (void)hipEventRecord(e1, s);
+    if (hipEventSynchronize(e1) != hipSuccess || st != RIME_OK) continue;
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = i;
+    }
+  }
+  cleanup();
+  b->variant[mode][prec] = best >= 0 ? best : saved;
+  return best >= 0 ? RIME_OK : RIME_ERR_UNSUPPORTED;
 }
 
 rime_status rime_tiling_host(int32_t na, int32_t nbl, const int32_t *ant1, const int32_t *ant2,

@@ -85,6 +85,9 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "rime_batch_destroy": (None, [vp]),
         "rime_chi2_batched": (i32, [vp, i32, vp, vp, vp, vp, vp, sz, vp, i32]),
         "rime_batch_workspace_size": (sz, [vp, i32, i32]),
+        "rime_batch_autotune": (i32, [vp, i32, i32, vp, vp, vp, sz]),
+        "rime_batch_set_variant": (i32, [vp, i32, i32, i32]),
+        "rime_batch_get_variant": (i32, [vp, i32, i32]),
         "rime_loglike_const": (dbl, [ctypes.POINTER(ctypes.c_double), sz]),
         "rime_status_string": (ctypes.c_char_p, [i32]),
         "rime_last_hip_error": (i32, []),
@@ -190,7 +193,12 @@ class Plan:
         return int(self._lib.rime_get_variant(self.handle, mode, prec))
 
     def set_timing_events(self, start=None, stop=None):
-        """torch.cuda.Event pair recorded around the main kernel of later calls."""
+        """torch.cuda.Event pair recorded around the main kernel of later calls.
+        torch creates an event's hipEvent on its first record(), so each event
+        must have been recorded once before it is passed here."""
+        for ev in (start, stop):
+            if ev is not None and not ev.cuda_event:
+                raise ValueError("timing event has no hipEvent yet: record() it once first")
         s = ctypes.c_void_p(start.cuda_event) if start is not None else None
         e = ctypes.c_void_p(stop.cuda_event) if stop is not None else None
         _check(self._lib.rime_plan_set_timing_events(self.handle, s, e),
@@ -337,6 +345,25 @@ def rime_chi2_batched(batch: Batch, prec: int, data, weight, chi2, grad, ws, str
                                        _dptr(chi2), _dptr(grad), _dptr(ws), ws.numel(),
                                        _stream(stream), 1 if use_graph else 0),
            "rime_chi2_batched")
+
+
+def rime_batch_autotune(batch: Batch, mode: int, prec: int, data, weight, ws):
+    plan = batch.plan
+    cdt, rdt = _vis_dtypes(prec)
+    shp = (plan.ntime, plan.nbl, plan.nchan, 4)
+    _expect(data, cdt, shp)
+    _expect(weight, rdt, shp)
+    _check(plan._lib.rime_batch_autotune(batch.handle, mode, prec, _dptr(data), _dptr(weight),
+                                         _dptr(ws), ws.numel()), "rime_batch_autotune")
+
+
+def rime_batch_set_variant(batch: Batch, mode: int, prec: int, index: int):
+    _check(batch.plan._lib.rime_batch_set_variant(batch.handle, mode, prec, index),
+           "rime_batch_set_variant")
+
+
+def rime_batch_get_variant(batch: Batch, mode: int, prec: int) -> int:
+    return int(batch.plan._lib.rime_batch_get_variant(batch.handle, mode, prec))
 
 
 def rime_autotune(plan: Plan, sky: DeviceSky, mode: int, prec: int, data, weight, ws,

@@ -241,10 +241,13 @@ class Problem:
 
 def make_problem(name: str, *, ntime: int | None = None, nchan: int | None = None,
                  na: int | None = None, npsrc: int | None = None,
-                 ngsrc: int | None = None, key: int | None = None) -> Problem:
+                 ngsrc: int | None = None, key: int | None = None,
+                 dense: bool = True) -> Problem:
     """Build configuration ``name`` (c0 ... c4).  Optional overrides shrink it
     (the recipe and seeds are unchanged, so e.g. ``ntime`` gives a time prefix
-    of the same uvw track when only ntime changes)."""
+    of the same uvw track when only ntime changes).  With dense=False the
+    per-visibility noise and weight arrays are not drawn (None): for callers
+    that only need the observation and the skies of a large configuration."""
     cfg = dict(CONFIGS[name])
     for k, v in (("ntime", ntime), ("nchan", nchan), ("na", na), ("npsrc", npsrc),
                  ("ngsrc", ngsrc)):
@@ -256,6 +259,8 @@ def make_problem(name: str, *, ntime: int | None = None, nchan: int | None = Non
     obs = make_observation(cfg, r_uvw, r_inst)
     sky = make_sky(cfg["npsrc"], cfg["ngsrc"], r_sky)
     truth = perturb(sky, r_pert)
+    if not dense:
+        return Problem(name=name, obs=obs, sky=sky, truth=truth, noise=None, weight=None)
     nz = noise((obs.ntime, obs.nbl, obs.nchan, 4), r_noise)
     return Problem(name=name, obs=obs, sky=sky, truth=truth, noise=nz, weight=weights(obs))
 

@@ -191,6 +191,13 @@ int32_t rime_variant_count(rime_mode mode, rime_precision prec);
 rime_status rime_variant_info(rime_mode mode, rime_precision prec, int32_t index,
                               int32_t *threads, int32_t *chans_per_thread,
                               int32_t *srcs_per_tile);
+/* 1 when variant `index` of (mode, prec) forms the point-source sums of a
+ * single sky on the matrix cores (the antenna x antenna product of
+ * A diag(St'_k) A^H per timestep and channel, fp16 hi/lo-split operands,
+ * float32 accumulation within 32 sources, float64 across), 0 when every
+ * source goes through the per-baseline kernel, -1 for an invalid index.
+ * Batched calls always use the per-baseline kernel. */
+int32_t rime_variant_matrix_cores(rime_mode mode, rime_precision prec, int32_t index);
 rime_status rime_set_variant(rime_plan *plan, rime_mode mode, rime_precision prec,
                              int32_t index);
 int32_t rime_get_variant(const rime_plan *plan, rime_mode mode, rime_precision prec);

@@ -8,5 +8,5 @@ from .rime import (  # noqa: F401
     load_library, rime_autotune, rime_batch_autotune, rime_batch_create, rime_batch_get_variant,
     rime_batch_set_variant, rime_chi2, rime_chi2_batched,
     rime_chi2_grad, rime_loglike_const, rime_predict, rime_tiling_host, rime_variant_count,
-    rime_variant_info, rime_workspace_size, workspace,
+    rime_variant_info, rime_variant_matrix_cores, rime_workspace_size, workspace,
 )

@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "librime.so")
 
-SOURCES = ["rime_kernels.hip", "rime_host.cpp"]
+SOURCES = ["rime_kernels.hip", "rime_pme.hip", "rime_host.cpp"]
 ARCH = os.environ.get("RIME_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are disabled for all device code.

@@ -1,0 +1,130 @@
+// Device-side numeric helpers shared by the kernels of librime.so: the
+// precision traits of the two arithmetic paths (float64, and float32 with the
+// gfx950 hardware transcendentals), definition-order products for the phase
+// argument, and float64 compensated (two-sum) accumulation with wavefront and
+// workgroup reductions.
+#pragma once
+
+#include "rime_internal.h"
+
+namespace rime {
+
+// ---------------------------------------------------------------------------
+// Numeric helpers
+// ---------------------------------------------------------------------------
+
+constexpr double kInvTwoPi = 0.15915494309189533576888376337251436;
+constexpr double kLog2e = 1.44269504088896340735992468100189214;
+
+template <class R> struct Num;
+
+template <> struct Num<double> {
+  using R2 = double2;
+  using R4 = double4;
+  // sin and cos of 2 pi r for r in [-1/2, 1/2] turns.
+  __device__ static inline void sincos_turns(double r, double *s, double *c) {
+    sincospi(2.0 * r, s, c);
+  }
+  // sin and cos of x radians, |x| <= 1.1.
+  __device__ static inline void sincos_rad(double x, double *s, double *c) { sincos(x, s, c); }
+  // exp(y) for y <= 0; y2 = y log2(e) is used by the float version.
+  __device__ static inline double exp_neg(double y, double /*y2*/) { return exp(y); }
+  __device__ static inline double sqrt_(double x) { return sqrt(x); }
+  __device__ static inline double rcp(double x) { return 1.0 / x; }
+};
+
+template <> struct Num<float> {
+  using R2 = float2;
+  using R4 = float4;
+  // v_sin_f32 / v_cos_f32 take the angle in turns.
+  __device__ static inline void sincos_turns(double r, float *s, float *c) {
+    const float rf = static_cast<float>(r);
+    *s = __builtin_amdgcn_sinf(rf);
+    *c = __builtin_amdgcn_cosf(rf);
+  }
+  __device__ static inline void sincos_rad(float x, float *s, float *c) {
+    const float t = x * static_cast<float>(kInvTwoPi);
+    *s = __builtin_amdgcn_sinf(t);
+    *c = __builtin_amdgcn_cosf(t);
+  }
+  __device__ static inline float exp_neg(float /*y*/, float y2) {
+    return __builtin_amdgcn_exp2f(y2);
+  }
+  __device__ static inline float sqrt_(double x) {
+    return __builtin_amdgcn_sqrtf(static_cast<float>(x));
+  }
+  __device__ static inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+};
+
+// (a0 b0 + a1 b1) + a2 b2 with every product and sum rounded separately (no
+// fused multiply-add), i.e. in the order in which the definitions are written.
+// The phase argument is hundreds of turns, so the rounding of this sum is
+// visible in the phase; evaluating it in definition order keeps the FP64 path
+// rounding-compatible with a plain evaluation of the same formula.
+__device__ inline double dot3_rn(double a0, double b0, double a1, double b1, double a2,
+                                 double b2) {
+#pragma clang fp contract(off)
+  return (a0 * b0 + a1 * b1) + a2 * b2;
+}
+
+__device__ inline double sumsq_rn(double a, double b) {
+#pragma clang fp contract(off)
+  return a * a + b * b;
+}
+
+// Error-free sum: s + e == a + b exactly.
+__device__ inline void two_sum(double a, double b, double &s, double &e) {
+  s = a + b;
+  const double bp = s - a;
+  e = (a - (s - bp)) + (b - bp);
+}
+
+// Compensated float64 accumulator.
+struct Comp {
+  double s = 0.0, c = 0.0;
+  __device__ inline void add(double x) {
+    double e;
+    two_sum(s, x, s, e);
+    c += e;
+  }
+  __device__ inline void merge(double os, double oc) {
+    double e;
+    two_sum(s, os, s, e);
+    c += oc + e;
+  }
+};
+
+__device__ inline Comp wave_reduce(Comp v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    const double os = __shfl_xor(v.s, off, kWave);
+    const double oc = __shfl_xor(v.c, off, kWave);
+    v.merge(os, oc);
+  }
+  return v;
+}
+
+// Workgroup reduction of a compensated pair; the result is valid in thread 0.
+template <int NT>
+__device__ inline Comp block_reduce(Comp v, double2 *scratch) {
+  constexpr int NW = NT / kWave;
+  v = wave_reduce(v);
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  if (NW == 1) return v;
+  __syncthreads();
+  if (lane == 0) scratch[wave] = make_double2(v.s, v.c);
+  __syncthreads();
+  Comp r;
+  if (wave == 0) {
+    if (lane < NW) {
+      r.s = scratch[lane].x;
+      r.c = scratch[lane].y;
+    }
+    r = wave_reduce(r);
+  }
+  return r;
+}
+
+constexpr int nat_for(int nbt) { return nbt >= 1024 ? 64 : nbt >= 256 ? 32 : 16; }
+
+}  // namespace rime

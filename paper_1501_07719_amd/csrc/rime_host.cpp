@@ -18,6 +18,9 @@
 namespace rime {
 hipError_t launch_prep(const KParams &p, bool fp64, int max_nsrc, hipStream_t stream);
 hipError_t launch_finalize(const KParams &p, int mode, int max_nsrc, hipStream_t stream);
+hipError_t launch_pme(const KParams &p, hipStream_t stream);
+hipError_t launch_pme_adjoint(const KParams &p, hipStream_t stream);
+hipError_t launch_pme_finalize(const KParams &p, hipStream_t stream);
 int variant_count(int mode, int prec);
 const Variant *variant_info(int mode, int prec, int index);
 hipError_t launch_variant(int mode, int prec, int index, const KParams &p, int nitems,
@@ -76,6 +79,13 @@ struct rime_plan {
   double *d_clip_r2 = nullptr;
   double *d_pointing = nullptr, *d_gains = nullptr;
   TileSet tiles[3];
+  // antenna-block pairs of the matrix-core point-source engine
+  int32_t nap = 0, npair = 0, nblk = 0;
+  int2 *d_pair_blk = nullptr;
+  int32_t *d_bl_slot = nullptr;
+  int32_t *d_pair_of = nullptr;
+  uint32_t *d_pair_mask = nullptr;
+  bool pme_adj_ok = false;  // every antenna-pair slot holds at most one baseline
   int32_t variant[3][2] = {{0, 0}, {0, 0}, {0, 0}};
   std::string signature;  // observation part of the autotune key
   hipEvent_t ev_start = nullptr, ev_stop = nullptr;
@@ -266,11 +276,26 @@ Geometry geometry(const rime_plan *plan, const Variant &v, int nset) {
 }
 
 struct WsLayout {
-  size_t geo = 0, lon = 0, st = 0, chi2 = 0, grad = 0, grad2 = 0, total = 0;
+  size_t geo = 0, lon = 0, st = 0, chi2 = 0, grad = 0, grad2 = 0;
+  size_t ph_hi = 0, ph_lo = 0, spts = 0, rho_t = 0, pgrad = 0;
+  int32_t pme_tchunk = 0;  // timesteps per phase-plane pass (0: engine off)
+  bool pme_adj = false;    // point-source adjoint on the matrix cores
+  size_t total = 0;
 };
 
+// Upper bound on the two phase planes of one pass of the matrix-core engine.
+constexpr size_t kPmePlaneBytes = size_t(1) << 30;
+
+int pme_ncg(const rime_plan *plan) { return (plan->nchan + kPmeNCW - 1) / kPmeNCW; }
+int pme_nqr(const rime_plan *plan) { return (plan->nblk + kPmeNQ - 1) / kPmeNQ; }
+
+// Whether a call runs the point sources on the matrix cores.
+bool pme_active(const Variant &v, int prec, int nset) {
+  return v.pme && prec == RIME_MIXED && nset == 1;
+}
+
 WsLayout ws_layout(const rime_plan *plan, int mode, int prec, const Geometry &g, int nset,
-                   int64_t total_src) {
+                   int64_t total_src, const Variant &v) {
   WsLayout L;
   const size_t r4 = prec == RIME_FP64 ? 32 : 16;
   size_t off = 0;
@@ -289,6 +314,28 @@ WsLayout ws_layout(const rime_plan *plan, int mode, int prec, const Geometry &g,
   L.grad2 = off;
   if (mode == RIME_MODE_CHI2_GRAD)
     off += align_up(static_cast<size_t>(g.grad_nchunk) * total_src * 10 * sizeof(double2));
+  if (pme_active(v, prec, nset)) {
+    // phase planes for pme_tchunk timesteps (total_src bounds the point count)
+    const size_t per_t = static_cast<size_t>(plan->nchan) * total_src * plan->nap * 4;
+    L.pme_tchunk = static_cast<int32_t>(
+        std::max<size_t>(1, std::min<size_t>(plan->ntime, kPmePlaneBytes / (2 * per_t))));
+    L.ph_hi = off;
+    off += align_up(per_t * L.pme_tchunk);
+    L.ph_lo = off;
+    off += align_up(per_t * L.pme_tchunk);
+    L.spts = off;
+    off += align_up(static_cast<size_t>(plan->ntime) * plan->nchan * plan->npair * 4 *
+                    kPmeBlk * kPmeBlk * sizeof(double2));
+    if (mode == RIME_MODE_CHI2_GRAD && plan->pme_adj_ok) {
+      L.pme_adj = true;
+      L.rho_t = off;
+      off += align_up(static_cast<size_t>(plan->ntime) * plan->nchan * plan->npair * 4 *
+                      kPmeBlk * kPmeBlk * sizeof(float2));
+      L.pgrad = off;
+      off += align_up(static_cast<size_t>((total_src + kPmeSR - 1) / kPmeSR) * plan->ntime *
+                      pme_ncg(plan) * plan->nblk * pme_nqr(plan) * kPmeSR * 7 * sizeof(float));
+    }
+  }
   L.total = off;
   return L;
 }
@@ -297,7 +344,8 @@ size_t ws_max(const rime_plan *plan, int mode, int prec, int nset, int64_t total
   size_t best = 0;
   for (int i = 0; i < variant_count(mode, prec); ++i) {
     const Variant *v = variant_info(mode, prec, i);
-    best = std::max(best, ws_layout(plan, mode, prec, geometry(plan, *v, nset), nset, total_src).total);
+    best = std::max(best,
+                    ws_layout(plan, mode, prec, geometry(plan, *v, nset), nset, total_src, *v).total);
   }
   return best;
 }
@@ -341,7 +389,7 @@ rime_status enqueue(const rime_plan *plan, int mode, int prec, int vidx, int nse
   const Variant *v = variant_info(mode, prec, vidx);
   if (!v) return RIME_ERR_UNSUPPORTED;
   const Geometry g = geometry(plan, *v, nset);
-  const WsLayout L = ws_layout(plan, mode, prec, g, nset, total_src);
+  const WsLayout L = ws_layout(plan, mode, prec, g, nset, total_src, *v);
   if (L.total > 0 && (!ws || ws_bytes < L.total)) return RIME_ERR_WORKSPACE;
   const int64_t nitems = static_cast<int64_t>(nset) * g.items_per_set;
   if (nitems <= 0 || nitems > 0x7fffffff) return RIME_ERR_UNSUPPORTED;
@@ -377,11 +425,49 @@ rime_status enqueue(const rime_plan *plan, int mode, int prec, int vidx, int nse
   p.grad_nchunk = g.grad_nchunk;
   p.chi2_out = chi2;
   p.grad_out = grad;
+  p.pme = 0;
+  p.pme_adj = 0;
+  if (L.pme_tchunk > 0 && one.npsrc > 0) {
+    p.pme = 1;
+    p.nap = plan->nap;
+    p.npair = plan->npair;
+    p.pair_blk = plan->d_pair_blk;
+    p.bl_slot = plan->d_bl_slot;
+    p.ph_hi = reinterpret_cast<uint32_t *>(w + L.ph_hi);
+    p.ph_lo = reinterpret_cast<uint32_t *>(w + L.ph_lo);
+    p.spts = reinterpret_cast<double2 *>(w + L.spts);
+    if (L.pme_adj) {
+      p.pme_adj = 1;
+      p.nblk = plan->nblk;
+      p.pair_of = plan->d_pair_of;
+      p.pair_mask = plan->d_pair_mask;
+      p.rho_t = reinterpret_cast<float2 *>(w + L.rho_t);
+      p.pgrad = reinterpret_cast<float *>(w + L.pgrad);
+      p.pme_ncg = pme_ncg(plan);
+      p.pme_nqr = pme_nqr(plan);
+      p.pme_nsr = (one.npsrc + kPmeSR - 1) / kPmeSR;
+    }
+  }
   RIME_HIP(launch_prep(p, prec == RIME_FP64, max_nsrc, stream));
   if (plan->ev_start) RIME_HIP(hipEventRecord(plan->ev_start, stream));
+  if (p.pme) {
+    for (int t0 = 0; t0 < plan->ntime; t0 += L.pme_tchunk) {
+      p.pme_t0 = t0;
+      p.pme_nt = std::min(L.pme_tchunk, plan->ntime - t0);
+      RIME_HIP(launch_pme(p, stream));
+    }
+  }
   RIME_HIP(launch_variant(mode, prec, vidx, p, static_cast<int>(nitems), stream));
+  if (p.pme_adj) {
+    for (int t0 = 0; t0 < plan->ntime; t0 += L.pme_tchunk) {
+      p.pme_t0 = t0;
+      p.pme_nt = std::min(L.pme_tchunk, plan->ntime - t0);
+      RIME_HIP(launch_pme_adjoint(p, stream));
+    }
+  }
   if (plan->ev_stop) RIME_HIP(hipEventRecord(plan->ev_stop, stream));
   RIME_HIP(launch_finalize(p, mode, max_nsrc, stream));
+  if (p.pme_adj) RIME_HIP(launch_pme_finalize(p, stream));
   return RIME_OK;
 }
 
@@ -458,6 +544,53 @@ void write_cache(const char *path, const std::map<std::string, int> &m) {
   f << "}\n";
 }
 
+// Antenna blocks of kPmeBlk antennas and the block pairs (P <= Q) that hold
+// baselines, for the matrix-core engine.  A baseline (a1, a2) lives in pair
+// (min, max) of its blocks at row i (antenna of block P) and column j
+// (antenna of block Q); when a1 lies in the later block the tile holds the
+// sums of (a2, a1) and the baseline takes their conjugate.
+rime_status build_pairs(int na, int nbl, const std::vector<int32_t> &a1,
+                        const std::vector<int32_t> &a2, rime_plan *pl) {
+  const int nblk = (na + kPmeBlk - 1) / kPmeBlk;
+  pl->nap = nblk * kPmeBlk;
+  std::vector<int32_t> pair_id(static_cast<size_t>(nblk) * nblk, -1);
+  std::vector<int2> pairs;
+  std::vector<int32_t> slot(nbl);
+  for (int b = 0; b < nbl; ++b) {
+    int P = a1[b] / kPmeBlk, Q = a2[b] / kPmeBlk;
+    int i = a1[b] % kPmeBlk, j = a2[b] % kPmeBlk, cj = 0;
+    if (P > Q) {
+      std::swap(P, Q);
+      std::swap(i, j);
+      cj = 1;
+    }
+    int &id = pair_id[static_cast<size_t>(P) * nblk + Q];
+    if (id < 0) {
+      id = static_cast<int32_t>(pairs.size());
+      pairs.push_back(make_int2(P, Q));
+    }
+    slot[b] = (id << 11) | (i << 6) | (j << 1) | cj;
+  }
+  pl->npair = static_cast<int32_t>(pairs.size());
+  pl->nblk = nblk;
+  // slot occupancy: the adjoint needs every slot to hold at most one baseline
+  std::vector<uint32_t> mask(static_cast<size_t>(pl->npair) * kPmeBlk, 0u);
+  pl->pme_adj_ok = true;
+  for (int b = 0; b < nbl; ++b) {
+    const int id = slot[b] >> 11, i = (slot[b] >> 6) & 31, j = (slot[b] >> 1) & 31;
+    uint32_t &w = mask[static_cast<size_t>(id) * kPmeBlk + i];
+    if ((w >> j) & 1u) pl->pme_adj_ok = false;
+    w |= 1u << j;
+  }
+  hipError_t e;
+  if ((e = upload(&pl->d_pair_blk, pairs)) != hipSuccess ||
+      (e = upload(&pl->d_bl_slot, slot)) != hipSuccess ||
+      (e = upload(&pl->d_pair_of, pair_id)) != hipSuccess ||
+      (e = upload(&pl->d_pair_mask, mask)) != hipSuccess)
+    return e == hipErrorOutOfMemory ? RIME_ERR_NOMEM : hip_fail(e);
+  return RIME_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -505,6 +638,10 @@ void rime_plan_destroy(rime_plan *plan) {
   (void)hipFree(plan->d_clip_r2);
   (void)hipFree(plan->d_pointing);
   (void)hipFree(plan->d_gains);
+  (void)hipFree(plan->d_pair_blk);
+  (void)hipFree(plan->d_bl_slot);
+  (void)hipFree(plan->d_pair_of);
+  (void)hipFree(plan->d_pair_mask);
   for (auto &t : plan->tiles) {
     (void)hipFree(t.bl);
     (void)hipFree(t.lpq);
@@ -598,6 +735,7 @@ rime_status rime_plan_create(const rime_obs_desc *obs, rime_plan **out) {
   }
   for (int i = 0; i < 3 && st == RIME_OK; ++i)
     st = build_tiles(obs->na, obs->nbl, a1, a2, kNbt[i], pl->tiles[i]);
+  if (st == RIME_OK) st = build_pairs(obs->na, obs->nbl, a1, a2, pl);
   if (st != RIME_OK) {
     rime_plan_destroy(pl);
     return st;
@@ -703,7 +841,8 @@ rime_status rime_chi2_batched(rime_batch *b, rime_precision prec, const void *da
   const int vidx = b->variant[mode][prec] >= 0 ? b->variant[mode][prec] : plan->variant[mode][prec];
   const Variant *v = variant_info(mode, prec, vidx);
   if (!v) return RIME_ERR_UNSUPPORTED;
-  const WsLayout L = ws_layout(plan, mode, prec, geometry(plan, *v, b->nset), b->nset, b->total_src);
+  const WsLayout L =
+      ws_layout(plan, mode, prec, geometry(plan, *v, b->nset), b->nset, b->total_src, *v);
   if (!ws || ws_bytes < L.total) return RIME_ERR_WORKSPACE;
   hipStream_t s = static_cast<hipStream_t>(stream);
   SetDesc dummy;
@@ -830,6 +969,11 @@ rime_status rime_plan_set_timing_events(rime_plan *plan, void *start, void *stop
   plan->ev_start = static_cast<hipEvent_t>(start);
   plan->ev_stop = static_cast<hipEvent_t>(stop);
   return RIME_OK;
+}
+
+int32_t rime_variant_matrix_cores(rime_mode mode, rime_precision prec, int32_t index) {
+  const Variant *v = variant_info(mode, prec, index);
+  return v ? (v->pme ? 1 : 0) : -1;
 }
 
 int32_t rime_variant_count(rime_mode mode, rime_precision prec) {

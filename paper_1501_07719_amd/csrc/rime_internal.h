@@ -78,13 +78,43 @@ struct KParams {
   int32_t grad_nchunk;
   double *chi2_out;        // [nset]
   double *grad_out;        // [total_src][10]
+  // matrix-core point-source engine (single sky, float32-mixed): the source
+  // sums of the point sources are formed per (timestep, channel) as the
+  // antenna x antenna product A diag(St_k) A^H over 32 x 32 antenna tiles
+  int32_t pme;             // 1: the point sources come from `spts`
+  int32_t nap;             // antennas padded to a multiple of kPmeBlk
+  int32_t npair;           // antenna-block pairs (P <= Q) that hold baselines
+  const int2 *pair_blk;    // [npair] (P, Q)
+  const int32_t *bl_slot;  // [nbl] pair << 11 | i << 6 | j << 1 | conj
+  uint32_t *ph_hi;         // phase planes [pme_nt][nchan][npsrc][nap] half2 (re, im):
+  uint32_t *ph_lo;         //   a = hi + lo, a = e exp(-2 pi i tau nu / c)
+  int32_t pme_t0, pme_nt;  // timesteps held by the phase planes
+  double2 *spts;           // [ntime][nchan][npair][4][kPmeBlk][kPmeBlk] Stokes sums
+  // matrix-core adjoint of the point sources
+  int32_t pme_adj;         // 1: point-source gradient from the antenna-pair product
+  int32_t nblk;            // antenna blocks (nap / kPmeBlk)
+  const int32_t *pair_of;  // [nblk][nblk] pair index of (P, Q), P <= Q, or -1
+  const uint32_t *pair_mask;  // [npair][kPmeBlk] bit j of word i: slot (i, j) used
+  float2 *rho_t;           // [ntime][nchan][npair][4][kPmeBlk][kPmeBlk] residual in
+                           //   Stokes form (conjugated for baselines stored as (q, p))
+  float *pgrad;            // adjoint partials [nsr][ntime][ncg][nblk][nqr][kPmeSR][7]
+  int32_t pme_ncg, pme_nqr, pme_nsr;
 };
+
+// Antenna block of the matrix-core engine (rows and columns of one MFMA tile),
+// and the work split of its adjoint: antenna blocks per Q range, sources per
+// source range, channels per workgroup.
+constexpr int kPmeBlk = 32;
+constexpr int kPmeNQ = 2;
+constexpr int kPmeSR = 512;
+constexpr int kPmeNCW = 8;
 
 // Kernel variant descriptor.
 struct Variant {
   int32_t threads;         // baselines per work item (one per thread)
   int32_t nc;              // channels per thread
   int32_t ns;              // sources per tile
+  int32_t pme;             // 1: point-source sums on the matrix cores
 };
 
 }  // namespace rime

@@ -22,127 +22,10 @@
 // float64; the per-visibility source sums run in float32 within a source tile
 // and are folded into float64 after each tile; chi^2 and gradient sums are
 // float64.
-#include "rime_internal.h"
+#include "rime_device.h"
 
 namespace rime {
 
-// ---------------------------------------------------------------------------
-// Numeric helpers
-// ---------------------------------------------------------------------------
-
-constexpr double kInvTwoPi = 0.15915494309189533576888376337251436;
-constexpr double kLog2e = 1.44269504088896340735992468100189214;
-
-template <class R> struct Num;
-
-template <> struct Num<double> {
-  using R2 = double2;
-  using R4 = double4;
-  // sin and cos of 2 pi r for r in [-1/2, 1/2] turns.
-  __device__ static inline void sincos_turns(double r, double *s, double *c) {
-    sincospi(2.0 * r, s, c);
-  }
-  // sin and cos of x radians, |x| <= 1.1.
-  __device__ static inline void sincos_rad(double x, double *s, double *c) { sincos(x, s, c); }
-  // exp(y) for y <= 0; y2 = y log2(e) is used by the float version.
-  __device__ static inline double exp_neg(double y, double /*y2*/) { return exp(y); }
-  __device__ static inline double sqrt_(double x) { return sqrt(x); }
-  __device__ static inline double rcp(double x) { return 1.0 / x; }
-};
-
-template <> struct Num<float> {
-  using R2 = float2;
-  using R4 = float4;
-  // v_sin_f32 / v_cos_f32 take the angle in turns.
-  __device__ static inline void sincos_turns(double r, float *s, float *c) {
-    const float rf = static_cast<float>(r);
-    *s = __builtin_amdgcn_sinf(rf);
-    *c = __builtin_amdgcn_cosf(rf);
-  }
-  __device__ static inline void sincos_rad(float x, float *s, float *c) {
-    const float t = x * static_cast<float>(kInvTwoPi);
-    *s = __builtin_amdgcn_sinf(t);
-    *c = __builtin_amdgcn_cosf(t);
-  }
-  __device__ static inline float exp_neg(float /*y*/, float y2) {
-    return __builtin_amdgcn_exp2f(y2);
-  }
-  __device__ static inline float sqrt_(double x) {
-    return __builtin_amdgcn_sqrtf(static_cast<float>(x));
-  }
-  __device__ static inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-};
-
-// (a0 b0 + a1 b1) + a2 b2 with every product and sum rounded separately (no
-// fused multiply-add), i.e. in the order in which the definitions are written.
-// The phase argument is hundreds of turns, so the rounding of this sum is
-// visible in the phase; evaluating it in definition order keeps the FP64 path
-// rounding-compatible with a plain evaluation of the same formula.
-__device__ inline double dot3_rn(double a0, double b0, double a1, double b1, double a2,
-                                 double b2) {
-#pragma clang fp contract(off)
-  return (a0 * b0 + a1 * b1) + a2 * b2;
-}
-
-__device__ inline double sumsq_rn(double a, double b) {
-#pragma clang fp contract(off)
-  return a * a + b * b;
-}
-
-// Error-free sum: s + e == a + b exactly.
-__device__ inline void two_sum(double a, double b, double &s, double &e) {
-  s = a + b;
-  const double bp = s - a;
-  e = (a - (s - bp)) + (b - bp);
-}
-
-// Compensated float64 accumulator.
-struct Comp {
-  double s = 0.0, c = 0.0;
-  __device__ inline void add(double x) {
-    double e;
-    two_sum(s, x, s, e);
-    c += e;
-  }
-  __device__ inline void merge(double os, double oc) {
-    double e;
-    two_sum(s, os, s, e);
-    c += oc + e;
-  }
-};
-
-__device__ inline Comp wave_reduce(Comp v) {
-#pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) {
-    const double os = __shfl_xor(v.s, off, kWave);
-    const double oc = __shfl_xor(v.c, off, kWave);
-    v.merge(os, oc);
-  }
-  return v;
-}
-
-// Workgroup reduction of a compensated pair; the result is valid in thread 0.
-template <int NT>
-__device__ inline Comp block_reduce(Comp v, double2 *scratch) {
-  constexpr int NW = NT / kWave;
-  v = wave_reduce(v);
-  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-  if (NW == 1) return v;
-  __syncthreads();
-  if (lane == 0) scratch[wave] = make_double2(v.s, v.c);
-  __syncthreads();
-  Comp r;
-  if (wave == 0) {
-    if (lane < NW) {
-      r.s = scratch[lane].x;
-      r.c = scratch[lane].y;
-    }
-    r = wave_reduce(r);
-  }
-  return r;
-}
-
-constexpr int nat_for(int nbt) { return nbt >= 1024 ? 64 : nbt >= 256 ? 32 : 16; }
 
 // ---------------------------------------------------------------------------
 // Per-source preparation: (l, m, n - 1), (l/n, m/n) and the spectrally scaled
@@ -594,19 +477,32 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
             Zi[k] = Yi[k] * gg[k].x - Yr[k] * gg[k].y;
           }
           R2 *rho = s_rho + (tid * NC + c) * 4;
-          R2 v;
-          v.x = static_cast<R>(Zr[0] + Zr[3]);
-          v.y = static_cast<R>(-(Zi[0] + Zi[3]));
-          rho[0] = v;
-          v.x = static_cast<R>(Zr[0] - Zr[3]);
-          v.y = static_cast<R>(-(Zi[0] - Zi[3]));
-          rho[1] = v;
-          v.x = static_cast<R>(Zr[1] + Zr[2]);
-          v.y = static_cast<R>(-(Zi[1] + Zi[2]));
-          rho[2] = v;
-          v.x = static_cast<R>(Zi[1] - Zi[2]);
-          v.y = static_cast<R>(Zr[1] - Zr[2]);
-          rho[3] = v;
+          R2 v[4];
+          v[0].x = static_cast<R>(Zr[0] + Zr[3]);
+          v[0].y = static_cast<R>(-(Zi[0] + Zi[3]));
+          v[1].x = static_cast<R>(Zr[0] - Zr[3]);
+          v[1].y = static_cast<R>(-(Zi[0] - Zi[3]));
+          v[2].x = static_cast<R>(Zr[1] + Zr[2]);
+          v[2].y = static_cast<R>(-(Zi[1] + Zi[2]));
+          v[3].x = static_cast<R>(Zi[1] - Zi[2]);
+          v[3].y = static_cast<R>(Zr[1] - Zr[2]);
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) rho[kk] = v[kk];
+          if (sizeof(R) == 4 && p.pme_adj && ok) {
+            // the point-source adjoint on the matrix cores reads rho from its
+            // antenna-pair slot (conjugated when the slot holds (q, p))
+            const int slot = p.bl_slot[bl];
+            const int pair = slot >> 11, si = (slot >> 6) & 31, sj = (slot >> 1) & 31;
+            const float cj = (slot & 1) ? -1.0f : 1.0f;
+            float2 *rt = p.rho_t +
+                         (((static_cast<int64_t>(t) * p.nchan + c0 + c) * p.npair + pair) * 4) *
+                             (kPmeBlk * kPmeBlk) +
+                         si * kPmeBlk + sj;
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+              rt[kk * kPmeBlk * kPmeBlk] =
+                  make_float2(static_cast<float>(v[kk].x), cj * static_cast<float>(v[kk].y));
+          }
         }
       }
     };
@@ -619,7 +515,8 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
 #pragma unroll
         for (int k = 0; k < 8; ++k) acc[c][k] = 0.0;
 
-      for (int k = 0; k < nst; ++k) {
+      // with the matrix-core engine the point-source sums arrive from HBM
+      for (int k = p.pme ? npt : 0; k < nst; ++k) {
         const bool gauss = k >= npt;
         const int s0 = gauss ? sd.npsrc + (k - npt) * NS : k * NS;
         const int cnt = min(NS, (gauss ? nsrc : sd.npsrc) - s0);
@@ -646,6 +543,29 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
 
       // ---- epilogue ------------------------------------------------------------
       if (active) {
+        if (p.pme) {
+          // point-source Stokes sums of this baseline from the antenna-pair
+          // tiles; a baseline stored as (q, p) takes the conjugate
+          const int slot = p.bl_slot[bl];
+          const int pair = slot >> 11, si = (slot >> 6) & 31, sj = (slot >> 1) & 31;
+          const double cj = (slot & 1) ? -1.0 : 1.0;
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            if (c < ncv) {
+              const double2 *sp =
+                  p.spts +
+                  (((static_cast<int64_t>(t) * p.nchan + c0 + c) * p.npair + pair) * 4) *
+                      (kPmeBlk * kPmeBlk) +
+                  si * kPmeBlk + sj;
+#pragma unroll
+              for (int kk = 0; kk < 4; ++kk) {
+                const double2 v = sp[kk * kPmeBlk * kPmeBlk];
+                acc[c][2 * kk] += v.x;
+                acc[c][2 * kk + 1] += cj * v.y;
+              }
+            }
+          }
+        }
         double2 gg[4];
         gains(gg);
 #pragma unroll
@@ -678,7 +598,8 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
       // gradient partials: [set][item][nsrc][10], sets laid out by src_off
       double *gout = p.grad_part + sd.src_off * p.items_per_set * 10 +
                      static_cast<int64_t>(local_item) * nsrc * 10;
-      for (int k = 0; k < nst; ++k) {
+      // with the matrix-core adjoint the point sources are done elsewhere
+      for (int k = p.pme_adj ? npt : 0; k < nst; ++k) {
         const bool gauss = k >= npt;
         const int s0 = gauss ? sd.npsrc + (k - npt) * NS : k * NS;
         const int cnt = min(NS, (gauss ? nsrc : sd.npsrc) - s0);
@@ -862,33 +783,43 @@ struct VariantEntry {
   hipError_t (*fn)(const KParams &, int, hipStream_t);
 };
 
-#define RIME_V(R, NBT, NC, NS, M) \
-  { {NBT, NC, NS}, &launch_main<R, NBT, NC, NS, M> }
+#define RIME_V(R, NBT, NC, NS, M, PME) \
+  { {NBT, NC, NS, PME}, &launch_main<R, NBT, NC, NS, M> }
 
-constexpr int kNumVariants = 4;
+// Float64 variants 0..3; float32-mixed variants 0..3 plus 4..5 with the
+// point-source sums on the matrix cores (single sky only).
+constexpr int kMaxVariants = 6;
+constexpr int kVariantCount[2] = {4, 6};
 
-static const VariantEntry kVariants[3][2][kNumVariants] = {
+static const VariantEntry kVariants[3][2][kMaxVariants] = {
     // MODE_PREDICT
-    {{RIME_V(double, 64, 2, 32, MODE_PREDICT), RIME_V(double, 256, 2, 32, MODE_PREDICT),
-      RIME_V(double, 1024, 2, 32, MODE_PREDICT), RIME_V(double, 256, 4, 16, MODE_PREDICT)},
-     {RIME_V(float, 64, 2, 32, MODE_PREDICT), RIME_V(float, 256, 2, 32, MODE_PREDICT),
-      RIME_V(float, 1024, 2, 32, MODE_PREDICT), RIME_V(float, 256, 4, 16, MODE_PREDICT)}},
+    {{RIME_V(double, 64, 2, 32, MODE_PREDICT, 0), RIME_V(double, 256, 2, 32, MODE_PREDICT, 0),
+      RIME_V(double, 1024, 2, 32, MODE_PREDICT, 0), RIME_V(double, 256, 4, 16, MODE_PREDICT, 0)},
+     {RIME_V(float, 64, 2, 32, MODE_PREDICT, 0), RIME_V(float, 256, 2, 32, MODE_PREDICT, 0),
+      RIME_V(float, 1024, 2, 32, MODE_PREDICT, 0), RIME_V(float, 256, 4, 16, MODE_PREDICT, 0),
+      RIME_V(float, 1024, 2, 32, MODE_PREDICT, 1), RIME_V(float, 256, 2, 32, MODE_PREDICT, 1)}},
     // MODE_CHI2
-    {{RIME_V(double, 64, 2, 32, MODE_CHI2), RIME_V(double, 256, 2, 32, MODE_CHI2),
-      RIME_V(double, 1024, 2, 32, MODE_CHI2), RIME_V(double, 256, 4, 16, MODE_CHI2)},
-     {RIME_V(float, 64, 2, 32, MODE_CHI2), RIME_V(float, 256, 2, 32, MODE_CHI2),
-      RIME_V(float, 1024, 2, 32, MODE_CHI2), RIME_V(float, 256, 4, 16, MODE_CHI2)}},
+    {{RIME_V(double, 64, 2, 32, MODE_CHI2, 0), RIME_V(double, 256, 2, 32, MODE_CHI2, 0),
+      RIME_V(double, 1024, 2, 32, MODE_CHI2, 0), RIME_V(double, 256, 4, 16, MODE_CHI2, 0)},
+     {RIME_V(float, 64, 2, 32, MODE_CHI2, 0), RIME_V(float, 256, 2, 32, MODE_CHI2, 0),
+      RIME_V(float, 1024, 2, 32, MODE_CHI2, 0), RIME_V(float, 256, 4, 16, MODE_CHI2, 0),
+      RIME_V(float, 1024, 2, 32, MODE_CHI2, 1), RIME_V(float, 256, 2, 32, MODE_CHI2, 1)}},
     // MODE_GRAD
-    {{RIME_V(double, 64, 2, 32, MODE_GRAD), RIME_V(double, 256, 2, 32, MODE_GRAD),
-      RIME_V(double, 256, 4, 16, MODE_GRAD), RIME_V(double, 64, 4, 16, MODE_GRAD)},
-     {RIME_V(float, 64, 2, 32, MODE_GRAD), RIME_V(float, 256, 2, 32, MODE_GRAD),
-      RIME_V(float, 1024, 2, 32, MODE_GRAD), RIME_V(float, 256, 4, 16, MODE_GRAD)}},
+    {{RIME_V(double, 64, 2, 32, MODE_GRAD, 0), RIME_V(double, 256, 2, 32, MODE_GRAD, 0),
+      RIME_V(double, 256, 4, 16, MODE_GRAD, 0), RIME_V(double, 64, 4, 16, MODE_GRAD, 0)},
+     {RIME_V(float, 64, 2, 32, MODE_GRAD, 0), RIME_V(float, 256, 2, 32, MODE_GRAD, 0),
+      RIME_V(float, 1024, 2, 32, MODE_GRAD, 0), RIME_V(float, 256, 4, 16, MODE_GRAD, 0),
+      RIME_V(float, 1024, 2, 32, MODE_GRAD, 1), RIME_V(float, 256, 2, 32, MODE_GRAD, 1)}},
 };
 
-int variant_count(int /*mode*/, int /*prec*/) { return kNumVariants; }
+int variant_count(int mode, int prec) {
+  if (mode < 0 || mode > 2 || prec < 0 || prec > 1) return 0;
+  return kVariantCount[prec];
+}
 
 const Variant *variant_info(int mode, int prec, int index) {
-  if (mode < 0 || mode > 2 || prec < 0 || prec > 1 || index < 0 || index >= kNumVariants)
+  if (mode < 0 || mode > 2 || prec < 0 || prec > 1 || index < 0 ||
+      index >= kVariantCount[prec])
     return nullptr;
   return &kVariants[mode][prec][index].v;
 }

@@ -94,6 +94,7 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "rime_autotune": (i32, [vp, ctypes.POINTER(SkyDesc), i32, i32, vp, vp, vp, sz,
                                 ctypes.c_char_p]),
         "rime_variant_count": (i32, [i32, i32]),
+        "rime_variant_matrix_cores": (i32, [i32, i32, i32]),
         "rime_variant_info": (i32, [i32, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                     ctypes.POINTER(i32)]),
         "rime_set_variant": (i32, [vp, i32, i32, i32]),
@@ -345,6 +346,14 @@ def rime_chi2_batched(batch: Batch, prec: int, data, weight, chi2, grad, ws, str
                                        _dptr(chi2), _dptr(grad), _dptr(ws), ws.numel(),
                                        _stream(stream), 1 if use_graph else 0),
            "rime_chi2_batched")
+
+
+def rime_variant_matrix_cores(mode: int, prec: int, index: int) -> bool:
+    """Whether the variant forms the point-source sums on the matrix cores."""
+    r = int(load_library().rime_variant_matrix_cores(mode, prec, index))
+    if r < 0:
+        raise RimeError(f"no variant {index} for mode {mode}, precision {prec}")
+    return bool(r)
 
 
 def rime_batch_autotune(batch: Batch, mode: int, prec: int, data, weight, ws):

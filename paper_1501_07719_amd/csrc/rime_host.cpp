@@ -21,6 +21,7 @@ hipError_t launch_finalize(const KParams &p, int mode, int max_nsrc, hipStream_t
 hipError_t launch_pme(const KParams &p, hipStream_t stream);
 hipError_t launch_pme_adjoint(const KParams &p, hipStream_t stream);
 hipError_t launch_pme_finalize(const KParams &p, hipStream_t stream);
+hipError_t launch_pme_scale(const KParams &p, hipStream_t stream);
 int variant_count(int mode, int prec);
 const Variant *variant_info(int mode, int prec, int index);
 hipError_t launch_variant(int mode, int prec, int index, const KParams &p, int nitems,
@@ -85,6 +86,8 @@ struct rime_plan {
   int32_t *d_bl_slot = nullptr;
   int32_t *d_pair_of = nullptr;
   uint32_t *d_pair_mask = nullptr;
+  int32_t ngroup = 0;
+  int32_t *d_groups = nullptr;  // [ngroup][5] forward work groups
   bool pme_adj_ok = false;  // every antenna-pair slot holds at most one baseline
   int32_t variant[3][2] = {{0, 0}, {0, 0}, {0, 0}};
   std::string signature;  // observation part of the autotune key
@@ -277,16 +280,21 @@ Geometry geometry(const rime_plan *plan, const Variant &v, int nset) {
 
 struct WsLayout {
   size_t geo = 0, lon = 0, st = 0, chi2 = 0, grad = 0, grad2 = 0;
-  size_t ph_hi = 0, ph_lo = 0, spts = 0, rho_t = 0, pgrad = 0;
+  size_t ph_hi = 0, ph_lo = 0, ph_k3 = 0, spts = 0, pexp = 0, rho_t = 0, pgrad = 0;
+  size_t src_f = 0, mfrag = 0, mscale = 0;
   int32_t pme_tchunk = 0;  // timesteps per phase-plane pass (0: engine off)
   bool pme_adj = false;    // point-source adjoint on the matrix cores
   size_t total = 0;
 };
 
 // Upper bound on the two phase planes of one pass of the matrix-core engine.
-constexpr size_t kPmePlaneBytes = size_t(1) << 30;
+constexpr size_t kPmePlaneBytes = size_t(8) << 30;
 
 int pme_ncg(const rime_plan *plan) { return (plan->nchan + kPmeNCW - 1) / kPmeNCW; }
+// bytes of one phase plane of one timestep (all channels)
+int64_t plane_bytes_t(const rime_plan *plan, int64_t npsrc) {
+  return static_cast<int64_t>(plan->nchan) * npsrc * plan->nap * 4;
+}
 int pme_nqr(const rime_plan *plan) { return (plan->nblk + kPmeNQ - 1) / kPmeNQ; }
 
 // Whether a call runs the point sources on the matrix cores.
@@ -315,25 +323,46 @@ WsLayout ws_layout(const rime_plan *plan, int mode, int prec, const Geometry &g,
   if (mode == RIME_MODE_CHI2_GRAD)
     off += align_up(static_cast<size_t>(g.grad_nchunk) * total_src * 10 * sizeof(double2));
   if (pme_active(v, prec, nset)) {
-    // phase planes for pme_tchunk timesteps (total_src bounds the point count)
-    const size_t per_t = static_cast<size_t>(plan->nchan) * total_src * plan->nap * 4;
+    const bool adj = mode == RIME_MODE_CHI2_GRAD && plan->pme_adj_ok;
+    const bool k3 = adj && plan->beam;
+    // per timestep: phase planes (total_src bounds the point count) and, for
+    // the adjoint, the residual fragments
+    const size_t plane_t = static_cast<size_t>(plane_bytes_t(plan, total_src));
+    const size_t frag_t = adj ? static_cast<size_t>(plan->nchan) * plan->nblk * pme_nqr(plan) *
+                                    (4 * 8 * kWave * 2 * sizeof(uint4) + sizeof(float))
+                              : 0;
+    const size_t per_t = plane_t * (k3 ? 3 : 2) + frag_t;
     L.pme_tchunk = static_cast<int32_t>(
-        std::max<size_t>(1, std::min<size_t>(plan->ntime, kPmePlaneBytes / (2 * per_t))));
+        std::max<size_t>(1, std::min<size_t>(plan->ntime, kPmePlaneBytes / per_t)));
     L.ph_hi = off;
-    off += align_up(per_t * L.pme_tchunk);
+    off += align_up(plane_t * L.pme_tchunk);
     L.ph_lo = off;
-    off += align_up(per_t * L.pme_tchunk);
+    off += align_up(plane_t * L.pme_tchunk);
     L.spts = off;
     off += align_up(static_cast<size_t>(plan->ntime) * plan->nchan * plan->npair * 4 *
                     kPmeBlk * kPmeBlk * sizeof(double2));
-    if (mode == RIME_MODE_CHI2_GRAD && plan->pme_adj_ok) {
+    L.pexp = off;
+    off += align_up(static_cast<size_t>(plan->nchan) * 4 * sizeof(int32_t));
+    if (adj) {
       L.pme_adj = true;
+      if (k3) {
+        L.ph_k3 = off;
+        off += align_up(plane_t * L.pme_tchunk);
+      }
       L.rho_t = off;
       off += align_up(static_cast<size_t>(plan->ntime) * plan->nchan * plan->npair * 4 *
                       kPmeBlk * kPmeBlk * sizeof(float2));
       L.pgrad = off;
       off += align_up(static_cast<size_t>((total_src + kPmeSR - 1) / kPmeSR) * plan->ntime *
                       pme_ncg(plan) * plan->nblk * pme_nqr(plan) * kPmeSR * 7 * sizeof(float));
+      L.src_f = off;
+      off += align_up(static_cast<size_t>(total_src) * plan->nchan * sizeof(float));
+      const size_t nfrag = static_cast<size_t>(L.pme_tchunk) * plan->nchan * plan->nblk *
+                           pme_nqr(plan);
+      L.mfrag = off;
+      off += align_up(nfrag * 4 * 8 * kWave * 2 * sizeof(uint4));
+      L.mscale = off;
+      off += align_up(nfrag * sizeof(float));
     }
   }
   L.total = off;
@@ -433,9 +462,12 @@ rime_status enqueue(const rime_plan *plan, int mode, int prec, int vidx, int nse
     p.npair = plan->npair;
     p.pair_blk = plan->d_pair_blk;
     p.bl_slot = plan->d_bl_slot;
+    p.ngroup = plan->ngroup;
+    p.groups = plan->d_groups;
     p.ph_hi = reinterpret_cast<uint32_t *>(w + L.ph_hi);
     p.ph_lo = reinterpret_cast<uint32_t *>(w + L.ph_lo);
     p.spts = reinterpret_cast<double2 *>(w + L.spts);
+    p.pme_exp = reinterpret_cast<int32_t *>(w + L.pexp);
     if (L.pme_adj) {
       p.pme_adj = 1;
       p.nblk = plan->nblk;
@@ -446,19 +478,26 @@ rime_status enqueue(const rime_plan *plan, int mode, int prec, int vidx, int nse
       p.pme_ncg = pme_ncg(plan);
       p.pme_nqr = pme_nqr(plan);
       p.pme_nsr = (one.npsrc + kPmeSR - 1) / kPmeSR;
+      p.src_f = reinterpret_cast<float *>(w + L.src_f);
+      p.mfrag = reinterpret_cast<uint4 *>(w + L.mfrag);
+      p.mscale = reinterpret_cast<float *>(w + L.mscale);
     }
   }
   RIME_HIP(launch_prep(p, prec == RIME_FP64, max_nsrc, stream));
   if (plan->ev_start) RIME_HIP(hipEventRecord(plan->ev_start, stream));
   if (p.pme) {
+    RIME_HIP(launch_pme_scale(p, stream));
+    KParams pf = p;  // the forward needs no beam-derivative plane
+    pf.ph_k3 = nullptr;
     for (int t0 = 0; t0 < plan->ntime; t0 += L.pme_tchunk) {
-      p.pme_t0 = t0;
-      p.pme_nt = std::min(L.pme_tchunk, plan->ntime - t0);
-      RIME_HIP(launch_pme(p, stream));
+      pf.pme_t0 = t0;
+      pf.pme_nt = std::min(L.pme_tchunk, plan->ntime - t0);
+      RIME_HIP(launch_pme(pf, stream));
     }
   }
   RIME_HIP(launch_variant(mode, prec, vidx, p, static_cast<int>(nitems), stream));
   if (p.pme_adj) {
+    if (L.ph_k3) p.ph_k3 = reinterpret_cast<float *>(w + L.ph_k3);
     for (int t0 = 0; t0 < plan->ntime; t0 += L.pme_tchunk) {
       p.pme_t0 = t0;
       p.pme_nt = std::min(L.pme_tchunk, plan->ntime - t0);
@@ -582,8 +621,25 @@ rime_status build_pairs(int na, int nbl, const std::vector<int32_t> &a1,
     if ((w >> j) & 1u) pl->pme_adj_ok = false;
     w |= 1u << j;
   }
+  // forward work groups: every Q block with the P blocks of its pairs, two at a time
+  std::vector<int32_t> groups;
+  for (int Q = 0; Q < nblk; ++Q) {
+    std::vector<int> ps;
+    for (int P = 0; P <= Q; ++P)
+      if (pair_id[static_cast<size_t>(P) * nblk + Q] >= 0) ps.push_back(P);
+    for (size_t x = 0; x < ps.size(); x += 2) {
+      const int Pa = ps[x], Pb = x + 1 < ps.size() ? ps[x + 1] : -1;
+      groups.push_back(Q);
+      groups.push_back(Pa);
+      groups.push_back(Pb);
+      groups.push_back(pair_id[static_cast<size_t>(Pa) * nblk + Q]);
+      groups.push_back(Pb >= 0 ? pair_id[static_cast<size_t>(Pb) * nblk + Q] : -1);
+    }
+  }
+  pl->ngroup = static_cast<int32_t>(groups.size() / 5);
   hipError_t e;
-  if ((e = upload(&pl->d_pair_blk, pairs)) != hipSuccess ||
+  if ((e = upload(&pl->d_groups, groups)) != hipSuccess ||
+      (e = upload(&pl->d_pair_blk, pairs)) != hipSuccess ||
       (e = upload(&pl->d_bl_slot, slot)) != hipSuccess ||
       (e = upload(&pl->d_pair_of, pair_id)) != hipSuccess ||
       (e = upload(&pl->d_pair_mask, mask)) != hipSuccess)
@@ -642,6 +698,7 @@ void rime_plan_destroy(rime_plan *plan) {
   (void)hipFree(plan->d_bl_slot);
   (void)hipFree(plan->d_pair_of);
   (void)hipFree(plan->d_pair_mask);
+  (void)hipFree(plan->d_groups);
   for (auto &t : plan->tiles) {
     (void)hipFree(t.bl);
     (void)hipFree(t.lpq);

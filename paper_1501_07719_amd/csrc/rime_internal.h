@@ -66,6 +66,7 @@ struct KParams {
   double4 *src_geo;        // [total_src] (l, m, n - 1, 0)
   double2 *src_lon;        // [total_src] (l / n, m / n)
   void *src_st;            // [total_src][nchan] Stokes scaled by (nu/nu_ref)^alpha (R4)
+  float *src_f;            // [total_src][nchan] (nu/nu_ref)^alpha, or nullptr
   int64_t total_src;
   // per-call data
   const void *data;        // [ntime][nbl][nchan][4] complex
@@ -88,6 +89,10 @@ struct KParams {
   const int32_t *bl_slot;  // [nbl] pair << 11 | i << 6 | j << 1 | conj
   uint32_t *ph_hi;         // phase planes [pme_nt][nchan][npsrc][nap] half2 (re, im):
   uint32_t *ph_lo;         //   a = hi + lo, a = e exp(-2 pi i tau nu / c)
+  float *ph_k3;            // [pme_nt][nchan][npsrc][nap] d ln e / d(l, m) = k3 (l - dl, m - dm)
+  int32_t ngroup;          // forward work groups: a Q block with up to two P blocks
+  const int32_t *groups;   // [ngroup][5] (Q, Pa, Pb or -1, pair of (Pa, Q), pair of (Pb, Q))
+  int32_t *pme_exp;        // [nchan][4] exponent of max_s |St'_k| (forward scale 2^-e)
   int32_t pme_t0, pme_nt;  // timesteps held by the phase planes
   double2 *spts;           // [ntime][nchan][npair][4][kPmeBlk][kPmeBlk] Stokes sums
   // matrix-core adjoint of the point sources
@@ -99,6 +104,8 @@ struct KParams {
                            //   Stokes form (conjugated for baselines stored as (q, p))
   float *pgrad;            // adjoint partials [nsr][ntime][ncg][nblk][nqr][kPmeSR][7]
   int32_t pme_ncg, pme_nqr, pme_nsr;
+  uint4 *mfrag;            // [pme_nt][nchan][nblk][nqr][4][8][64][2] fp16 fragments of M
+  float *mscale;           // [pme_nt][nchan][nblk][nqr] 2^e undoing the fragment scale
 };
 
 // Antenna block of the matrix-core engine (rows and columns of one MFMA tile),

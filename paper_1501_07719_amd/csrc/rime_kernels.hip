@@ -58,6 +58,7 @@ __global__ __launch_bounds__(256) void prep_sources(const KParams p) {
     v.z = static_cast<R>(f * U);
     v.w = static_cast<R>(f * V);
     st[c] = v;
+    if (p.src_f) p.src_f[g * p.nchan + c] = static_cast<float>(f);
   }
 }
 

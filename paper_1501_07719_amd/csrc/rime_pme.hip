@@ -6,23 +6,25 @@
 //   S_k[p][q] = sum_s a_ps conj(a_qs) St'_sk,   a_ps = e_ps K_ps,
 // i.e. for every (timestep, channel) the four Stokes sums of all baselines
 // form the antenna x antenna matrix product A diag(St'_k) A^H.  This file
-// evaluates that product on the matrix cores:
-//   pme_phase   a_ps for every (t, nu, s, p), split into fp16 hi + lo parts
-//               (22 significant bits; the phase argument is reduced in
-//               float64 exactly as in the per-baseline kernels);
-//   pme_forward one 32 x 32 antenna tile (P, Q) per workgroup, one Stokes
-//               parameter per wavefront: the real product over (s, re/im)
-//               with v_mfma_f32_32x32x16_f16, each fp16 product taken as
-//               hi*hi + hi*lo + lo*hi, summed in float32 within a chunk of 32
-//               sources and in float64 across chunks.  The result (float64
-//               Stokes sums of every antenna pair of the tile) goes to HBM,
-//               where the per-baseline kernel adds it to the sums of the
-//               remaining (Gaussian) sources before forming V and chi^2;
-//   pme_adjoint the gradient of chi^2 with respect to the point-source
-//               parameters from the weighted residual that the per-baseline
-//               kernel leaves in the antenna-pair slots, as the product
-//               (T + T^H) conj(A) on the matrix cores followed by per-source
-//               reductions over the antennas (see the comment there);
+// evaluates that product, and the corresponding part of the adjoint, on the
+// matrix cores:
+//   pme_phase    a_ps for every (t, nu, s, p), split into fp16 hi + lo parts
+//                (22 significant bits; the phase argument is reduced in
+//                float64 exactly as in the per-baseline kernels), and the
+//                beam's d ln e / d(l, m) factor;
+//   pme_scale    per (channel, Stokes parameter) power-of-two scale of the
+//                source-side operand;
+//   pme_forward  one Q block of 32 antennas against up to two P blocks per
+//                workgroup, one Stokes parameter per wavefront: the real form
+//                of the product over (s, re/im) with v_mfma_f32_32x32x16_f16,
+//                each fp16 product taken as hi*hi + hi*lo + lo*hi, summed in
+//                float32 over 128 sources and in float64 beyond.  The float64
+//                Stokes sums of every antenna pair go to HBM, where the
+//                per-baseline kernel adds them to the sums of the remaining
+//                (Gaussian) sources before forming V and chi^2;
+//   pme_mfrag    the residual matrices of the adjoint as fp16 MFMA fragments;
+//   pme_adjoint  the gradient of chi^2 with respect to the point-source
+//                parameters (see the comment there);
 //   pme_finalize float64 sums of the adjoint's per-workgroup partials.
 // Operand fragments follow the gfx950 lane layout of the 32x32x16 fp16
 // instruction: A[i][k] in lane i + 32 (k / 8), element k % 8; B[k][j] in lane
@@ -37,6 +39,7 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 constexpr int kPmeCh = 32;                 // sources per staged chunk
 constexpr int kPmeRow = 2 * kPmeCh + 8;    // fp16 per LDS row: (s, re/im) + 16 B pad
+constexpr int kPmeFold = 4;                // chunks summed in float32 before a float64 fold
 
 __device__ inline uint32_t pack_h2(_Float16 re, _Float16 im) {
   return static_cast<uint32_t>(__builtin_bit_cast(uint16_t, re)) |
@@ -60,6 +63,13 @@ __device__ inline void split_h(float x, _Float16 &h, _Float16 &l) {
 // of a conj(b) in the real form of the complex product.
 __device__ inline uint32_t rot_h2(uint32_t w) { return (w >> 16) | ((w ^ 0x8000u) << 16); }
 
+// Workgroups are dealt round-robin to the 8 XCDs; renumbering them makes
+// consecutive work items (which share operands through L2) land on one XCD.
+__device__ inline int xcd_item(int nitems) {
+  const int per_xcd = (nitems + 7) / 8;
+  return static_cast<int>(blockIdx.x % 8) * per_xcd + static_cast<int>(blockIdx.x / 8);
+}
+
 // ---------------------------------------------------------------------------
 // Phase planes: thread = (source, antenna) of one timestep; loops over the
 // channels reusing the float64 phase argument tau and the beam radius.
@@ -75,12 +85,15 @@ __global__ __launch_bounds__(256) void pme_phase(const KParams p) {
   if (idx >= plane) return;
   const int s = static_cast<int>(idx / nap);
   const int a = static_cast<int>(idx - static_cast<int64_t>(s) * nap);
-  uint32_t *hi = p.ph_hi + static_cast<int64_t>(tt) * p.nchan * plane + idx;
-  uint32_t *lo = p.ph_lo + static_cast<int64_t>(tt) * p.nchan * plane + idx;
+  const int64_t o = static_cast<int64_t>(tt) * p.nchan * plane + idx;
+  uint32_t *hi = p.ph_hi + o;
+  uint32_t *lo = p.ph_lo + o;
+  float *k3p = p.ph_k3 ? p.ph_k3 + o : nullptr;
   if (a >= p.na) {
     for (int c = 0; c < p.nchan; ++c) {
       hi[c * plane] = 0u;
       lo[c * plane] = 0u;
+      if (k3p) k3p[c * plane] = 0.0f;
     }
     return;
   }
@@ -100,7 +113,7 @@ __global__ __launch_bounds__(256) void pme_phase(const KParams p) {
     const double r = xt - rint(xt);
     float sn, cs;
     N::sincos_turns(r, &sn, &cs);
-    float e = 1.0f;
+    float e = 1.0f, k3 = 0.0f;
     if (p.beam) {
       // cos^3 of beam_k r nu / beam_ref_freq, clipped (eq. e_term); the clip
       // is decided in float64 on r^2 as in the per-baseline kernels
@@ -110,110 +123,161 @@ __global__ __launch_bounds__(256) void pme_phase(const KParams p) {
       float sb, cb;
       N::sincos_rad(xr, &sb, &cb);
       e = cb * cb * cb;
+      // d ln e / dl = -3 bs^2 (l - dl_p) tan(x)/x; zero past the clip
+      if (!clipped) {
+        const float tx = xr > 1e-4f ? sb * N::rcp(cb * xr) : 1.0f + xr * xr / 3.0f;
+        k3 = static_cast<float>(-3.0 * bs * bs) * tx;
+      }
     }
     _Float16 rh, rl, ih, il;
     split_h(e * cs, rh, rl);
     split_h(-e * sn, ih, il);
     hi[c * plane] = pack_h2(rh, ih);
     lo[c * plane] = pack_h2(rl, il);
+    if (k3p) k3p[c * plane] = k3;
   }
 }
 
 // ---------------------------------------------------------------------------
-// Antenna-pair product for one (timestep, channel, tile pair).
+// Forward scale: exponent e of max_s |St'_k,s(nu)|, one workgroup per channel.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void pme_forward(const KParams p) {
-  // Workgroups are dealt round-robin to the 8 XCDs; renumber them so that
-  // the tile pairs of one (timestep, channel) share an XCD and its L2.
-  const int nitems = p.pme_nt * p.nchan * p.npair;
-  const int per_xcd = (nitems + 7) / 8;
-  const int item = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+__global__ __launch_bounds__(256) void pme_scale(const KParams p) {
+  __shared__ float s_m[4][256 / kWave];
+  const int c = blockIdx.x;
+  const SetDesc sd = p.one;
+  const float4 *st = static_cast<const float4 *>(p.src_st);
+  float m[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  for (int s = threadIdx.x; s < sd.npsrc; s += 256) {
+    const float4 v = st[(sd.src_off + s) * p.nchan + c];
+    m[0] = fmaxf(m[0], fabsf(v.x));
+    m[1] = fmaxf(m[1], fabsf(v.y));
+    m[2] = fmaxf(m[2], fabsf(v.z));
+    m[3] = fmaxf(m[3], fabsf(v.w));
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) m[k] = fmaxf(m[k], __shfl_xor(m[k], off, kWave));
+    if (threadIdx.x % kWave == 0) s_m[k][threadIdx.x / kWave] = m[k];
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    const int k = threadIdx.x;
+    const float mm = fmaxf(fmaxf(s_m[k][0], s_m[k][1]), fmaxf(s_m[k][2], s_m[k][3]));
+    int e = 0;
+    if (mm > 0.0f) frexpf(mm, &e);
+    p.pme_exp[c * 4 + k] = e;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Forward: workgroup = (timestep, channel, group of one Q block and up to two
+// P blocks); wavefront k accumulates S_k for both (P, Q) tiles.  The Q side
+// carries St'_k 2^-e(nu, k) and is split after the product; the P side is the
+// plain a (and its rotation for the imaginary part).
+// ---------------------------------------------------------------------------
+struct FwdRegs {
+  uint4 pah, pal, pbh, pbl, qh, ql;
+  float4 st;
+};
+
+// Global operands of one chunk for thread (source tid / 8, antennas 4 (tid % 8) ..).
+__device__ inline FwdRegs fwd_load(const KParams &p, const uint32_t *hi0, const uint32_t *lo0,
+                                   int c, int s0, int cnt, int Q, int Pa, int Pb) {
+  const int tid = threadIdx.x;
+  const int s = tid >> 3, ag = (tid & 7) * 4;
+  FwdRegs r;
+  r.pah = r.pal = r.pbh = r.pbl = r.qh = r.ql = make_uint4(0, 0, 0, 0);
+  r.st = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  if (s < cnt) {
+    const int64_t row = static_cast<int64_t>(s0 + s) * p.nap;
+    r.pah = *reinterpret_cast<const uint4 *>(hi0 + row + Pa * kPmeBlk + ag);
+    r.pal = *reinterpret_cast<const uint4 *>(lo0 + row + Pa * kPmeBlk + ag);
+    if (Pb >= 0) {
+      r.pbh = *reinterpret_cast<const uint4 *>(hi0 + row + Pb * kPmeBlk + ag);
+      r.pbl = *reinterpret_cast<const uint4 *>(lo0 + row + Pb * kPmeBlk + ag);
+    }
+    r.qh = *reinterpret_cast<const uint4 *>(hi0 + row + Q * kPmeBlk + ag);
+    r.ql = *reinterpret_cast<const uint4 *>(lo0 + row + Q * kPmeBlk + ag);
+    r.st = static_cast<const float4 *>(p.src_st)[(p.one.src_off + s0 + s) * p.nchan + c];
+  }
+  return r;
+}
+
+__global__ __launch_bounds__(256, 2) void pme_forward(const KParams p) {
+  const int nitems = p.pme_nt * p.nchan * p.ngroup;
+  const int item = xcd_item(nitems);
   if (item >= nitems) return;
-  const int pair = item % p.npair;
-  const int rest = item / p.npair;
+  const int grp = item % p.ngroup;
+  const int rest = item / p.ngroup;
   const int c = rest % p.nchan;
   const int tt = rest / p.nchan;
 
-  __shared__ __attribute__((aligned(16))) _Float16 s_ah[kPmeBlk][kPmeRow];
-  __shared__ __attribute__((aligned(16))) _Float16 s_al[kPmeBlk][kPmeRow];
-  __shared__ __attribute__((aligned(16))) _Float16 s_rh[kPmeBlk][kPmeRow];
-  __shared__ __attribute__((aligned(16))) _Float16 s_rl[kPmeBlk][kPmeRow];
+  // [P block a/b][antenna][(s, re/im)]
+  __shared__ __attribute__((aligned(16))) _Float16 s_ah[2][kPmeBlk][kPmeRow];
+  __shared__ __attribute__((aligned(16))) _Float16 s_al[2][kPmeBlk][kPmeRow];
+  __shared__ __attribute__((aligned(16))) _Float16 s_rh[2][kPmeBlk][kPmeRow];
+  __shared__ __attribute__((aligned(16))) _Float16 s_rl[2][kPmeBlk][kPmeRow];
   __shared__ __attribute__((aligned(16))) _Float16 s_bh[4][kPmeBlk][kPmeRow];
   __shared__ __attribute__((aligned(16))) _Float16 s_bl[4][kPmeBlk][kPmeRow];
-  __shared__ float s_st[4][kPmeCh];
-  __shared__ float s_scale[4];
 
   const SetDesc sd = p.one;
-  const int2 pq = p.pair_blk[pair];
+  const int *gr = p.groups + grp * 5;
+  const int Q = gr[0], Pa = gr[1], Pb = gr[2], ida = gr[3], idb = gr[4];
   const int tid = threadIdx.x;
   const int wave = tid / kWave, lane = tid % kWave;
   const int k = wave;  // Stokes parameter of this wavefront
+  const int row = lane & 31, g = lane >> 5;
 
   const int64_t plane = static_cast<int64_t>(sd.npsrc) * p.nap;
   const uint32_t *hi0 = p.ph_hi + (static_cast<int64_t>(tt) * p.nchan + c) * plane;
   const uint32_t *lo0 = p.ph_lo + (static_cast<int64_t>(tt) * p.nchan + c) * plane;
-  const float4 *st = static_cast<const float4 *>(p.src_st);
+  // St'_k 2^-e(nu, k): |scaled| < 1
+  float fsc[4];
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) fsc[kk] = ldexpf(1.0f, -p.pme_exp[c * 4 + kk]);
+  const double unscale = ldexp(1.0, p.pme_exp[c * 4 + k]);
 
-  floatx16 accR, accI;
-  double dR[16], dI[16];
+  floatx16 aR0, aI0, aR1, aI1;
+  double dR0[16], dI0[16], dR1[16], dI1[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
-    accR[r] = 0.0f;
-    accI[r] = 0.0f;
-    dR[r] = 0.0;
-    dI[r] = 0.0;
+    aR0[r] = aI0[r] = aR1[r] = aI1[r] = 0.0f;
+    dR0[r] = dI0[r] = dR1[r] = dI1[r] = 0.0;
   }
 
   const int nchunk = (sd.npsrc + kPmeCh - 1) / kPmeCh;
+  FwdRegs nx = fwd_load(p, hi0, lo0, c, 0, min(kPmeCh, sd.npsrc), Q, Pa, Pb);
   for (int ch = 0; ch < nchunk; ++ch) {
-    const int s0 = ch * kPmeCh;
-    const int cnt = min(kPmeCh, sd.npsrc - s0);
-    __syncthreads();  // previous chunk's fragments are consumed
-    if (tid < kPmeCh) {
-      float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      if (tid < cnt) v = st[(sd.src_off + s0 + tid) * p.nchan + c];
-      s_st[0][tid] = v.x;
-      s_st[1][tid] = v.y;
-      s_st[2][tid] = v.z;
-      s_st[3][tid] = v.w;
-    }
-    __syncthreads();
-    // per-chunk power-of-two scale of Stokes parameter k: max |St'_k| -> [1/2, 1)
-    if (lane < kPmeCh) {
-      float m = fabsf(s_st[k][lane]);
-#pragma unroll
-      for (int off = kPmeCh / 2; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, kWave));
-      if (lane == 0) {
-        int e = 0;
-        if (m > 0.0f) frexpf(m, &e);
-        s_scale[k] = ldexpf(1.0f, -e);
-      }
-    }
-    __syncthreads();
+    const FwdRegs cur = nx;
+    __syncthreads();  // the previous chunk's fragments are consumed
     {
-      // staging: thread = (source, 4 antennas) of both antenna blocks
       const int s = tid >> 3, ag = (tid & 7) * 4;
-      uint4 ph = make_uint4(0, 0, 0, 0), pl = ph, qh = ph, ql = ph;
-      if (s < cnt) {
-        const int64_t row = static_cast<int64_t>(s0 + s) * p.nap;
-        ph = *reinterpret_cast<const uint4 *>(hi0 + row + pq.x * kPmeBlk + ag);
-        pl = *reinterpret_cast<const uint4 *>(lo0 + row + pq.x * kPmeBlk + ag);
-        qh = *reinterpret_cast<const uint4 *>(hi0 + row + pq.y * kPmeBlk + ag);
-        ql = *reinterpret_cast<const uint4 *>(lo0 + row + pq.y * kPmeBlk + ag);
-      }
-      const uint32_t phw[4] = {ph.x, ph.y, ph.z, ph.w}, plw[4] = {pl.x, pl.y, pl.z, pl.w};
-      const uint32_t qhw[4] = {qh.x, qh.y, qh.z, qh.w}, qlw[4] = {ql.x, ql.y, ql.z, ql.w};
+      const uint32_t w0[4] = {cur.pah.x, cur.pah.y, cur.pah.z, cur.pah.w};
+      const uint32_t w1[4] = {cur.pal.x, cur.pal.y, cur.pal.z, cur.pal.w};
+      const uint32_t w2[4] = {cur.pbh.x, cur.pbh.y, cur.pbh.z, cur.pbh.w};
+      const uint32_t w3[4] = {cur.pbl.x, cur.pbl.y, cur.pbl.z, cur.pbl.w};
+      const uint32_t wq[4] = {cur.qh.x, cur.qh.y, cur.qh.z, cur.qh.w};
+      const uint32_t wl[4] = {cur.ql.x, cur.ql.y, cur.ql.z, cur.ql.w};
       float f[4];
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) f[kk] = s_st[kk][s] * s_scale[kk];
+      f[0] = cur.st.x * fsc[0];
+      f[1] = cur.st.y * fsc[1];
+      f[2] = cur.st.z * fsc[2];
+      f[3] = cur.st.w * fsc[3];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        *reinterpret_cast<uint32_t *>(&s_ah[ag + j][2 * s]) = phw[j];
-        *reinterpret_cast<uint32_t *>(&s_al[ag + j][2 * s]) = plw[j];
-        *reinterpret_cast<uint32_t *>(&s_rh[ag + j][2 * s]) = rot_h2(phw[j]);
-        *reinterpret_cast<uint32_t *>(&s_rl[ag + j][2 * s]) = rot_h2(plw[j]);
-        const float ar = lo_h(qhw[j]) + lo_h(qlw[j]);
-        const float ai = hi_h(qhw[j]) + hi_h(qlw[j]);
+        *reinterpret_cast<uint32_t *>(&s_ah[0][ag + j][2 * s]) = w0[j];
+        *reinterpret_cast<uint32_t *>(&s_al[0][ag + j][2 * s]) = w1[j];
+        *reinterpret_cast<uint32_t *>(&s_rh[0][ag + j][2 * s]) = rot_h2(w0[j]);
+        *reinterpret_cast<uint32_t *>(&s_rl[0][ag + j][2 * s]) = rot_h2(w1[j]);
+        if (Pb >= 0) {
+          *reinterpret_cast<uint32_t *>(&s_ah[1][ag + j][2 * s]) = w2[j];
+          *reinterpret_cast<uint32_t *>(&s_al[1][ag + j][2 * s]) = w3[j];
+          *reinterpret_cast<uint32_t *>(&s_rh[1][ag + j][2 * s]) = rot_h2(w2[j]);
+          *reinterpret_cast<uint32_t *>(&s_rl[1][ag + j][2 * s]) = rot_h2(w3[j]);
+        }
+        const float ar = lo_h(wq[j]) + lo_h(wl[j]);
+        const float ai = hi_h(wq[j]) + hi_h(wl[j]);
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
           _Float16 rh, rl, ih, il;
@@ -225,46 +289,72 @@ __global__ __launch_bounds__(256) void pme_forward(const KParams p) {
       }
     }
     __syncthreads();
-    {
-      const int row = lane & 31, g = lane >> 5;
+    if (ch + 1 < nchunk) {
+      // the next chunk's operands are in flight during this chunk's products
+      const int s1 = (ch + 1) * kPmeCh;
+      nx = fwd_load(p, hi0, lo0, c, s1, min(kPmeCh, sd.npsrc - s1), Q, Pa, Pb);
+    }
 #pragma unroll
-      for (int step = 0; step < kPmeCh / 8; ++step) {
-        // K index (s, re/im) with s = 8 step + 4 g + e / 2 for element e
-        const int col = 16 * step + 8 * g;
-        const half8 ah = *reinterpret_cast<const half8 *>(&s_ah[row][col]);
-        const half8 al = *reinterpret_cast<const half8 *>(&s_al[row][col]);
-        const half8 rh = *reinterpret_cast<const half8 *>(&s_rh[row][col]);
-        const half8 rl = *reinterpret_cast<const half8 *>(&s_rl[row][col]);
-        const half8 bh = *reinterpret_cast<const half8 *>(&s_bh[k][row][col]);
-        const half8 bl = *reinterpret_cast<const half8 *>(&s_bl[k][row][col]);
-        accR = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bh, accR, 0, 0, 0);
-        accR = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bl, accR, 0, 0, 0);
-        accR = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, bh, accR, 0, 0, 0);
-        accI = __builtin_amdgcn_mfma_f32_32x32x16_f16(rh, bh, accI, 0, 0, 0);
-        accI = __builtin_amdgcn_mfma_f32_32x32x16_f16(rh, bl, accI, 0, 0, 0);
-        accI = __builtin_amdgcn_mfma_f32_32x32x16_f16(rl, bh, accI, 0, 0, 0);
+    for (int step = 0; step < kPmeCh / 8; ++step) {
+      // K index (s, re/im) with s = 8 step + 4 g + e / 2 for element e
+      const int col = 16 * step + 8 * g;
+      const half8 bh = *reinterpret_cast<const half8 *>(&s_bh[k][row][col]);
+      const half8 bl = *reinterpret_cast<const half8 *>(&s_bl[k][row][col]);
+      {
+        const half8 ah = *reinterpret_cast<const half8 *>(&s_ah[0][row][col]);
+        const half8 al = *reinterpret_cast<const half8 *>(&s_al[0][row][col]);
+        const half8 rh = *reinterpret_cast<const half8 *>(&s_rh[0][row][col]);
+        const half8 rl = *reinterpret_cast<const half8 *>(&s_rl[0][row][col]);
+        aR0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bh, aR0, 0, 0, 0);
+        aI0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(rh, bh, aI0, 0, 0, 0);
+        aR0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bl, aR0, 0, 0, 0);
+        aI0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(rh, bl, aI0, 0, 0, 0);
+        aR0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, bh, aR0, 0, 0, 0);
+        aI0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(rl, bh, aI0, 0, 0, 0);
       }
-      // fold the chunk into float64, undoing its scale
-      const double inv = 1.0 / static_cast<double>(s_scale[k]);
+      if (Pb >= 0) {
+        const half8 ah = *reinterpret_cast<const half8 *>(&s_ah[1][row][col]);
+        const half8 al = *reinterpret_cast<const half8 *>(&s_al[1][row][col]);
+        const half8 rh = *reinterpret_cast<const half8 *>(&s_rh[1][row][col]);
+        const half8 rl = *reinterpret_cast<const half8 *>(&s_rl[1][row][col]);
+        aR1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bh, aR1, 0, 0, 0);
+        aI1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(rh, bh, aI1, 0, 0, 0);
+        aR1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bl, aR1, 0, 0, 0);
+        aI1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(rh, bl, aI1, 0, 0, 0);
+        aR1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, bh, aR1, 0, 0, 0);
+        aI1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(rl, bh, aI1, 0, 0, 0);
+      }
+    }
+    if ((ch + 1) % kPmeFold == 0 || ch + 1 == nchunk) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        dR[r] += static_cast<double>(accR[r]) * inv;
-        dI[r] += static_cast<double>(accI[r]) * inv;
-        accR[r] = 0.0f;
-        accI[r] = 0.0f;
+        dR0[r] += static_cast<double>(aR0[r]) * unscale;
+        dI0[r] += static_cast<double>(aI0[r]) * unscale;
+        dR1[r] += static_cast<double>(aR1[r]) * unscale;
+        dI1[r] += static_cast<double>(aI1[r]) * unscale;
+        aR0[r] = aI0[r] = aR1[r] = aI1[r] = 0.0f;
       }
     }
   }
 
   // Stokes sums S_k[i][j] of antennas (32 P + i, 32 Q + j)
-  double2 *out = p.spts +
-                 ((((static_cast<int64_t>(p.pme_t0) + tt) * p.nchan + c) * p.npair + pair) * 4 + k) *
-                     (kPmeBlk * kPmeBlk);
+  const int64_t slice = (static_cast<int64_t>(p.pme_t0) + tt) * p.nchan + c;
   const int j = lane & 31;
+  {
+    double2 *out = p.spts + ((slice * p.npair + ida) * 4 + k) * (kPmeBlk * kPmeBlk);
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int i = (r & 3) + 8 * (r >> 2) + 4 * (lane >> 5);
-    out[i * kPmeBlk + j] = make_double2(dR[r], dI[r]);
+    for (int r = 0; r < 16; ++r) {
+      const int i = (r & 3) + 8 * (r >> 2) + 4 * g;
+      out[i * kPmeBlk + j] = make_double2(dR0[r], dI0[r]);
+    }
+  }
+  if (Pb >= 0) {
+    double2 *out = p.spts + ((slice * p.npair + idb) * 4 + k) * (kPmeBlk * kPmeBlk);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int i = (r & 3) + 8 * (r >> 2) + 4 * g;
+      out[i * kPmeBlk + j] = make_double2(dR1[r], dI1[r]);
+    }
   }
 }
 
@@ -273,17 +363,18 @@ __global__ __launch_bounds__(256) void pme_forward(const KParams p) {
 // rho_k of every baseline stored in its antenna-pair slot T (rho, or its
 // conjugate for a baseline stored as (q, p)), the Hermitian matrix
 // M_k = T_k + T_k^H has M_k[p][q] = rho_k for the baseline (p, q) and
-// conj(rho_k) for (q, p).  Then, with Z_k = M_k conj(A) (antennas x sources):
-//   sum_{p<q} Re(c_pq rho_k)            = 1/2 sum_p Re(a_ps Z_k[p][s])
-//   W_ps = a_ps sum_k St'_k Z_k[p][s]   sums P = c sum_k St'_k rho_k over
-//                                       the baselines of antenna p, so that
-//   sum_{p<q} (u_p - u_q) Im P          = sum_p u_p Im W_ps   (v, w alike)
-//   sum_{p<q} (beta_p + beta_q) Re P    = sum_p beta_ps Re W_ps
-// which are the per-source sums of the per-baseline adjoint.  Workgroup =
-// (source range, timestep, kPmeNCW channels, antenna block P, kPmeNQ blocks
-// of q); wavefront k holds the fp16 hi/lo fragments of rows (p in P, re/im)
-// of M_k (scaled by a power of two per channel so that max |M| < 1) for the
-// whole q range and streams 32-source chunks of A as the B operand.
+// conj(rho_k) for (q, p).  With Z_k = M_k conj(A) (antennas x sources) and
+// c_pq = a_p conj(a_q), summing over the baselines (p < q):
+//   sum Re(c rho_k)                   = 1/2 sum_p Re(a_ps Z_k[p][s])
+//   sum (u_p - u_q) Im(c rho_k)       = sum_p u_p Im(a_ps Z_k[p][s])  (v, w alike)
+//   sum (beta_p + beta_q) Re(c rho_k) = sum_p beta_ps Re(a_ps Z_k[p][s])
+// and P = c sum_k St'_k rho_k combines the four k with weights St'_k, so the
+// per-baseline adjoint's source sums follow from Z_k by reductions over the
+// antennas p.  Workgroup = (source range, timestep, kPmeNCW channels,
+// antenna block P, kPmeNQ blocks of q); wavefront k holds the fp16 hi/lo
+// fragments of rows (p in P, re/im) of M_k for the q range (scaled by a power
+// of two so that max |M| < 1) and streams 32-source chunks of A as the B
+// operand.
 // ---------------------------------------------------------------------------
 constexpr int kPmeBRow = 2 * kPmeBlk * kPmeNQ + 8;  // fp16 per B row: (q, re/im) + pad
 
@@ -293,12 +384,98 @@ __device__ inline float2 rho_at(const KParams &p, int64_t base, int pair, int i,
   return p.rho_t[base + static_cast<int64_t>(pair) * 4 * kPmeBlk * kPmeBlk + i * kPmeBlk + j];
 }
 
+// Fragments of M_k (rows of block P, columns of the q range) for one
+// (timestep, channel): workgroup = (timestep, channel, P, q range),
+// wavefront = k.  Element e of K-step st of lane (row, g) is (q, re/im) with
+// q = 8 st + 4 g + e / 2 local to the range.
+__global__ __launch_bounds__(256) void pme_mfrag(const KParams p) {
+  __shared__ float s_gmax[4];
+  const int nP = p.nblk, nQR = p.pme_nqr;
+  const int item = blockIdx.x;  // ((tt * nchan + c) * nP + P) * nQR + qr
+  int rest = item;
+  const int qr = rest % nQR;
+  rest /= nQR;
+  const int P = rest % nP;
+  rest /= nP;
+  const int c = rest % p.nchan;
+  const int tt = rest / p.nchan;
+  const int t = p.pme_t0 + tt;
+  const int Q0 = qr * kPmeNQ;
+  const int nq = min(kPmeNQ, nP - Q0);
+  const int tid = threadIdx.x;
+  const int k = tid / kWave, lane = tid % kWave;
+  const int row = lane & 31, g = lane >> 5;
+  const int64_t base =
+      ((static_cast<int64_t>(t) * p.nchan + c) * p.npair * 4 + k) * (kPmeBlk * kPmeBlk);
+  float2 m[kPmeNQ * 4][4];
+  float mx = 0.0f;
+#pragma unroll
+  for (int st = 0; st < kPmeNQ * 4; ++st) {
+    const int ql = 8 * st + 4 * g;
+    const int qb = Q0 + ql / kPmeBlk;
+    const int j0 = ql % kPmeBlk;
+    int pr = -1, mode = 0;  // 0: T[P][qb], 1: T + T^H (P == qb), 2: T[qb][P]^H
+    if (st < nq * 4) {
+      if (qb == P) {
+        pr = p.pair_of[P * nP + P];
+        mode = 1;
+      } else if (P < qb) {
+        pr = p.pair_of[P * nP + qb];
+      } else {
+        pr = p.pair_of[qb * nP + P];
+        mode = 2;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int j = j0 + e;
+      float2 v = make_float2(0.0f, 0.0f);
+      if (mode == 0) {
+        v = rho_at(p, base, pr, row, j);
+      } else if (mode == 1) {
+        const float2 a = rho_at(p, base, pr, row, j);
+        const float2 b = rho_at(p, base, pr, j, row);
+        v = make_float2(a.x + b.x, a.y - b.y);
+      } else {
+        const float2 b = rho_at(p, base, pr, j, row);
+        v = make_float2(b.x, -b.y);
+      }
+      m[st][e] = v;
+      mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
+    }
+  }
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, kWave));
+  if (lane == 0) s_gmax[k] = mx;
+  __syncthreads();
+  const float gmax = fmaxf(fmaxf(s_gmax[0], s_gmax[1]), fmaxf(s_gmax[2], s_gmax[3]));
+  int ex = 0;
+  if (gmax > 0.0f) frexpf(gmax, &ex);
+  const float scl = ldexpf(1.0f, -ex);
+  if (tid == 0) p.mscale[item] = gmax > 0.0f ? ldexpf(1.0f, ex) : 0.0f;
+  uint4 *dst = p.mfrag + ((static_cast<int64_t>(item) * 4 + k) * (kPmeNQ * 4) * kWave) * 2;
+#pragma unroll
+  for (int st = 0; st < kPmeNQ * 4; ++st) {
+    if (st < nq * 4) {
+      uint32_t hw[4], lw[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        _Float16 rh, rl, ih, il;
+        split_h(m[st][e].x * scl, rh, rl);
+        split_h(m[st][e].y * scl, ih, il);
+        hw[e] = pack_h2(rh, ih);
+        lw[e] = pack_h2(rl, il);
+      }
+      dst[(st * kWave + lane) * 2] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+      dst[(st * kWave + lane) * 2 + 1] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+    }
+  }
+}
+
 __global__ __launch_bounds__(256, 2) void pme_adjoint(const KParams p) {
-  using N = Num<float>;
   const int nP = p.nblk, nQR = p.pme_nqr, nCG = p.pme_ncg, nT = p.pme_nt;
   const int nitems = p.pme_nsr * nT * nCG * nP * nQR;
-  const int per_xcd = (nitems + 7) / 8;
-  const int item = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  const int item = xcd_item(nitems);
   if (item >= nitems) return;
   int rest = item;
   const int qr = rest % nQR;
@@ -318,14 +495,13 @@ __global__ __launch_bounds__(256, 2) void pme_adjoint(const KParams p) {
 
   __shared__ __attribute__((aligned(16))) _Float16 s_bh[kPmeCh][kPmeBRow];
   __shared__ __attribute__((aligned(16))) _Float16 s_bl[kPmeCh][kPmeBRow];
-  __shared__ float2 s_ap[kPmeBlk][kPmeCh + 1];
-  __shared__ float2 s_w[kPmeBlk][kPmeCh + 1];
-  __shared__ float s_g[4][kPmeCh];
-  __shared__ float s_red[4][kPmeCh][5];
+  __shared__ float2 s_ap[kPmeBlk][kPmeCh + 1];  // a of block P (float32)
+  __shared__ float s_betl[kPmeBlk][kPmeCh + 1];  // beta_l = k3 (l - dl_p)
+  __shared__ float s_betm[kPmeBlk][kPmeCh + 1];  // beta_m = k3 (m - dm_p)
+  __shared__ float s_out[4][kPmeCh][6];          // per k: G, u, v, w, beam l, beam m
   __shared__ float s_acc[kPmeSR][7];
   __shared__ float s_uvw[kPmeBlk][3];
   __shared__ double s_pnt[kPmeBlk][2];
-  __shared__ float s_gmax[4];
 
   const int tid = threadIdx.x;
   const int wave = tid / kWave, lane = tid % kWave;
@@ -359,78 +535,41 @@ __global__ __launch_bounds__(256, 2) void pme_adjoint(const KParams p) {
   for (int ci = 0; ci < kPmeNCW; ++ci) {
     const int c = cg * kPmeNCW + ci;
     if (c >= p.nchan) break;
-    // ---- fragments of M_k for rows (32 P + row) and the q range ------------
-    const int64_t base = ((static_cast<int64_t>(t) * p.nchan + c) * p.npair * 4 + k) *
-                         (kPmeBlk * kPmeBlk);
-    // base + pair * 4 * 1024 addresses T_k of that pair
-    // M_k[32 P + row][q] for the four q of element group e of K-step st
-    auto fetch = [&](int st, int e) -> float2 {
-      const int ql = 8 * st + 4 * g;  // first of four q (local to the range)
-      const int qb = Q0 + ql / kPmeBlk;
-      const int j = ql % kPmeBlk + e;
-      if (qb == P) {
-        const int pr = p.pair_of[P * nP + P];
-        const float2 a = rho_at(p, base, pr, row, j);
-        const float2 b = rho_at(p, base, pr, j, row);
-        return make_float2(a.x + b.x, a.y - b.y);
-      }
-      if (P < qb) return rho_at(p, base, p.pair_of[P * nP + qb], row, j);
-      const float2 b = rho_at(p, base, p.pair_of[qb * nP + P], j, row);
-      return make_float2(b.x, -b.y);
-    };
-    float mx = 0.0f;
-    for (int st = 0; st < nq * 4; ++st) {
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const float2 v = fetch(st, e);
-        mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
-      }
-    }
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, kWave));
-    __syncthreads();  // previous channel's s_gmax readers are done
-    if (lane == 0) s_gmax[wave] = mx;
-    __syncthreads();
-    const float gmax = fmaxf(fmaxf(s_gmax[0], s_gmax[1]), fmaxf(s_gmax[2], s_gmax[3]));
-    if (gmax == 0.0f) continue;  // uniform across the workgroup
-    int ex = 0;
-    frexpf(gmax, &ex);
-    const float scl = ldexpf(1.0f, -ex);
-    const float unscl = ldexpf(1.0f, ex);
+    const int64_t fitem = ((static_cast<int64_t>(tt) * p.nchan + c) * nP + P) * nQR + qr;
+    const float unscl = p.mscale[fitem];
+    if (unscl == 0.0f) continue;  // the residual of this block row is zero
     half8 mh[kPmeNQ * 4], ml[kPmeNQ * 4];
+    {
+      const uint4 *src = p.mfrag + ((fitem * 4 + k) * (kPmeNQ * 4) * kWave) * 2;
 #pragma unroll
-    for (int st = 0; st < kPmeNQ * 4; ++st) {
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        float2 v = make_float2(0.0f, 0.0f);
-        if (st < nq * 4) v = fetch(st, e);
-        _Float16 rh, rl, ih, il;
-        split_h(v.x * scl, rh, rl);
-        split_h(v.y * scl, ih, il);
-        mh[st][2 * e] = rh;
-        mh[st][2 * e + 1] = ih;
-        ml[st][2 * e] = rl;
-        ml[st][2 * e + 1] = il;
+      for (int st = 0; st < kPmeNQ * 4; ++st) {
+        uint4 h = make_uint4(0, 0, 0, 0), l = h;
+        if (st < nq * 4) {
+          h = src[(st * kWave + lane) * 2];
+          l = src[(st * kWave + lane) * 2 + 1];
+        }
+        mh[st] = __builtin_bit_cast(half8, h);
+        ml[st] = __builtin_bit_cast(half8, l);
       }
     }
     const uint32_t *hi0 = p.ph_hi + (static_cast<int64_t>(tt) * p.nchan + c) * plane;
     const uint32_t *lo0 = p.ph_lo + (static_cast<int64_t>(tt) * p.nchan + c) * plane;
+    const float *k30 =
+        p.beam ? p.ph_k3 + (static_cast<int64_t>(tt) * p.nchan + c) * plane : nullptr;
     const float4 *stk = static_cast<const float4 *>(p.src_st);
-    const double nuc = p.nu_c[c];
-    const float tpnc = static_cast<float>(2.0 * kPi * nuc);
-    const double lnfr = p.lnfr[c];
-    const double bs = p.beam_k * (p.beam ? p.bfr[c] : 0.0);
-    const double clip_r2 = p.beam ? p.clip_r2[c] : 0.0;
-    const float k3s = static_cast<float>(-3.0 * bs * bs);
+    const float tpnc = static_cast<float>(2.0 * kPi * p.nu_c[c]);
+    const float lnfr = static_cast<float>(p.lnfr[c]);
 
     for (int s0 = sbeg; s0 < send; s0 += kPmeCh) {
       const int cnt = min(kPmeCh, send - s0);
       __syncthreads();  // LDS of the previous chunk is consumed
       {
-        // B operand rows: a of the q range for 32 sources; a_p in float32
+        // B operand rows: a of the q range for 32 sources; block P in float32
         const int s = tid >> 3, part = tid & 7;
         uint4 h0 = make_uint4(0, 0, 0, 0), h1 = h0, l0 = h0, l1 = h0;
         uint4 ph = h0, pl = h0;
+        float4 k3 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        double sl = 0.0, sm = 0.0;
         if (s < cnt) {
           const int64_t rowoff = static_cast<int64_t>(s0 + s) * p.nap;
           const int q0 = Q0 * kPmeBlk + part * 8;  // 8 antennas per thread
@@ -442,6 +581,12 @@ __global__ __launch_bounds__(256, 2) void pme_adjoint(const KParams p) {
           }
           ph = *reinterpret_cast<const uint4 *>(hi0 + rowoff + P * kPmeBlk + part * 4);
           pl = *reinterpret_cast<const uint4 *>(lo0 + rowoff + P * kPmeBlk + part * 4);
+          if (k30) {
+            k3 = *reinterpret_cast<const float4 *>(k30 + rowoff + P * kPmeBlk + part * 4);
+            const double4 geo = p.src_geo[sd.src_off + s0 + s];
+            sl = geo.x;
+            sm = geo.y;
+          }
         }
         uint4 *bh = reinterpret_cast<uint4 *>(&s_bh[s][part * 16]);
         uint4 *bl = reinterpret_cast<uint4 *>(&s_bl[s][part * 16]);
@@ -450,10 +595,14 @@ __global__ __launch_bounds__(256, 2) void pme_adjoint(const KParams p) {
         bl[0] = l0;
         bl[1] = l1;
         const uint32_t phw[4] = {ph.x, ph.y, ph.z, ph.w}, plw[4] = {pl.x, pl.y, pl.z, pl.w};
+        const float k3v[4] = {k3.x, k3.y, k3.z, k3.w};
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          s_ap[part * 4 + j][s] =
-              make_float2(lo_h(phw[j]) + lo_h(plw[j]), hi_h(phw[j]) + hi_h(plw[j]));
+        for (int j = 0; j < 4; ++j) {
+          const int i = part * 4 + j;
+          s_ap[i][s] = make_float2(lo_h(phw[j]) + lo_h(plw[j]), hi_h(phw[j]) + hi_h(plw[j]));
+          s_betl[i][s] = k3v[j] * static_cast<float>(sl - s_pnt[i][0]);
+          s_betm[i][s] = k3v[j] * static_cast<float>(sm - s_pnt[i][1]);
+        }
       }
       __syncthreads();
       floatx16 accR, accI;
@@ -477,116 +626,62 @@ __global__ __launch_bounds__(256, 2) void pme_adjoint(const KParams p) {
             rl[2 * e + 1] = -ml[st][2 * e];
           }
           accR = __builtin_amdgcn_mfma_f32_32x32x16_f16(mh[st], bh, accR, 0, 0, 0);
-          accR = __builtin_amdgcn_mfma_f32_32x32x16_f16(mh[st], bl, accR, 0, 0, 0);
-          accR = __builtin_amdgcn_mfma_f32_32x32x16_f16(ml[st], bh, accR, 0, 0, 0);
           accI = __builtin_amdgcn_mfma_f32_32x32x16_f16(rh, bh, accI, 0, 0, 0);
+          accR = __builtin_amdgcn_mfma_f32_32x32x16_f16(mh[st], bl, accR, 0, 0, 0);
           accI = __builtin_amdgcn_mfma_f32_32x32x16_f16(rh, bl, accI, 0, 0, 0);
+          accR = __builtin_amdgcn_mfma_f32_32x32x16_f16(ml[st], bh, accR, 0, 0, 0);
           accI = __builtin_amdgcn_mfma_f32_32x32x16_f16(rl, bh, accI, 0, 0, 0);
         }
       }
-      // Z_k[p][s] (scaled) in lane (s = row, p = i(r)) ------------------------
-      float4 st4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      if (row < cnt) st4 = stk[(sd.src_off + s0 + row) * p.nchan + c];
-      const float stk_k = k == 0 ? st4.x : k == 1 ? st4.y : k == 2 ? st4.z : st4.w;
-      float gk = 0.0f;
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int i = (r & 3) + 8 * (r >> 2) + 4 * g;
-        const float2 a = s_ap[i][row];
-        gk += a.x * accR[r];
-        gk -= a.y * accI[r];
-      }
-      gk += __shfl_xor(gk, 32, kWave);
-      if (g == 0) s_g[k][row] = gk;
-      // W partial sums: wavefronts add St'_k Z_k in a fixed order
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        if (k == kk) {
-#pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            const int i = (r & 3) + 8 * (r >> 2) + 4 * g;
-            float2 w = make_float2(stk_k * accR[r], stk_k * accI[r]);
-            if (kk > 0) {
-              const float2 o = s_w[i][row];
-              w.x += o.x;
-              w.y += o.y;
-            }
-            s_w[i][row] = w;
-          }
-        }
-        __syncthreads();
-      }
-      // phase and beam sums over the antennas p of block P -------------------
+      // reductions of a_ps Z_k[p][s] over this lane's 16 antennas p --------
       {
-        const int s = tid & 31, pg = tid >> 5;
-        float g5 = 0.0f, g6 = 0.0f, g7 = 0.0f, g8 = 0.0f, g9 = 0.0f;
-        if (s < cnt) {
-          const double4 geo = p.src_geo[sd.src_off + s0 + s];
+        float o[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int i = pg * 4 + e;
-            const float2 a = s_ap[i][s];
-            const float2 z = s_w[i][s];
-            const float wr = a.x * z.x - a.y * z.y;
-            const float wi = a.x * z.y + a.y * z.x;
-            g7 += s_uvw[i][0] * wi;
-            g8 += s_uvw[i][1] * wi;
-            g9 += s_uvw[i][2] * wi;
-            if (p.beam) {
-              // d ln e / d(l, m) as in the per-baseline adjoint
-              const double dl = geo.x - s_pnt[i][0];
-              const double dm = geo.y - s_pnt[i][1];
-              const double r2b = sumsq_rn(dl, dm);
-              const bool clipped = r2b >= clip_r2;
-              if (!clipped) {
-                const float rb = N::sqrt_(r2b);
-                const float xr = static_cast<float>(bs) * rb;
-                float sb, cb;
-                N::sincos_rad(xr, &sb, &cb);
-                const float tx = xr > 1e-4f ? sb * N::rcp(cb * xr) : 1.0f + xr * xr / 3.0f;
-                const float k3 = k3s * tx;
-                g5 += k3 * static_cast<float>(dl) * wr;
-                g6 += k3 * static_cast<float>(dm) * wr;
-              }
-            }
-          }
+        for (int r = 0; r < 16; ++r) {
+          const int i = (r & 3) + 8 * (r >> 2) + 4 * g;
+          const float2 a = s_ap[i][row];
+          const float wr = a.x * accR[r] - a.y * accI[r];
+          const float wi = a.x * accI[r] + a.y * accR[r];
+          o[0] += wr;
+          o[1] += s_uvw[i][0] * wi;
+          o[2] += s_uvw[i][1] * wi;
+          o[3] += s_uvw[i][2] * wi;
+          o[4] += s_betl[i][row] * wr;
+          o[5] += s_betm[i][row] * wr;
         }
-        g5 += __shfl_xor(g5, 32, kWave);
-        g6 += __shfl_xor(g6, 32, kWave);
-        g7 += __shfl_xor(g7, 32, kWave);
-        g8 += __shfl_xor(g8, 32, kWave);
-        g9 += __shfl_xor(g9, 32, kWave);
+#pragma unroll
+        for (int j = 0; j < 6; ++j) o[j] += __shfl_xor(o[j], 32, kWave);
         if (g == 0) {
-          s_red[wave][s][0] = g5;
-          s_red[wave][s][1] = g6;
-          s_red[wave][s][2] = g7;
-          s_red[wave][s][3] = g8;
-          s_red[wave][s][4] = g9;
+#pragma unroll
+          for (int j = 0; j < 6; ++j) s_out[k][row][j] = o[j];
         }
       }
       __syncthreads();
       if (tid < cnt) {
         const int s = tid;
-        float gs[5];
-#pragma unroll
-        for (int j = 0; j < 5; ++j)
-          gs[j] = unscl * (((s_red[0][s][j] + s_red[1][s][j]) + s_red[2][s][j]) + s_red[3][s][j]);
-        float G[4];
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) G[kk] = 0.5f * unscl * s_g[kk][s];
         const float4 sv = stk[(sd.src_off + s0 + s) * p.nchan + c];
+        const float stv[4] = {sv.x, sv.y, sv.z, sv.w};
+        float G[4], h[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          G[kk] = 0.5f * unscl * s_out[kk][s][0];
+#pragma unroll
+          for (int j = 0; j < 5; ++j) h[j] += stv[kk] * s_out[kk][s][1 + j];
+        }
+#pragma unroll
+        for (int j = 0; j < 5; ++j) h[j] *= unscl;
+        // h = (sum u Im W, sum v Im W, sum w Im W, sum beta_l Re W, sum beta_m Re W)
         const double2 lo = p.src_lon[sd.src_off + s0 + s];
-        const float f = static_cast<float>(exp(sd.alpha[s0 + s] * lnfr));
+        const float f = p.src_f[(sd.src_off + s0 + s) * p.nchan + c];
         const float lon = static_cast<float>(lo.x), mon = static_cast<float>(lo.y);
         float *acc = s_acc[s0 + s - sbeg];
-        acc[0] += gs[0] + tpnc * (gs[2] - lon * gs[4]);
-        acc[1] += gs[1] + tpnc * (gs[3] - mon * gs[4]);
+        acc[0] += h[3] + tpnc * (h[0] - lon * h[2]);
+        acc[1] += h[4] + tpnc * (h[1] - mon * h[2]);
         acc[2] += G[0] * f;
         acc[3] += G[1] * f;
         acc[4] += G[2] * f;
         acc[5] += G[3] * f;
-        acc[6] += (sv.x * G[0] + sv.y * G[1] + sv.z * G[2] + sv.w * G[3]) *
-                  static_cast<float>(lnfr);
+        acc[6] += (stv[0] * G[0] + stv[1] * G[1] + stv[2] * G[2] + stv[3] * G[3]) * lnfr;
       }
     }
   }
@@ -617,13 +712,39 @@ __global__ __launch_bounds__(256) void pme_finalize(const KParams p) {
   if (threadIdx.x < 3) p.grad_out[(p.one.src_off + s) * 10 + 7 + threadIdx.x] = 0.0;
 }
 
-hipError_t launch_pme_adjoint(const KParams &p, hipStream_t stream) {
+// ---------------------------------------------------------------------------
+// Launchers (timesteps [p.pme_t0, p.pme_t0 + p.pme_nt))
+// ---------------------------------------------------------------------------
+static hipError_t launch_phase(const KParams &p, hipStream_t stream) {
   const int64_t plane = static_cast<int64_t>(p.one.npsrc) * p.nap;
-  if (plane <= 0 || p.pme_nt <= 0) return hipSuccess;
   dim3 g1(static_cast<unsigned>((plane + 255) / 256), static_cast<unsigned>(p.pme_nt));
   hipLaunchKernelGGL(pme_phase, g1, dim3(256), 0, stream, p);
-  hipError_t e = hipGetLastError();
+  return hipGetLastError();
+}
+
+hipError_t launch_pme_scale(const KParams &p, hipStream_t stream) {
+  if (p.one.npsrc <= 0) return hipSuccess;
+  hipLaunchKernelGGL(pme_scale, dim3(p.nchan), dim3(256), 0, stream, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_pme(const KParams &p, hipStream_t stream) {
+  if (p.one.npsrc <= 0 || p.pme_nt <= 0) return hipSuccess;
+  hipError_t e = launch_phase(p, stream);
   if (e != hipSuccess) return e;
+  const int64_t nitems = static_cast<int64_t>(p.pme_nt) * p.nchan * p.ngroup;
+  const int64_t grid = 8 * ((nitems + 7) / 8);
+  hipLaunchKernelGGL(pme_forward, dim3(static_cast<unsigned>(grid)), dim3(256), 0, stream, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_pme_adjoint(const KParams &p, hipStream_t stream) {
+  if (p.one.npsrc <= 0 || p.pme_nt <= 0) return hipSuccess;
+  hipError_t e = launch_phase(p, stream);
+  if (e != hipSuccess) return e;
+  const int64_t nfrag = static_cast<int64_t>(p.pme_nt) * p.nchan * p.nblk * p.pme_nqr;
+  hipLaunchKernelGGL(pme_mfrag, dim3(static_cast<unsigned>(nfrag)), dim3(256), 0, stream, p);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   const int64_t nitems =
       static_cast<int64_t>(p.pme_nsr) * p.pme_nt * p.pme_ncg * p.nblk * p.pme_nqr;
   const int64_t grid = 8 * ((nitems + 7) / 8);
@@ -634,20 +755,6 @@ hipError_t launch_pme_adjoint(const KParams &p, hipStream_t stream) {
 hipError_t launch_pme_finalize(const KParams &p, hipStream_t stream) {
   if (p.one.npsrc <= 0) return hipSuccess;
   hipLaunchKernelGGL(pme_finalize, dim3(p.one.npsrc), dim3(256), 0, stream, p);
-  return hipGetLastError();
-}
-
-// Phase planes and antenna-pair sums for timesteps [p.pme_t0, p.pme_t0 + p.pme_nt).
-hipError_t launch_pme(const KParams &p, hipStream_t stream) {
-  const int64_t plane = static_cast<int64_t>(p.one.npsrc) * p.nap;
-  if (plane <= 0 || p.pme_nt <= 0) return hipSuccess;
-  dim3 g1(static_cast<unsigned>((plane + 255) / 256), static_cast<unsigned>(p.pme_nt));
-  hipLaunchKernelGGL(pme_phase, g1, dim3(256), 0, stream, p);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const int64_t nitems = static_cast<int64_t>(p.pme_nt) * p.nchan * p.npair;
-  const int64_t grid = 8 * ((nitems + 7) / 8);
-  hipLaunchKernelGGL(pme_forward, dim3(static_cast<unsigned>(grid)), dim3(256), 0, stream, p);
   return hipGetLastError();
 }
 

@@ -44,8 +44,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Published MI355X peaks (dense): FP32 vector 157.3 TFLOP/s, FP64 vector 78.6.
-PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
+# Published MI355X peaks (dense): FP32 vector 157.3 TFLOP/s, FP64 vector 78.6,
+# fp16 matrix 2.5 PFLOP/s.
+PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6, "f16_mfma": 2500.0}
 
 # Algorithmic flops per source x visibility term (4 correlations), minimal
 # formulation: forward point 22, forward Gaussian 25 (+1 exp); adjoint point
@@ -178,34 +179,76 @@ def roofline(flops, kernel_ms, variant, traffic):
             "kernel_ms": kernel_ms, "flops_per_launch": flops}
 
 
-def timed(call, steps, warmup, events_fn=None):
+def rooflines(g, tp, tg, obs, sky, traffic):
+    """Roofline objects of one chi^2 + gradient call.  Without the matrix
+    cores the per-baseline kernel does all the work: VALU-bound, algorithmic
+    flops of all terms over its time.  With them it does the Gaussian sources
+    (algorithmic flops of the Gaussian terms over its time) and the point
+    sources run on the matrix cores (executed fp16 MFMA flops over the time of
+    those kernels, against the dense fp16 peak); the larger time is the
+    dominant kernel and goes in "roofline", the other in "roofline_other"."""
+    main = roofline(alg_flops(0 if g["matrix_cores"] else tp, tg), g["main_ms"], g["variant"],
+                    traffic)
+    main["kernel_ms"] = g["main_ms"]
+    if not g["matrix_cores"]:
+        return {"roofline": main}
+    mc_ms = g["kernel_ms"] - g["main_ms"]
+    fl = mfma_flops(obs, sky.npsrc)
+    ach = fl / (mc_ms * 1e-3) / 1e12
+    mc = {"bound": "mfma", "achieved": ach, "peak": PEAK_TFLOPS["f16_mfma"], "unit": "TFLOP/s",
+          "frac": ach / PEAK_TFLOPS["f16_mfma"], "traffic": None,
+          "kernel": "pme_phase + pme_forward + pme_mfrag + pme_adjoint (point sources)",
+          "kernel_ms": mc_ms, "flops_per_launch": fl}
+    main["kernel"] += " (Gaussian sources)"
+    if mc_ms > g["main_ms"]:
+        return {"roofline": mc, "roofline_other": main}
+    return {"roofline": main, "roofline_other": mc}
+
+
+def timed(call, steps, warmup, events_fns=()):
     """Mean ms per call over `steps` timed calls after `warmup` untimed ones.
-    `events_fn(start, stop)` installs per-call kernel timing events (or
-    removes them with None, None); returns (ms, kernel_ms or None)."""
+    Each of `events_fns` is a setter `fn(start, stop)` installing a pair of
+    per-call timing events in the library (None, None removes it); returns
+    (ms, [mean ms between each pair])."""
     import torch
     for _ in range(warmup):
         call()
     torch.cuda.synchronize()
-    ks = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
-    ke = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
-    # torch creates the underlying hipEvent on first record: record each once
-    # so that the handles passed to the library are valid
-    for e in ks + ke:
-        e.record()
+    evs = []
+    for _ in events_fns:
+        ks = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+        ke = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+        # torch creates the underlying hipEvent on first record: record each
+        # once so that the handles passed to the library are valid
+        for e in ks + ke:
+            e.record()
+        evs.append((ks, ke))
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     start.record()
     for i in range(steps):
-        if events_fn:
-            events_fn(ks[i], ke[i])
+        for fn, (ks, ke) in zip(events_fns, evs):
+            fn(ks[i], ke[i])
         call()
     stop.record()
     torch.cuda.synchronize()
-    if events_fn:
-        events_fn(None, None)
+    for fn in events_fns:
+        fn(None, None)
     ms = start.elapsed_time(stop) / steps
-    kms = float(np.mean([ks[i].elapsed_time(ke[i]) for i in range(steps)])) if events_fn else None
+    kms = [float(np.mean([ks[i].elapsed_time(ke[i]) for i in range(steps)])) for ks, ke in evs]
     return ms, kms
+
+
+def mfma_flops(obs, npsrc):
+    """fp16 matrix-core flops one chi^2 + gradient call executes with a
+    matrix-core variant: per (timestep, channel) and 32-source chunk, the
+    forward runs 4 Stokes x 6 products x 4 K-steps per antenna-pair tile and
+    the adjoint 4 x 6 x 4 per (P block, q block); 32x32x16 = 32768 flops."""
+    nblk = (obs.na + 31) // 32
+    pairs = {(min(a // 32, b // 32), max(a // 32, b // 32)) for a, b in zip(obs.ant1, obs.ant2)}
+    nch = (npsrc + 31) // 32
+    per_slice = 96 * nch * (len(pairs) + nblk * nblk)
+    return per_slice * obs.ntime * obs.nchan * 32768
 
 
 def upload_data(R, plan, truth, noise, weight):
@@ -288,8 +331,11 @@ def bench_single(args):
             else:
                 R.rime_chi2(plan, dsky, prec, D, W, chi2, wsp)
 
-        ms, kms = timed(call, steps, warmup, plan.set_timing_events)
-        return {"ms_per_step": ms, "kernel_ms": kms, "chi2": chi2.item(), "variant": variant,
+        ms, (kms, mms) = timed(call, steps, warmup,
+                               (plan.set_timing_events, plan.set_main_events))
+        mc = R.rime_variant_matrix_cores(mode, prec, plan.get_variant(mode, prec))
+        return {"ms_per_step": ms, "kernel_ms": kms, "main_ms": mms, "chi2": chi2.item(),
+                "variant": variant, "matrix_cores": mc,
                 "terms_per_s": terms / (ms * 1e-3), "evals_per_s": 1e3 / ms}
 
     out = {}
@@ -307,7 +353,8 @@ def bench_single(args):
         log(m, out[m])
 
     g = out["grad_mixed"]
-    traffic = measured_traffic(args.traffic, list(g["variant"]), args.config)
+    traffic = measured_traffic(args.traffic, list(g["variant"]) + [int(g["matrix_cores"])],
+                               args.config)
     rec = base_record(
         args, "source x visibility terms/s (chi2+grad, FP32-mixed), 1 GPU", g["terms_per_s"],
         g["ms_per_step"], "f32",
@@ -316,7 +363,8 @@ def bench_single(args):
         f"Gaussian sources, beam",
         {"terms_per_eval": terms, "precision": "mixed (FP64 phase and sums)"})
     rec["evals_per_s"] = g["evals_per_s"]
-    rec["roofline"] = roofline(alg_flops(tp, tg), g["kernel_ms"], g["variant"], traffic)
+    rec["variant"] = {"per_baseline": list(g["variant"]), "matrix_cores": g["matrix_cores"]}
+    rec.update(rooflines(g, tp, tg, obs, sky, traffic))
     if "grad_fp64" in out:
         rec["fp64"] = {"terms_per_s": out["grad_fp64"]["terms_per_s"],
                        "ms_per_step": out["grad_fp64"]["ms_per_step"],
@@ -392,7 +440,7 @@ def bench_batch(args):
     log("graph tuned", variant, res["graph_tuned"])
     # the same launches without the graph, with the main kernel timed alone
     call, ws = batched(R.MIXED, False)
-    res["stream_tuned"], kms = timed(call, args.steps, 1, plan.set_timing_events)
+    res["stream_tuned"], (kms,) = timed(call, args.steps, 1, (plan.set_timing_events,))
     log("stream tuned", res["stream_tuned"], "kernel", kms)
     del ws, call
     # per-set loop: one rime_chi2_grad call per proposal, same variant
@@ -475,7 +523,7 @@ def bench_latency(args):
         R.rime_chi2_grad(plan, dsky, R.FP64, D64, W64, chi2, grad, ws)
 
     ms_graph, _ = timed(graph_call, args.steps, args.warmup)
-    ms_plain, kms = timed(plain_call, args.steps, args.warmup, plan.set_timing_events)
+    ms_plain, (kms,) = timed(plain_call, args.steps, args.warmup, (plan.set_timing_events,))
     variant = R.rime_variant_info(R.MODE_CHI2_GRAD, R.FP64,
                                   plan.get_variant(R.MODE_CHI2_GRAD, R.FP64))
     rec = base_record(

@@ -202,12 +202,15 @@ rime_status rime_set_variant(rime_plan *plan, rime_mode mode, rime_precision pre
                              int32_t index);
 int32_t rime_get_variant(const rime_plan *plan, rime_mode mode, rime_precision prec);
 
-/* Timing hook: when start/stop are non-NULL hipEvent_t handles, every later
- * compute call on this plan records `start` immediately before and `stop`
- * immediately after its main kernel, on the call's stream (the small
- * per-source preparation and final-reduction kernels fall outside).  NULL
- * turns it off.  Used to time the dominant kernel in isolation. */
+/* Timing hooks.  When start/stop are non-NULL hipEvent_t handles, every later
+ * compute call on this plan records them on the call's stream:
+ * rime_plan_set_timing_events around all of its compute kernels (the
+ * per-baseline kernel and, with a matrix-core variant, the point-source
+ * kernels; the small per-source preparation and final-reduction kernels fall
+ * outside), rime_plan_set_main_events around the per-baseline kernel alone.
+ * NULL turns a hook off.  Used to time the kernels in isolation. */
 rime_status rime_plan_set_timing_events(rime_plan *plan, void *start, void *stop);
+rime_status rime_plan_set_main_events(rime_plan *plan, void *start, void *stop);
 
 /* Host-only view of the baseline tiling used by the kernels: every baseline
  * index appears in exactly one tile; a tile holds at most `threads`

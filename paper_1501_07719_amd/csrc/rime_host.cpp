@@ -19,7 +19,7 @@ namespace rime {
 hipError_t launch_prep(const KParams &p, bool fp64, int max_nsrc, hipStream_t stream);
 hipError_t launch_finalize(const KParams &p, int mode, int max_nsrc, hipStream_t stream);
 hipError_t launch_pme(const KParams &p, hipStream_t stream);
-hipError_t launch_pme_adjoint(const KParams &p, hipStream_t stream);
+hipError_t launch_pme_adjoint(const KParams &p, bool phase, hipStream_t stream);
 hipError_t launch_pme_finalize(const KParams &p, hipStream_t stream);
 hipError_t launch_pme_scale(const KParams &p, hipStream_t stream);
 int variant_count(int mode, int prec);
@@ -91,7 +91,8 @@ struct rime_plan {
   bool pme_adj_ok = false;  // every antenna-pair slot holds at most one baseline
   int32_t variant[3][2] = {{0, 0}, {0, 0}, {0, 0}};
   std::string signature;  // observation part of the autotune key
-  hipEvent_t ev_start = nullptr, ev_stop = nullptr;
+  hipEvent_t ev_start = nullptr, ev_stop = nullptr;        // around all compute kernels
+  hipEvent_t ev_main0 = nullptr, ev_main1 = nullptr;       // around the per-baseline kernel
 };
 
 struct GraphKey {
@@ -487,21 +488,27 @@ rime_status enqueue(const rime_plan *plan, int mode, int prec, int vidx, int nse
   if (plan->ev_start) RIME_HIP(hipEventRecord(plan->ev_start, stream));
   if (p.pme) {
     RIME_HIP(launch_pme_scale(p, stream));
-    KParams pf = p;  // the forward needs no beam-derivative plane
-    pf.ph_k3 = nullptr;
+    KParams pf = p;
+    // with one pass over time the adjoint reuses the forward's phase planes,
+    // which then carry the beam-derivative plane too
+    pf.ph_k3 = (L.pme_adj && L.ph_k3 && L.pme_tchunk >= plan->ntime)
+                   ? reinterpret_cast<float *>(w + L.ph_k3)
+                   : nullptr;
     for (int t0 = 0; t0 < plan->ntime; t0 += L.pme_tchunk) {
       pf.pme_t0 = t0;
       pf.pme_nt = std::min(L.pme_tchunk, plan->ntime - t0);
       RIME_HIP(launch_pme(pf, stream));
     }
   }
+  if (plan->ev_main0) RIME_HIP(hipEventRecord(plan->ev_main0, stream));
   RIME_HIP(launch_variant(mode, prec, vidx, p, static_cast<int>(nitems), stream));
+  if (plan->ev_main1) RIME_HIP(hipEventRecord(plan->ev_main1, stream));
   if (p.pme_adj) {
     if (L.ph_k3) p.ph_k3 = reinterpret_cast<float *>(w + L.ph_k3);
     for (int t0 = 0; t0 < plan->ntime; t0 += L.pme_tchunk) {
       p.pme_t0 = t0;
       p.pme_nt = std::min(L.pme_tchunk, plan->ntime - t0);
-      RIME_HIP(launch_pme_adjoint(p, stream));
+      RIME_HIP(launch_pme_adjoint(p, L.pme_tchunk < plan->ntime, stream));
     }
   }
   if (plan->ev_stop) RIME_HIP(hipEventRecord(plan->ev_stop, stream));
@@ -1018,6 +1025,13 @@ rime_status rime_tiling_host(int32_t na, int32_t nbl, const int32_t *ant1, const
   if (tile_bl) std::copy(hbl.begin(), hbl.end(), tile_bl);
   if (tile_lpq) std::copy(hlpq.begin(), hlpq.end(), tile_lpq);
   if (tile_ant) std::copy(hant.begin(), hant.end(), tile_ant);
+  return RIME_OK;
+}
+
+rime_status rime_plan_set_main_events(rime_plan *plan, void *start, void *stop) {
+  if (!plan || ((start == nullptr) != (stop == nullptr))) return RIME_ERR_ARG;
+  plan->ev_main0 = static_cast<hipEvent_t>(start);
+  plan->ev_main1 = static_cast<hipEvent_t>(stop);
   return RIME_OK;
 }
 

@@ -59,9 +59,17 @@ __device__ inline void split_h(float x, _Float16 &h, _Float16 &l) {
   l = static_cast<_Float16>(x - static_cast<float>(h));
 }
 
-// (re, im) -> (im, -re) on a packed fp16 pair: the row of the imaginary part
-// of a conj(b) in the real form of the complex product.
-__device__ inline uint32_t rot_h2(uint32_t w) { return (w >> 16) | ((w ^ 0x8000u) << 16); }
+// (re, im) -> (im, -re) on the four pairs of a fragment: the row of the
+// imaginary part of a conj(b) in the real form of the complex product.
+__device__ inline half8 rot8(half8 v) {
+  half8 r;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    r[2 * e] = v[2 * e + 1];
+    r[2 * e + 1] = -v[2 * e];
+  }
+  return r;
+}
 
 // Workgroups are dealt round-robin to the 8 XCDs; renumbering them makes
 // consecutive work items (which share operands through L2) land on one XCD.
@@ -216,8 +224,6 @@ __global__ __launch_bounds__(256, 2) void pme_forward(const KParams p) {
   // [P block a/b][antenna][(s, re/im)]
   __shared__ __attribute__((aligned(16))) _Float16 s_ah[2][kPmeBlk][kPmeRow];
   __shared__ __attribute__((aligned(16))) _Float16 s_al[2][kPmeBlk][kPmeRow];
-  __shared__ __attribute__((aligned(16))) _Float16 s_rh[2][kPmeBlk][kPmeRow];
-  __shared__ __attribute__((aligned(16))) _Float16 s_rl[2][kPmeBlk][kPmeRow];
   __shared__ __attribute__((aligned(16))) _Float16 s_bh[4][kPmeBlk][kPmeRow];
   __shared__ __attribute__((aligned(16))) _Float16 s_bl[4][kPmeBlk][kPmeRow];
 
@@ -268,13 +274,9 @@ __global__ __launch_bounds__(256, 2) void pme_forward(const KParams p) {
       for (int j = 0; j < 4; ++j) {
         *reinterpret_cast<uint32_t *>(&s_ah[0][ag + j][2 * s]) = w0[j];
         *reinterpret_cast<uint32_t *>(&s_al[0][ag + j][2 * s]) = w1[j];
-        *reinterpret_cast<uint32_t *>(&s_rh[0][ag + j][2 * s]) = rot_h2(w0[j]);
-        *reinterpret_cast<uint32_t *>(&s_rl[0][ag + j][2 * s]) = rot_h2(w1[j]);
         if (Pb >= 0) {
           *reinterpret_cast<uint32_t *>(&s_ah[1][ag + j][2 * s]) = w2[j];
           *reinterpret_cast<uint32_t *>(&s_al[1][ag + j][2 * s]) = w3[j];
-          *reinterpret_cast<uint32_t *>(&s_rh[1][ag + j][2 * s]) = rot_h2(w2[j]);
-          *reinterpret_cast<uint32_t *>(&s_rl[1][ag + j][2 * s]) = rot_h2(w3[j]);
         }
         const float ar = lo_h(wq[j]) + lo_h(wl[j]);
         const float ai = hi_h(wq[j]) + hi_h(wl[j]);
@@ -303,8 +305,7 @@ __global__ __launch_bounds__(256, 2) void pme_forward(const KParams p) {
       {
         const half8 ah = *reinterpret_cast<const half8 *>(&s_ah[0][row][col]);
         const half8 al = *reinterpret_cast<const half8 *>(&s_al[0][row][col]);
-        const half8 rh = *reinterpret_cast<const half8 *>(&s_rh[0][row][col]);
-        const half8 rl = *reinterpret_cast<const half8 *>(&s_rl[0][row][col]);
+        const half8 rh = rot8(ah), rl = rot8(al);
         aR0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bh, aR0, 0, 0, 0);
         aI0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(rh, bh, aI0, 0, 0, 0);
         aR0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bl, aR0, 0, 0, 0);
@@ -315,8 +316,7 @@ __global__ __launch_bounds__(256, 2) void pme_forward(const KParams p) {
       if (Pb >= 0) {
         const half8 ah = *reinterpret_cast<const half8 *>(&s_ah[1][row][col]);
         const half8 al = *reinterpret_cast<const half8 *>(&s_al[1][row][col]);
-        const half8 rh = *reinterpret_cast<const half8 *>(&s_rh[1][row][col]);
-        const half8 rl = *reinterpret_cast<const half8 *>(&s_rl[1][row][col]);
+        const half8 rh = rot8(ah), rl = rot8(al);
         aR1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bh, aR1, 0, 0, 0);
         aI1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(rh, bh, aI1, 0, 0, 0);
         aR1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bl, aR1, 0, 0, 0);
@@ -617,14 +617,7 @@ __global__ __launch_bounds__(256, 2) void pme_adjoint(const KParams p) {
           const int col = 16 * st + 8 * g;
           const half8 bh = *reinterpret_cast<const half8 *>(&s_bh[row][col]);
           const half8 bl = *reinterpret_cast<const half8 *>(&s_bl[row][col]);
-          half8 rh, rl;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            rh[2 * e] = mh[st][2 * e + 1];
-            rh[2 * e + 1] = -mh[st][2 * e];
-            rl[2 * e] = ml[st][2 * e + 1];
-            rl[2 * e + 1] = -ml[st][2 * e];
-          }
+          const half8 rh = rot8(mh[st]), rl = rot8(ml[st]);
           accR = __builtin_amdgcn_mfma_f32_32x32x16_f16(mh[st], bh, accR, 0, 0, 0);
           accI = __builtin_amdgcn_mfma_f32_32x32x16_f16(rh, bh, accI, 0, 0, 0);
           accR = __builtin_amdgcn_mfma_f32_32x32x16_f16(mh[st], bl, accR, 0, 0, 0);
@@ -738,9 +731,9 @@ hipError_t launch_pme(const KParams &p, hipStream_t stream) {
   return hipGetLastError();
 }
 
-hipError_t launch_pme_adjoint(const KParams &p, hipStream_t stream) {
+hipError_t launch_pme_adjoint(const KParams &p, bool phase, hipStream_t stream) {
   if (p.one.npsrc <= 0 || p.pme_nt <= 0) return hipSuccess;
-  hipError_t e = launch_phase(p, stream);
+  hipError_t e = phase ? launch_phase(p, stream) : hipSuccess;
   if (e != hipSuccess) return e;
   const int64_t nfrag = static_cast<int64_t>(p.pme_nt) * p.nchan * p.nblk * p.pme_nqr;
   hipLaunchKernelGGL(pme_mfrag, dim3(static_cast<unsigned>(nfrag)), dim3(256), 0, stream, p);

@@ -100,6 +100,7 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "rime_set_variant": (i32, [vp, i32, i32, i32]),
         "rime_get_variant": (i32, [vp, i32, i32]),
         "rime_plan_set_timing_events": (i32, [vp, vp, vp]),
+        "rime_plan_set_main_events": (i32, [vp, vp, vp]),
         "rime_tiling_host": (i32, [i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), i32, i32,
                                    ctypes.POINTER(i32), ctypes.POINTER(i32),
                                    ctypes.POINTER(i32), ctypes.POINTER(i32)]),
@@ -204,6 +205,16 @@ class Plan:
         e = ctypes.c_void_p(stop.cuda_event) if stop is not None else None
         _check(self._lib.rime_plan_set_timing_events(self.handle, s, e),
                "rime_plan_set_timing_events")
+
+    def set_main_events(self, start=None, stop=None):
+        """torch.cuda.Event pair recorded around the per-baseline kernel alone
+        (same creation rule as set_timing_events)."""
+        for ev in (start, stop):
+            if ev is not None and not ev.cuda_event:
+                raise ValueError("timing event has no hipEvent yet: record() it once first")
+        s = ctypes.c_void_p(start.cuda_event) if start is not None else None
+        e = ctypes.c_void_p(stop.cuda_event) if stop is not None else None
+        _check(self._lib.rime_plan_set_main_events(self.handle, s, e), "rime_plan_set_main_events")
 
 
 @dataclass

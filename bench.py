@@ -146,7 +146,7 @@ def kernel_source_digest():
     for the exact code they were taken on."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("rime_kernels.hip", "rime_internal.h"):
+    for f in ("rime_kernels.hip", "rime_pme.hip", "rime_device.h", "rime_internal.h"):
         with open(os.path.join(ROOT, "paper_1501_07719_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()

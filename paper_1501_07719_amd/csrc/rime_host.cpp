@@ -546,11 +546,12 @@ rime_status single(const rime_plan *plan, int mode, rime_precision prec, const r
 
 int default_variant(const rime_plan *plan, int mode, int prec) {
   // index layout of the compiled variants: 0 -> 64 threads, 1 -> 256, 2 -> 1024
-  // (FP64 adjoint: 2 -> 256 threads x 4 channels, the fastest on 64 antennas)
+  // (FP64 adjoint: 2 -> 256 threads x 4 channels, the fastest on 64 antennas);
+  // float32-mixed 4 / 5 -> 1024 / 256 threads with the point sources on the
+  // matrix cores (measured faster from 64 antennas up)
   if (plan->nbl <= 96) return 0;
-  if (mode == RIME_MODE_CHI2_GRAD && prec == RIME_FP64) return 2;
-  if (plan->nbl >= 1024 && prec == RIME_MIXED) return 2;
-  return 1;
+  if (prec == RIME_FP64) return 1 + (mode == RIME_MODE_CHI2_GRAD ? 1 : 0);
+  return plan->nbl >= 1024 ? 4 : 5;
 }
 
 std::string sky_signature(const rime_sky *sky) {

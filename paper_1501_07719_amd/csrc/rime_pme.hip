@@ -198,15 +198,24 @@ __device__ inline FwdRegs fwd_load(const KParams &p, const uint32_t *hi0, const 
   r.pah = r.pal = r.pbh = r.pbl = r.qh = r.ql = make_uint4(0, 0, 0, 0);
   r.st = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   if (s < cnt) {
+    // a P block equal to the Q block (a diagonal tile) reuses the Q operands
     const int64_t row = static_cast<int64_t>(s0 + s) * p.nap;
-    r.pah = *reinterpret_cast<const uint4 *>(hi0 + row + Pa * kPmeBlk + ag);
-    r.pal = *reinterpret_cast<const uint4 *>(lo0 + row + Pa * kPmeBlk + ag);
-    if (Pb >= 0) {
+    r.qh = *reinterpret_cast<const uint4 *>(hi0 + row + Q * kPmeBlk + ag);
+    r.ql = *reinterpret_cast<const uint4 *>(lo0 + row + Q * kPmeBlk + ag);
+    if (Pa == Q) {
+      r.pah = r.qh;
+      r.pal = r.ql;
+    } else {
+      r.pah = *reinterpret_cast<const uint4 *>(hi0 + row + Pa * kPmeBlk + ag);
+      r.pal = *reinterpret_cast<const uint4 *>(lo0 + row + Pa * kPmeBlk + ag);
+    }
+    if (Pb == Q) {
+      r.pbh = r.qh;
+      r.pbl = r.ql;
+    } else if (Pb >= 0) {
       r.pbh = *reinterpret_cast<const uint4 *>(hi0 + row + Pb * kPmeBlk + ag);
       r.pbl = *reinterpret_cast<const uint4 *>(lo0 + row + Pb * kPmeBlk + ag);
     }
-    r.qh = *reinterpret_cast<const uint4 *>(hi0 + row + Q * kPmeBlk + ag);
-    r.ql = *reinterpret_cast<const uint4 *>(lo0 + row + Q * kPmeBlk + ag);
     r.st = static_cast<const float4 *>(p.src_st)[(p.one.src_off + s0 + s) * p.nchan + c];
   }
   return r;
@@ -253,9 +262,9 @@ __global__ __launch_bounds__(256, 2) void pme_forward(const KParams p) {
   }
 
   const int nchunk = (sd.npsrc + kPmeCh - 1) / kPmeCh;
-  FwdRegs nx = fwd_load(p, hi0, lo0, c, 0, min(kPmeCh, sd.npsrc), Q, Pa, Pb);
   for (int ch = 0; ch < nchunk; ++ch) {
-    const FwdRegs cur = nx;
+    const FwdRegs cur =
+        fwd_load(p, hi0, lo0, c, ch * kPmeCh, min(kPmeCh, sd.npsrc - ch * kPmeCh), Q, Pa, Pb);
     __syncthreads();  // the previous chunk's fragments are consumed
     {
       const int s = tid >> 3, ag = (tid & 7) * 4;
@@ -291,11 +300,6 @@ __global__ __launch_bounds__(256, 2) void pme_forward(const KParams p) {
       }
     }
     __syncthreads();
-    if (ch + 1 < nchunk) {
-      // the next chunk's operands are in flight during this chunk's products
-      const int s1 = (ch + 1) * kPmeCh;
-      nx = fwd_load(p, hi0, lo0, c, s1, min(kPmeCh, sd.npsrc - s1), Q, Pa, Pb);
-    }
 #pragma unroll
     for (int step = 0; step < kPmeCh / 8; ++step) {
       // K index (s, re/im) with s = 8 step + 4 g + e / 2 for element e
@@ -508,6 +512,7 @@ __global__ __launch_bounds__(256, 2) void pme_adjoint(const KParams p) {
   const int k = wave;
   const int row = lane & 31, g = lane >> 5;
   const int64_t plane = static_cast<int64_t>(sd.npsrc) * p.nap;
+  const bool p_in_range = P >= Q0 && P < Q0 + nq;
 
   for (int i = tid; i < kPmeSR * 7; i += 256) (&s_acc[0][0])[i] = 0.0f;
   if (tid < kPmeBlk) {
@@ -579,8 +584,10 @@ __global__ __launch_bounds__(256, 2) void pme_adjoint(const KParams p) {
             l0 = *reinterpret_cast<const uint4 *>(lo0 + rowoff + q0);
             l1 = *reinterpret_cast<const uint4 *>(lo0 + rowoff + q0 + 4);
           }
-          ph = *reinterpret_cast<const uint4 *>(hi0 + rowoff + P * kPmeBlk + part * 4);
-          pl = *reinterpret_cast<const uint4 *>(lo0 + rowoff + P * kPmeBlk + part * 4);
+          if (!p_in_range) {
+            ph = *reinterpret_cast<const uint4 *>(hi0 + rowoff + P * kPmeBlk + part * 4);
+            pl = *reinterpret_cast<const uint4 *>(lo0 + rowoff + P * kPmeBlk + part * 4);
+          }
           if (k30) {
             k3 = *reinterpret_cast<const float4 *>(k30 + rowoff + P * kPmeBlk + part * 4);
             const double4 geo = p.src_geo[sd.src_off + s0 + s];
@@ -594,12 +601,28 @@ __global__ __launch_bounds__(256, 2) void pme_adjoint(const KParams p) {
         bh[1] = h1;
         bl[0] = l0;
         bl[1] = l1;
-        const uint32_t phw[4] = {ph.x, ph.y, ph.z, ph.w}, plw[4] = {pl.x, pl.y, pl.z, pl.w};
         const float k3v[4] = {k3.x, k3.y, k3.z, k3.w};
+        if (p_in_range) {
+          // block P is part of the q range: a from the words just loaded
+          const int a0 = Q0 * kPmeBlk + part * 8 - P * kPmeBlk;  // first antenna, local to P
+          if (a0 >= 0 && a0 < kPmeBlk) {
+            const uint32_t hw[8] = {h0.x, h0.y, h0.z, h0.w, h1.x, h1.y, h1.z, h1.w};
+            const uint32_t lw[8] = {l0.x, l0.y, l0.z, l0.w, l1.x, l1.y, l1.z, l1.w};
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+              s_ap[a0 + j][s] =
+                  make_float2(lo_h(hw[j]) + lo_h(lw[j]), hi_h(hw[j]) + hi_h(lw[j]));
+          }
+        } else {
+          const uint32_t phw[4] = {ph.x, ph.y, ph.z, ph.w}, plw[4] = {pl.x, pl.y, pl.z, pl.w};
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            s_ap[part * 4 + j][s] =
+                make_float2(lo_h(phw[j]) + lo_h(plw[j]), hi_h(phw[j]) + hi_h(plw[j]));
+        }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int i = part * 4 + j;
-          s_ap[i][s] = make_float2(lo_h(phw[j]) + lo_h(plw[j]), hi_h(phw[j]) + hi_h(plw[j]));
           s_betl[i][s] = k3v[j] * static_cast<float>(sl - s_pnt[i][0]);
           s_betm[i][s] = k3v[j] * static_cast<float>(sm - s_pnt[i][1]);
         }

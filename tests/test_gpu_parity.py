@@ -98,7 +98,8 @@ def check(name, obs, sky, D, W, prec, res, ref, grad=True, scale=None):
                 if nm not in ge:
                     continue
                 rows = slice(sky.npsrc, None) if k >= 7 else slice(None)
-                kappa = max(1.0, np.linalg.norm(scale[rows, k]) / np.linalg.norm(g[rows, k]))
+                gn = np.linalg.norm(g[rows, k])
+                kappa = max(1.0, np.linalg.norm(scale[rows, k]) / gn) if gn > 0 else 1.0
                 say(name, f"{nm}: err {ge[nm]:.2e} conditioning {kappa:.1f}")
                 assert ge[nm] <= tol * kappa, (name, nm, ge[nm], kappa)
         else:
@@ -327,7 +328,8 @@ def test_autograd_function():
 @pytest.mark.parametrize("prec", [0, 1])
 def test_batched_matches_single_and_oracle(prec):
     """Batched proposals with ragged source counts (1 .. 70) equal per-set
-    calls, and two of them equal the oracle."""
+    calls of the same per-baseline kernel variant (batched calls never use the
+    matrix-core engine), and two of them equal the oracle."""
     from rime_synth import make_batch_problem
     bp = make_batch_problem(nset=7, ntime=2, nchan=4, nmin=1, nmax=70, key=41)
     obs = bp.obs
@@ -339,6 +341,12 @@ def test_batched_matches_single_and_oracle(prec):
     plan = R.Plan(obs)
     skies = [R.DeviceSky.from_host(s) for s in bp.skies]
     batch = R.rime_batch_create(plan, skies)
+    # the same per-baseline variant on both sides
+    vi = next(i for i in range(R.rime_variant_count(R.MODE_CHI2_GRAD, prec))
+              if not R.rime_variant_matrix_cores(R.MODE_CHI2_GRAD, prec, i)
+              and R.rime_variant_info(R.MODE_CHI2_GRAD, prec, i)[0] == 256)
+    R.rime_batch_set_variant(batch, R.MODE_CHI2_GRAD, prec, vi)
+    plan.set_variant(R.MODE_CHI2_GRAD, prec, vi)
     nset = len(skies)
     chi2 = torch.empty(nset, dtype=torch.float64, device="cuda")
     grad = torch.empty((batch.total_src, 10), dtype=torch.float64, device="cuda")

@@ -288,8 +288,10 @@ struct WsLayout {
   size_t total = 0;
 };
 
-// Upper bound on the two phase planes of one pass of the matrix-core engine.
-constexpr size_t kPmePlaneBytes = size_t(8) << 30;
+// Upper bound on the workspace of one time pass of the matrix-core engine (phase
+// planes and residual fragments); one pass avoids recomputing the planes for
+// the adjoint.
+constexpr size_t kPmePlaneBytes = size_t(48) << 30;
 
 int pme_ncg(const rime_plan *plan) { return (plan->nchan + kPmeNCW - 1) / kPmeNCW; }
 // bytes of one phase plane of one timestep (all channels)

@@ -503,6 +503,7 @@ __global__ __launch_bounds__(256, 2) void pme_adjoint(const KParams p) {
   __shared__ float s_betl[kPmeBlk][kPmeCh + 1];  // beta_l = k3 (l - dl_p)
   __shared__ float s_betm[kPmeBlk][kPmeCh + 1];  // beta_m = k3 (m - dm_p)
   __shared__ float s_out[4][kPmeCh][6];          // per k: G, u, v, w, beam l, beam m
+  __shared__ float s_src[kPmeCh][8];             // St'(nu) I..V, l/n, m/n, (nu/nu_ref)^alpha
   __shared__ float s_acc[kPmeSR][7];
   __shared__ float s_uvw[kPmeBlk][3];
   __shared__ double s_pnt[kPmeBlk][2];
@@ -595,6 +596,25 @@ __global__ __launch_bounds__(256, 2) void pme_adjoint(const KParams p) {
             sm = geo.y;
           }
         }
+        if (part == 0) {
+          // per-source factors of the assembly below
+          float4 sv = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+          double2 lo = make_double2(0.0, 0.0);
+          float f = 0.0f;
+          if (s < cnt) {
+            const int64_t gs = sd.src_off + s0 + s;
+            sv = stk[gs * p.nchan + c];
+            lo = p.src_lon[gs];
+            f = p.src_f[gs * p.nchan + c];
+          }
+          s_src[s][0] = sv.x;
+          s_src[s][1] = sv.y;
+          s_src[s][2] = sv.z;
+          s_src[s][3] = sv.w;
+          s_src[s][4] = static_cast<float>(lo.x);
+          s_src[s][5] = static_cast<float>(lo.y);
+          s_src[s][6] = f;
+        }
         uint4 *bh = reinterpret_cast<uint4 *>(&s_bh[s][part * 16]);
         uint4 *bl = reinterpret_cast<uint4 *>(&s_bl[s][part * 16]);
         bh[0] = h0;
@@ -675,8 +695,7 @@ __global__ __launch_bounds__(256, 2) void pme_adjoint(const KParams p) {
       __syncthreads();
       if (tid < cnt) {
         const int s = tid;
-        const float4 sv = stk[(sd.src_off + s0 + s) * p.nchan + c];
-        const float stv[4] = {sv.x, sv.y, sv.z, sv.w};
+        const float stv[4] = {s_src[s][0], s_src[s][1], s_src[s][2], s_src[s][3]};
         float G[4], h[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
@@ -687,9 +706,7 @@ __global__ __launch_bounds__(256, 2) void pme_adjoint(const KParams p) {
 #pragma unroll
         for (int j = 0; j < 5; ++j) h[j] *= unscl;
         // h = (sum u Im W, sum v Im W, sum w Im W, sum beta_l Re W, sum beta_m Re W)
-        const double2 lo = p.src_lon[sd.src_off + s0 + s];
-        const float f = p.src_f[(sd.src_off + s0 + s) * p.nchan + c];
-        const float lon = static_cast<float>(lo.x), mon = static_cast<float>(lo.y);
+        const float lon = s_src[s][4], mon = s_src[s][5], f = s_src[s][6];
         float *acc = s_acc[s0 + s - sbeg];
         acc[0] += h[3] + tpnc * (h[0] - lon * h[2]);
         acc[1] += h[4] + tpnc * (h[1] - mon * h[2]);

@@ -196,7 +196,8 @@ rime_status rime_variant_info(rime_mode mode, rime_precision prec, int32_t index
  * A diag(St'_k) A^H per timestep and channel, fp16 hi/lo-split operands,
  * float32 accumulation within 32 sources, float64 across), 0 when every
  * source goes through the per-baseline kernel, -1 for an invalid index.
- * Batched calls always use the per-baseline kernel. */
+ * A batched call with such a variant runs the single-sky pipeline once per
+ * set in stream order (workspace: one set's, from rime_batch_workspace_size). */
 int32_t rime_variant_matrix_cores(rime_mode mode, rime_precision prec, int32_t index);
 rime_status rime_set_variant(rime_plan *plan, rime_mode mode, rime_precision prec,
                              int32_t index);

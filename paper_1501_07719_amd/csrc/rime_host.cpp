@@ -115,6 +115,7 @@ struct rime_batch {
   int64_t total_src = 0;
   int32_t max_nsrc = 0;
   SetDesc *d_sets = nullptr;
+  std::vector<SetDesc> h_sets;  // host copy (per-set launches of matrix-core variants)
   int32_t *d_order = nullptr;
   bool has_graph = false;
   GraphKey key{};
@@ -417,7 +418,7 @@ rime_status enqueue(const rime_plan *plan, int mode, int prec, int vidx, int nse
                     const SetDesc *d_sets, const SetDesc &one, const int32_t *d_order,
                     int max_nsrc, int64_t total_src, const void *data, const void *weight,
                     void *vis, double *chi2, double *grad, void *ws, size_t ws_bytes,
-                    hipStream_t stream) {
+                    hipStream_t stream, bool events = true) {
   const Variant *v = variant_info(mode, prec, vidx);
   if (!v) return RIME_ERR_UNSUPPORTED;
   const Geometry g = geometry(plan, *v, nset);
@@ -487,7 +488,7 @@ rime_status enqueue(const rime_plan *plan, int mode, int prec, int vidx, int nse
     }
   }
   RIME_HIP(launch_prep(p, prec == RIME_FP64, max_nsrc, stream));
-  if (plan->ev_start) RIME_HIP(hipEventRecord(plan->ev_start, stream));
+  if (events && plan->ev_start) RIME_HIP(hipEventRecord(plan->ev_start, stream));
   if (p.pme) {
     RIME_HIP(launch_pme_scale(p, stream));
     KParams pf = p;
@@ -502,9 +503,9 @@ rime_status enqueue(const rime_plan *plan, int mode, int prec, int vidx, int nse
       RIME_HIP(launch_pme(pf, stream));
     }
   }
-  if (plan->ev_main0) RIME_HIP(hipEventRecord(plan->ev_main0, stream));
+  if (events && plan->ev_main0) RIME_HIP(hipEventRecord(plan->ev_main0, stream));
   RIME_HIP(launch_variant(mode, prec, vidx, p, static_cast<int>(nitems), stream));
-  if (plan->ev_main1) RIME_HIP(hipEventRecord(plan->ev_main1, stream));
+  if (events && plan->ev_main1) RIME_HIP(hipEventRecord(plan->ev_main1, stream));
   if (p.pme_adj) {
     if (L.ph_k3) p.ph_k3 = reinterpret_cast<float *>(w + L.ph_k3);
     for (int t0 = 0; t0 < plan->ntime; t0 += L.pme_tchunk) {
@@ -513,7 +514,7 @@ rime_status enqueue(const rime_plan *plan, int mode, int prec, int vidx, int nse
       RIME_HIP(launch_pme_adjoint(p, L.pme_tchunk < plan->ntime, stream));
     }
   }
-  if (plan->ev_stop) RIME_HIP(hipEventRecord(plan->ev_stop, stream));
+  if (events && plan->ev_stop) RIME_HIP(hipEventRecord(plan->ev_stop, stream));
   RIME_HIP(launch_finalize(p, mode, max_nsrc, stream));
   if (p.pme_adj) RIME_HIP(launch_pme_finalize(p, stream));
   return RIME_OK;
@@ -882,6 +883,7 @@ rime_status rime_batch_create(const rime_plan *plan, int32_t nset, const rime_sk
   rime_batch *b = new rime_batch;
   b->plan = plan;
   b->nset = nset;
+  b->h_sets = sets;
   b->total_src = off;
   b->max_nsrc = mx;
   hipError_t e;
@@ -893,9 +895,22 @@ rime_status rime_batch_create(const rime_plan *plan, int32_t nset, const rime_sk
   return RIME_OK;
 }
 
+// Workspace of one batched call with variant v: a matrix-core variant runs
+// the single-sky pipeline once per set (one set's layout, reused in stream
+// order); the others run all sets in one launch sequence.
+size_t batch_ws(const rime_batch *b, int mode, int prec, const Variant &v) {
+  if (pme_active(v, prec, 1) && mode != RIME_MODE_PREDICT)
+    return ws_layout(b->plan, mode, prec, geometry(b->plan, v, 1), 1, b->max_nsrc, v).total;
+  return ws_layout(b->plan, mode, prec, geometry(b->plan, v, b->nset), b->nset, b->total_src, v)
+      .total;
+}
+
 size_t rime_batch_workspace_size(const rime_batch *b, rime_mode mode, rime_precision prec) {
   if (!b || mode < 0 || mode > 2 || prec < 0 || prec > 1) return 0;
-  return ws_max(b->plan, mode, prec, b->nset, b->total_src);
+  size_t best = 0;
+  for (int i = 0; i < variant_count(mode, prec); ++i)
+    best = std::max(best, batch_ws(b, mode, prec, *variant_info(mode, prec, i)));
+  return best;
 }
 
 rime_status rime_chi2_batched(rime_batch *b, rime_precision prec, const void *data,
@@ -908,15 +923,31 @@ rime_status rime_chi2_batched(rime_batch *b, rime_precision prec, const void *da
   const int vidx = b->variant[mode][prec] >= 0 ? b->variant[mode][prec] : plan->variant[mode][prec];
   const Variant *v = variant_info(mode, prec, vidx);
   if (!v) return RIME_ERR_UNSUPPORTED;
-  const WsLayout L =
-      ws_layout(plan, mode, prec, geometry(plan, *v, b->nset), b->nset, b->total_src, *v);
-  if (!ws || ws_bytes < L.total) return RIME_ERR_WORKSPACE;
+  if (!ws || ws_bytes < batch_ws(b, mode, prec, *v)) return RIME_ERR_WORKSPACE;
   hipStream_t s = static_cast<hipStream_t>(stream);
   SetDesc dummy;
   std::memset(&dummy, 0, sizeof(dummy));
+  const bool per_set = pme_active(*v, prec, 1);
   auto run = [&]() {
-    return enqueue(plan, mode, prec, vidx, b->nset, b->d_sets, dummy, b->d_order, b->max_nsrc,
-                   b->total_src, data, weight, nullptr, chi2, grad, ws, ws_bytes, s);
+    if (!per_set)
+      return enqueue(plan, mode, prec, vidx, b->nset, b->d_sets, dummy, b->d_order,
+                     b->max_nsrc, b->total_src, data, weight, nullptr, chi2, grad, ws,
+                     ws_bytes, s);
+    // matrix-core variant: the single-sky pipeline per set, in stream order;
+    // the timing events (if any) bracket the whole sequence
+    if (plan->ev_start) RIME_HIP(hipEventRecord(plan->ev_start, s));
+    for (int i = 0; i < b->nset; ++i) {
+      SetDesc one = b->h_sets[i];
+      const int64_t off = one.src_off;
+      one.src_off = 0;
+      const int n = one.npsrc + one.ngsrc;
+      const rime_status st =
+          enqueue(plan, mode, prec, vidx, 1, nullptr, one, nullptr, n, n, data, weight, nullptr,
+                  chi2 + i, grad ? grad + off * 10 : nullptr, ws, ws_bytes, s, false);
+      if (st != RIME_OK) return st;
+    }
+    if (plan->ev_stop) RIME_HIP(hipEventRecord(plan->ev_stop, s));
+    return RIME_OK;
   };
   if (!use_graph || s == nullptr) return run();
   GraphKey key{data, weight, chi2, grad, ws, ws_bytes, stream, prec, vidx, mode};

@@ -97,7 +97,9 @@ typedef struct rime_obs_desc {
 typedef struct rime_sky {
   int32_t npsrc;             /* point sources, >= 0                               */
   int32_t ngsrc;             /* Gaussian sources, >= 0; npsrc + ngsrc >= 1        */
-  const double *lm;          /* device [nsrc][2] direction cosines, rad           */
+  const double *lm;          /* device [nsrc][2] direction cosines, rad; l^2 + m^2  */
+                             /* < 1 is not checked (device data): n - 1 becomes   */
+                             /* NaN and propagates to every output                */
   const double *stokes;      /* device [nsrc][4] I, Q, U, V in Jy at ref_freq     */
   const double *alpha;       /* device [nsrc] spectral index                      */
   const double *gshape;      /* device [ngsrc][3] (el, em, R): el = theta_maj sin(pa), */

@@ -168,3 +168,29 @@ def test_batched_matrix_cores():
         off += s.nsrc
     batch.close()
     plan.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_bitwise_deterministic(prec):
+    """Fixed-order reductions: repeated chi^2 + gradient calls (the default
+    variant: matrix cores in float32-mixed) give bitwise identical results."""
+    obs, sky, D, W = problem("three_blocks")
+    D, W = round_inputs(D, W, prec)
+    cdt = torch.complex128 if prec == R.FP64 else torch.complex64
+    rdt = torch.float64 if prec == R.FP64 else torch.float32
+    plan = R.Plan(obs)
+    dsky = R.DeviceSky.from_host(sky)
+    Dd = torch.as_tensor(D, dtype=cdt, device="cuda")
+    Wd = torch.as_tensor(W, dtype=rdt, device="cuda")
+    ws = R.workspace(plan, R.MODE_CHI2_GRAD, prec, 1, sky.nsrc)
+    res = []
+    for rep in range(3):
+        chi2 = torch.empty(1, dtype=torch.float64, device="cuda")
+        grad = torch.empty((sky.nsrc, 10), dtype=torch.float64, device="cuda")
+        ws.fill_(rep)  # stale workspace contents must not matter
+        R.rime_chi2_grad(plan, dsky, prec, Dd, Wd, chi2, grad, ws)
+        res.append((chi2.cpu().numpy(), grad.cpu().numpy()))
+    for c, g in res[1:]:
+        np.testing.assert_array_equal(c, res[0][0])
+        np.testing.assert_array_equal(g, res[0][1])
+    plan.close()

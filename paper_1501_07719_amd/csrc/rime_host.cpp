@@ -379,6 +379,11 @@ size_t ws_max(const rime_plan *plan, int mode, int prec, int nset, int64_t total
     const Variant *v = variant_info(mode, prec, i);
     best = std::max(best,
                     ws_layout(plan, mode, prec, geometry(plan, *v, nset), nset, total_src, *v).total);
+    // a batched call with a matrix-core variant runs one set at a time; no
+    // set has more than total_src sources
+    if (nset > 1 && pme_active(*v, prec, 1) && mode != RIME_MODE_PREDICT)
+      best = std::max(best,
+                      ws_layout(plan, mode, prec, geometry(plan, *v, 1), 1, total_src, *v).total);
   }
   return best;
 }

@@ -388,7 +388,11 @@ def rime_batch_get_variant(batch: Batch, mode: int, prec: int) -> int:
 
 def rime_autotune(plan: Plan, sky: DeviceSky, mode: int, prec: int, data, weight, ws,
                   cache_path: str | None = None):
+    """Time every compiled variant on this sky and keep the fastest; the choice
+    is cached in `cache_path` (default: the file named by RIME_TUNE_CACHE, if
+    set)."""
     d = sky.desc()
+    cache_path = cache_path or os.environ.get("RIME_TUNE_CACHE")
     cp = cache_path.encode() if cache_path else None
     _check(plan._lib.rime_autotune(plan.handle, ctypes.byref(d), mode, prec,
                                    _dptr(data) if data is not None else None,

@@ -16,6 +16,53 @@ namespace rime {
 constexpr double kInvTwoPi = 0.15915494309189533576888376337251436;
 constexpr double kLog2e = 1.44269504088896340735992468100189214;
 
+// Pointers into the constant address space: loads through them at a
+// wavefront-uniform address become scalar (SMEM) loads whose results are
+// operands in SGPRs.  Only data written by an earlier kernel is read this way.
+// (The host compilation pass parses the device code without address spaces.)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define RIME_CONST __attribute__((address_space(4)))
+#else
+#define RIME_CONST
+#endif
+
+template <class T>
+__device__ inline const RIME_CONST T *const_ptr(const void *p) {
+  return (const RIME_CONST T *)(p);  // an address-space cast needs the C form
+}
+
+// Plain 4-vector for loads through constant-space pointers (the HIP vector
+// types have no copy from that address space); copies merge into one wide
+// scalar load.
+template <class R>
+struct alignas(4 * sizeof(R)) Quad {
+  R x, y, z, w;
+};
+
+// Returns x unchanged in a VGPR the compiler cannot see through, so that a
+// constant folded into x (an LDS region offset) stays in the per-lane base
+// address instead of being re-added inside a loop.
+__device__ inline uint32_t opaque_vgpr(uint32_t x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
+// The set descriptor of a work item, read through the constant space so that
+// its fields are wavefront-uniform (scalar) values.
+__device__ inline SetDesc load_set(const KParams &p, int set) {
+  if (!p.sets) return p.one;
+  const RIME_CONST SetDesc *q = const_ptr<SetDesc>(p.sets) + set;
+  SetDesc d;
+  d.lm = q->lm;
+  d.stokes = q->stokes;
+  d.alpha = q->alpha;
+  d.gshape = q->gshape;
+  d.npsrc = q->npsrc;
+  d.ngsrc = q->ngsrc;
+  d.src_off = q->src_off;
+  return d;
+}
+
 template <class R> struct Num;
 
 template <> struct Num<double> {
@@ -27,8 +74,17 @@ template <> struct Num<double> {
   }
   // sin and cos of x radians, |x| <= 1.1.
   __device__ static inline void sincos_rad(double x, double *s, double *c) { sincos(x, s, c); }
-  // exp(y) for y <= 0; y2 = y log2(e) is used by the float version.
-  __device__ static inline double exp_neg(double y, double /*y2*/) { return exp(y); }
+  // expb(y) = exp(y / kExpScale): the exponential in the base whose argument
+  // scale is kExpScale (e here, 2 in the float version).
+  static constexpr double kExpScale = 1.0;
+  __device__ static inline double expb(double y) { return exp(y); }
+  // the 32 bits packed into the last word of a per-baseline record
+  __device__ static inline uint32_t bits(double w) {
+    return static_cast<uint32_t>(__double_as_longlong(w));
+  }
+  __device__ static inline double from_bits(uint32_t b) {
+    return __longlong_as_double(static_cast<long long>(b));
+  }
   __device__ static inline double sqrt_(double x) { return sqrt(x); }
   __device__ static inline double rcp(double x) { return 1.0 / x; }
 };
@@ -47,9 +103,10 @@ template <> struct Num<float> {
     *s = __builtin_amdgcn_sinf(t);
     *c = __builtin_amdgcn_cosf(t);
   }
-  __device__ static inline float exp_neg(float /*y*/, float y2) {
-    return __builtin_amdgcn_exp2f(y2);
-  }
+  static constexpr double kExpScale = kLog2e;
+  __device__ static inline float expb(float y) { return __builtin_amdgcn_exp2f(y); }
+  __device__ static inline uint32_t bits(float w) { return __float_as_uint(w); }
+  __device__ static inline float from_bits(uint32_t b) { return __uint_as_float(b); }
   __device__ static inline float sqrt_(double x) {
     return __builtin_amdgcn_sqrtf(static_cast<float>(x));
   }

@@ -17,6 +17,7 @@
 
 namespace rime {
 hipError_t launch_prep(const KParams &p, bool fp64, int max_nsrc, hipStream_t stream);
+hipError_t launch_prep_baselines(const KParams &p, bool fp64, int nc, hipStream_t stream);
 hipError_t launch_finalize(const KParams &p, int mode, int max_nsrc, hipStream_t stream);
 hipError_t launch_pme(const KParams &p, hipStream_t stream);
 hipError_t launch_pme_adjoint(const KParams &p, bool phase, hipStream_t stream);
@@ -281,7 +282,7 @@ Geometry geometry(const rime_plan *plan, const Variant &v, int nset) {
 }
 
 struct WsLayout {
-  size_t geo = 0, lon = 0, st = 0, chi2 = 0, grad = 0, grad2 = 0;
+  size_t geo = 0, lon = 0, st = 0, gs = 0, rec = 0, chi2 = 0, grad = 0, grad2 = 0;
   size_t ph_hi = 0, ph_lo = 0, ph_k3 = 0, spts = 0, pexp = 0, rho_t = 0, pgrad = 0;
   size_t src_f = 0, mfrag = 0, mscale = 0;
   int32_t pme_tchunk = 0;  // timesteps per phase-plane pass (0: engine off)
@@ -317,6 +318,12 @@ WsLayout ws_layout(const rime_plan *plan, int mode, int prec, const Geometry &g,
   off += align_up(static_cast<size_t>(total_src) * sizeof(double2));
   L.st = off;
   off += align_up(static_cast<size_t>(total_src) * plan->nchan * r4);
+  L.gs = off;
+  off += align_up(static_cast<size_t>(total_src) * r4);
+  if (mode == RIME_MODE_CHI2_GRAD) {
+    L.rec = off;
+    off += align_up((static_cast<size_t>(plan->ntime) * g.ntile * v.threads + kRecPad) * r4);
+  }
   L.chi2 = off;
   if (mode != RIME_MODE_PREDICT)
     off += align_up(static_cast<size_t>(nset) * g.items_per_set * sizeof(double2));
@@ -452,6 +459,8 @@ rime_status enqueue(const rime_plan *plan, int mode, int prec, int vidx, int nse
   p.src_geo = reinterpret_cast<double4 *>(w + L.geo);
   p.src_lon = reinterpret_cast<double2 *>(w + L.lon);
   p.src_st = w + L.st;
+  p.src_gs = w + L.gs;
+  if (mode == RIME_MODE_CHI2_GRAD) p.bl_rec = w + L.rec;
   p.total_src = total_src;
   p.data = data;
   p.weight = weight;
@@ -493,6 +502,8 @@ rime_status enqueue(const rime_plan *plan, int mode, int prec, int vidx, int nse
     }
   }
   RIME_HIP(launch_prep(p, prec == RIME_FP64, max_nsrc, stream));
+  if (mode == RIME_MODE_CHI2_GRAD)
+    RIME_HIP(launch_prep_baselines(p, prec == RIME_FP64, v->nc, stream));
   if (events && plan->ev_start) RIME_HIP(hipEventRecord(plan->ev_start, stream));
   if (p.pme) {
     RIME_HIP(launch_pme_scale(p, stream));

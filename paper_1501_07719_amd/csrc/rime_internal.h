@@ -66,6 +66,9 @@ struct KParams {
   double4 *src_geo;        // [total_src] (l, m, n - 1, 0)
   double2 *src_lon;        // [total_src] (l / n, m / n)
   void *src_st;            // [total_src][nchan] Stokes scaled by (nu/nu_ref)^alpha (R4)
+  void *src_gs;            // [total_src] Gaussian shape (el, em, R em, R el) (R4)
+  const void *bl_rec;      // [ntime][ntile][nbt] per-baseline records of the adjoint (R4):
+                           //   (du, dv, dw, a-tile byte offsets of p | q << 16)
   float *src_f;            // [total_src][nchan] (nu/nu_ref)^alpha, or nullptr
   int64_t total_src;
   // per-call data
@@ -115,6 +118,10 @@ constexpr int kPmeBlk = 32;
 constexpr int kPmeNQ = 2;
 constexpr int kPmeSR = 512;
 constexpr int kPmeNCW = 8;
+
+// Padding (in records) after the per-baseline records of the adjoint, which
+// reads one record ahead.
+constexpr int kRecPad = 1024;
 
 // Kernel variant descriptor.
 struct Variant {

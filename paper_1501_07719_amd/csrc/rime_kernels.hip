@@ -60,6 +60,57 @@ __global__ __launch_bounds__(256) void prep_sources(const KParams p) {
     st[c] = v;
     if (p.src_f) p.src_f[g * p.nchan + c] = static_cast<float>(f);
   }
+  if (s >= sd.npsrc) {
+    // Gaussian shape with the axis ratio folded into the minor-axis pair, so
+    // that the exponent is A^2 + B^2 with A = du el + dv em and
+    // B = du (R em) - dv (R el)
+    const int gi = s - sd.npsrc;
+    const double el = sd.gshape[3 * gi], em = sd.gshape[3 * gi + 1], Rr = sd.gshape[3 * gi + 2];
+    R4 v;
+    v.x = static_cast<R>(el);
+    v.y = static_cast<R>(em);
+    v.z = static_cast<R>(Rr * em);
+    v.w = static_cast<R>(Rr * el);
+    static_cast<R4 *>(p.src_gs)[g] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Per-baseline records of the adjoint, one per (timestep, tile, slot): the
+// baseline vector (u_p - u_q, v_p - v_q, w_p - w_q) and, in the bits of the
+// last word, the byte offsets of antennas p (low 16 bits) and q (high 16 bits)
+// within a source row of the a-tile of a kernel with `nc` channels per thread.
+// The adjoint reads them with scalar loads.
+// ---------------------------------------------------------------------------
+template <class R>
+__global__ __launch_bounds__(256) void prep_baselines(const KParams p, int nc) {
+  using N = Num<R>;
+  using R2 = typename N::R2;
+  using R4 = typename N::R4;
+  const int t = blockIdx.y;
+  const int64_t n = static_cast<int64_t>(p.ntile) * p.nbt;
+  R4 *rec = static_cast<R4 *>(const_cast<void *>(p.bl_rec)) + t * n;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * 256) {
+    const int tile = static_cast<int>(i / p.nbt);
+    R4 r;
+    r.x = r.y = r.z = R(0);
+    uint32_t off = 0;
+    if (p.tile_bl[i] >= 0) {
+      const int lpq = p.tile_lpq[i];
+      const int lp = lpq & 0xffff, lq = lpq >> 16;
+      const int ap = p.tile_ant[tile * p.nat + lp], aq = p.tile_ant[tile * p.nat + lq];
+      const double *up = p.uvw + (static_cast<int64_t>(t) * p.na + ap) * 3;
+      const double *uq = p.uvw + (static_cast<int64_t>(t) * p.na + aq) * 3;
+      r.x = static_cast<R>(up[0] - uq[0]);
+      r.y = static_cast<R>(up[1] - uq[1]);
+      r.z = static_cast<R>(up[2] - uq[2]);
+      const uint32_t row = static_cast<uint32_t>(nc * sizeof(R2));
+      off = lp * row | (lq * row) << 16;
+    }
+    r.w = N::from_bits(off);
+    rec[i] = r;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -78,15 +129,31 @@ struct Layout {
   // elements so that the adjoint's lanes (source x channel) hit distinct banks.
   static constexpr int AST = NAT * NC + 2;
   static constexpr bool GRAD = MODE == MODE_GRAD;
-  static constexpr size_t A_BYTES = sizeof(R2) * NS * AST;
-  static constexpr size_t BETA_BYTES = GRAD ? sizeof(R2) * NS * AST : 0;
+  static constexpr size_t A_BYTES = (sizeof(R2) * NS * AST + 511) / 512 * 512;
+  static constexpr size_t BETA_BYTES = GRAD ? A_BYTES : 0;
   static constexpr size_t RED_BYTES = GRAD ? sizeof(R) * NBT * 10 : 0;
-  // the adjoint's cross-wave reduction buffer reuses the a/beta tiles
-  static constexpr size_t AB_BYTES =
-      (A_BYTES + BETA_BYTES) > RED_BYTES ? (A_BYTES + BETA_BYTES) : RED_BYTES;
   static constexpr size_t RHO_BYTES = GRAD ? sizeof(R2) * NBT * NC * 4 : 0;
-  static constexpr size_t GEO_BYTES = GRAD ? sizeof(R4) * NBT : 0;
   static_assert(!GRAD || NS * NC == kWave, "the adjoint maps one wavefront to NS x NC");
+  // LDS byte offsets.  The residual tile comes first: the adjoint addresses it
+  // per lane plus constant offsets, which fold into the 16-bit offset field of
+  // ds_read only below 64 KiB.  Beta follows the a-tile at a multiple of 512
+  // bytes (one base for both in ds_read2st64); the adjoint's cross-wave
+  // reduction buffer reuses the a and beta tiles, which are dead at that point.
+  static constexpr size_t OFF_RHO = 0;
+  static constexpr size_t OFF_A = OFF_RHO + RHO_BYTES;
+  static constexpr size_t OFF_BETA = OFF_A + A_BYTES;
+  // per-source records of the tile: NC scaled Stokes rows, then the shape
+  static constexpr int SREC = NC + 1;
+  static constexpr size_t OFF_SRC = OFF_BETA + BETA_BYTES;
+  static constexpr size_t OFF_UVW = OFF_SRC + sizeof(R4) * NS * SREC;
+  static constexpr size_t OFF_PNT = OFF_UVW + sizeof(double) * NAT * 3;
+  static constexpr size_t OFF_SCR = OFF_PNT + sizeof(double) * NAT * 2;
+  static constexpr size_t OFF_RED = OFF_A;
+  static constexpr size_t LDS_BYTES = OFF_SCR + sizeof(double2) * (NW > 0 ? NW : 1);
+  static_assert(A_BYTES % 512 == 0 && RHO_BYTES % 16 == 0, "alignment of the LDS regions");
+  static_assert(RED_BYTES <= A_BYTES + BETA_BYTES, "reduction buffer within the a/beta tiles");
+  static_assert(RHO_BYTES <= 65536, "the residual tile must lie below 64 KiB");
+  static_assert(LDS_BYTES <= 160 * 1024, "LDS of one CU");
 };
 
 // Per-antenna stage for one source tile: a[s][ant][c] = e K (and, for the
@@ -96,8 +163,7 @@ template <class R, int NBT, int NC, int NS, int MODE, bool WITH_BETA>
 __device__ inline void stage_tile(const KParams &p, const SetDesc &sd, int tile, int s0, int cnt,
                                   bool gauss, int c0, int ncv, const double (*s_uvw)[3],
                                   const double (*s_pnt)[2], typename Num<R>::R2 *s_a,
-                                  typename Num<R>::R2 *s_beta, typename Num<R>::R4 *s_st,
-                                  typename Num<R>::R4 *s_gs) {
+                                  typename Num<R>::R2 *s_beta, typename Num<R>::R4 *s_src) {
   using L = Layout<R, NBT, NC, NS, MODE>;
   using N = Num<R>;
   using R2 = typename N::R2;
@@ -168,60 +234,74 @@ __device__ inline void stage_tile(const KParams &p, const SetDesc &sd, int tile,
       if (WITH_BETA) s_beta[s * L::AST + ai * NC + c] = bet[c];
     }
   }
+  // per-source records: the NC Stokes rows of the block's channels, then the
+  // Gaussian shape (zeros for point sources and past the tile's end)
   const R4 *st = static_cast<const R4 *>(p.src_st);
-  for (int idx = tid; idx < NS * NC; idx += NBT) {
-    const int s = idx / NC, c = idx - (idx / NC) * NC;
+  const R4 *gs = static_cast<const R4 *>(p.src_gs);
+  for (int idx = tid; idx < NS * L::SREC; idx += NBT) {
+    const int s = idx / L::SREC, c = idx - s * L::SREC;
     R4 v;
     v.x = v.y = v.z = v.w = R(0);
-    if (s < cnt && c < ncv) v = st[(sd.src_off + s0 + s) * p.nchan + c0 + c];
-    s_st[idx] = v;
-  }
-  if (gauss) {
-    for (int s = tid; s < NS; s += NBT) {
-      R4 v;
-      v.x = v.y = v.z = v.w = R(0);
-      if (s < cnt) {
-        const int gi = s0 + s - sd.npsrc;
-        const double R_ = sd.gshape[3 * gi + 2];
-        v.x = static_cast<R>(sd.gshape[3 * gi]);
-        v.y = static_cast<R>(sd.gshape[3 * gi + 1]);
-        v.z = static_cast<R>(R_ * R_);
-        v.w = static_cast<R>(R_);
+    if (s < cnt) {
+      if (c < NC) {
+        if (c < ncv) v = st[(sd.src_off + s0 + s) * p.nchan + c0 + c];
+      } else if (gauss) {
+        v = gs[sd.src_off + s0 + s];
       }
-      s_gs[s] = v;
     }
+    s_src[idx] = v;
   }
 }
 
-// Pass 1 inner loop over the sources of one staged tile: adds
+// Pass 1 inner loop over the sources of one tile: adds
 // sum_s S c_s (I', Q', U', V')_s to the 8 accumulators of each channel.
+// `src` holds the tile's per-source records (NC scaled Stokes rows, then the
+// shape coefficients (el, em, R em, R el)); the Gaussian factor is
+// S = expb(gqs[c] (A^2 + B^2)) with A = du el + dv em, B = du R em - dv R el.
+// All lanes read the same record (an LDS broadcast).
 template <class R, int NC, int AST, bool GAUSS>
 __device__ inline void accumulate(int cnt, const typename Num<R>::R2 *ap_row,
                                   const typename Num<R>::R2 *aq_row,
-                                  const typename Num<R>::R4 *s_st,
-                                  const typename Num<R>::R4 *s_gs, R du, R dv, const R *gq,
-                                  const R *gq2, R (&in)[NC][8]) {
+                                  const typename Num<R>::R4 *src, R du, R dv, const R *gqs,
+                                  R (&in)[NC][8]) {
   using N = Num<R>;
   using R2 = typename N::R2;
   using R4 = typename N::R4;
+  static_assert(NC % 2 == 0, "channel pairs");
 #pragma unroll 2
   for (int s = 0; s < cnt; ++s) {
+    const R4 *rs = src + s * (NC + 1);
     R Qf = R(0);
     if (GAUSS) {
-      const R4 g = s_gs[s];
+      const R4 g = rs[NC];
       const R A = du * g.x + dv * g.y;
-      const R B = du * g.y - dv * g.x;
-      Qf = A * A + g.z * B * B;
+      const R B = du * g.z - dv * g.w;
+      Qf = A * A + B * B;
+    }
+    // the a-terms of channel pairs as one 4-vector load each
+    R2 apc[NC], aqc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; c += 2) {
+      const R4 p4 = *reinterpret_cast<const R4 *>(ap_row + s * AST + c);
+      const R4 q4 = *reinterpret_cast<const R4 *>(aq_row + s * AST + c);
+      apc[c].x = p4.x;
+      apc[c].y = p4.y;
+      apc[c + 1].x = p4.z;
+      apc[c + 1].y = p4.w;
+      aqc[c].x = q4.x;
+      aqc[c].y = q4.y;
+      aqc[c + 1].x = q4.z;
+      aqc[c + 1].y = q4.w;
     }
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      const R2 ap = ap_row[s * AST + c];
-      const R2 aq = aq_row[s * AST + c];
-      const R4 st = s_st[s * NC + c];
+      const R2 ap = apc[c];
+      const R2 aq = aqc[c];
+      const R4 st = rs[c];
       R cr = ap.x * aq.x + ap.y * aq.y;
       R ci = ap.y * aq.x - ap.x * aq.y;
       if (GAUSS) {
-        const R S = N::exp_neg(gq[c] * Qf, gq2[c] * Qf);
+        const R S = N::expb(gqs[c] * Qf);
         cr *= S;
         ci *= S;
       }
@@ -244,26 +324,28 @@ __device__ inline void accumulate(int cnt, const typename Num<R>::R2 *ap_row,
 //   g[5], g[6]   sum (beta_p + beta_q)_{l,m} Re P  (beam part of l, m)
 //   g[7], g[8], g[9]  sum (du, dv, dw) Im P        (phase part of l, m)
 //   g[10..14]  Gaussian: sum du A ReP, sum dv B ReP, sum dv A ReP, sum du B ReP,
-//              sum B^2 ReP
-// with P = c Phi, Phi = sum_k St'_k rho_k.  `s_off` holds, per baseline, the
-// byte offsets of a_p and a_q within a source row of the a-tile; the beta row
-// of the same source lies BETA_OFF bytes further.
+//              sum B^2 ReP, with A = du e.x + dv e.y and B = du e.z - dv e.w the
+//              lane-scaled shape terms (S = expb(-(A^2 + B^2)))
+// with P = c Phi, Phi = sum_k St'_k rho_k.  `rec` holds the tile's
+// per-baseline records (du, dv, dw, a-tile offsets of p and q), read with
+// scalar loads; the beta row of a source lies BETA_OFF bytes after its a row.
 template <class R, int NC, bool GAUSS, bool BEAM, int BETA_OFF>
-__device__ inline void adjoint_loop(int wave, int nw, int nact, const int2 *s_off,
-                                    const typename Num<R>::R4 *s_geo,
+__device__ inline void adjoint_loop(int wave, int nw, int nact, const RIME_CONST Quad<R> *rec,
                                     const typename Num<R>::R2 *s_rho, const char *arow,
                                     const typename Num<R>::R4 st,
-                                    const typename Num<R>::R4 gsh, R gq, R gq2, int cl,
-                                    R (&g)[15]) {
+                                    const typename Num<R>::R4 e, int cl, R (&g)[15]) {
   using N = Num<R>;
   using R2 = typename N::R2;
   using R4 = typename N::R4;
+  // records are read one iteration ahead (the record array is padded)
+  Quad<R> geo_n = rec[wave];
 #pragma unroll 2
   for (int bi = wave; bi < nact; bi += nw) {
-    const int2 o = s_off[bi];
-    const R4 geo = s_geo[bi];
-    const char *pa = arow + o.x;
-    const char *qa = arow + o.y;
+    const Quad<R> geo = geo_n;
+    geo_n = rec[bi + nw];
+    const uint32_t off = N::bits(geo.w);
+    const char *pa = arow + (off & 0xffffu);
+    const char *qa = arow + (off >> 16);
     const R2 ap = *reinterpret_cast<const R2 *>(pa);
     const R2 aq = *reinterpret_cast<const R2 *>(qa);
     const R2 *rho = s_rho + (bi * NC + cl) * 4;
@@ -272,10 +354,9 @@ __device__ inline void adjoint_loop(int wave, int nw, int nact, const int2 *s_of
     R ci = ap.y * aq.x - ap.x * aq.y;
     R A = R(0), B = R(0);
     if (GAUSS) {
-      A = geo.x * gsh.x + geo.y * gsh.y;
-      B = geo.x * gsh.y - geo.y * gsh.x;
-      const R Qf = A * A + gsh.z * B * B;
-      const R S = N::exp_neg(gq * Qf, gq2 * Qf);
+      A = geo.x * e.x + geo.y * e.y;
+      B = geo.x * e.z - geo.y * e.w;
+      const R S = N::expb(-(A * A + B * B));
       cr *= S;
       ci *= S;
     }
@@ -321,27 +402,23 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
   constexpr int NAT = L::NAT;
   constexpr int NW = L::NW;
 
-  __shared__ double s_uvw[NAT][3];
-  __shared__ double s_pnt[NAT][2];
-  __shared__ R4 s_st[NS * NC];
-  __shared__ R4 s_gs[NS];
-  __shared__ double2 s_scr[NW > 0 ? NW : 1];
-  __shared__ __attribute__((aligned(16))) char s_ab[L::AB_BYTES];
-  __shared__ __attribute__((aligned(16))) char s_rho_raw[L::RHO_BYTES > 0 ? L::RHO_BYTES : 16];
-  __shared__ __attribute__((aligned(16))) char s_geo_raw[L::GEO_BYTES > 0 ? L::GEO_BYTES : 16];
-  __shared__ int2 s_off[L::GRAD ? NBT : 1];  // a-tile offsets of (p, q)
-  R2 *s_a = reinterpret_cast<R2 *>(s_ab);
-  R2 *s_beta = reinterpret_cast<R2 *>(s_ab + L::A_BYTES);
-  R *s_red = reinterpret_cast<R *>(s_ab);
-  R2 *s_rho = reinterpret_cast<R2 *>(s_rho_raw);
-  R4 *s_geo = reinterpret_cast<R4 *>(s_geo_raw);
+  // one LDS block, laid out by Layout
+  __shared__ __attribute__((aligned(16))) char smem[L::LDS_BYTES];
+  R2 *s_rho = reinterpret_cast<R2 *>(smem + L::OFF_RHO);
+  R2 *s_a = reinterpret_cast<R2 *>(smem + L::OFF_A);
+  R2 *s_beta = reinterpret_cast<R2 *>(smem + L::OFF_BETA);
+  R *s_red = reinterpret_cast<R *>(smem + L::OFF_RED);
+  R4 *s_src = reinterpret_cast<R4 *>(smem + L::OFF_SRC);
+  double(*s_uvw)[3] = reinterpret_cast<double(*)[3]>(smem + L::OFF_UVW);
+  double(*s_pnt)[2] = reinterpret_cast<double(*)[2]>(smem + L::OFF_PNT);
+  double2 *s_scr = reinterpret_cast<double2 *>(smem + L::OFF_SCR);
 
   // ---- work item ----------------------------------------------------------
   const int item = blockIdx.x;
   const int set_rank = item / p.items_per_set;
   const int local_item = item - set_rank * p.items_per_set;
-  const int set = p.order ? p.order[set_rank] : set_rank;
-  const SetDesc sd = p.sets ? p.sets[set] : p.one;
+  const int set = p.order ? const_ptr<int32_t>(p.order)[set_rank] : set_rank;
+  const SetDesc sd = load_set(p, set);
   int rem = local_item;
   const int tile = rem % p.ntile;
   rem /= p.ntile;
@@ -364,12 +441,12 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
   const int nst = npt + ngt;
 
   // per-channel constants of this thread's channels: -pi^2/(4 ln 2) (nu/c)^2
-  R gq[NC], gq2[NC];
+  // in the argument scale of N::expb
+  R gqs[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     const double nuc = c < ncv ? p.nu_c[c0 + c] : 0.0;
-    gq[c] = static_cast<R>(-kGauss * nuc * nuc);
-    gq2[c] = static_cast<R>(-kGauss * kLog2e * nuc * nuc);
+    gqs[c] = static_cast<R>(-kGauss * N::kExpScale * nuc * nuc);
   }
 
   Comp chi;
@@ -399,7 +476,6 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
     __syncthreads();
     const R du = static_cast<R>(s_uvw[lp][0] - s_uvw[lq][0]);
     const R dv = static_cast<R>(s_uvw[lp][1] - s_uvw[lq][1]);
-    const R dw = static_cast<R>(s_uvw[lp][2] - s_uvw[lq][2]);
 
     // ---- epilogue for one channel: V, residual, chi^2 (and rho) ---------------
     // S = the four Stokes sums (re, im) of this thread's baseline.
@@ -523,19 +599,33 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
         const int cnt = min(NS, (gauss ? nsrc : sd.npsrc) - s0);
         __syncthreads();
         stage_tile<R, NBT, NC, NS, MODE, false>(p, sd, tile, s0, cnt, gauss, c0, ncv, s_uvw,
-                                                s_pnt, s_a, s_beta, s_st, s_gs);
+                                                s_pnt, s_a, s_beta, s_src);
         __syncthreads();
         R in[NC][8];
 #pragma unroll
         for (int c = 0; c < NC; ++c)
 #pragma unroll
           for (int j = 0; j < 8; ++j) in[c][j] = R(0);
-        if (gauss)
-          accumulate<R, NC, L::AST, true>(cnt, s_a + lp * NC, s_a + lq * NC, s_st, s_gs, du,
-                                          dv, gq, gq2, in);
-        else
-          accumulate<R, NC, L::AST, false>(cnt, s_a + lp * NC, s_a + lq * NC, s_st, s_gs, du,
-                                           dv, gq, gq2, in);
+        {
+          // the per-lane a-tile rows and the record base go through an opaque
+          // register, so that the region offsets stay in the base addresses
+          // and the loop advances them with immediate offsets
+          // (16-byte aligned: NC * sizeof(R2) and the row stride are multiples
+          // of 16, so a thread's NC channels load as one 16-byte word)
+          static_assert((NC * sizeof(R2)) % 16 == 0 && (L::AST * sizeof(R2)) % 16 == 0 &&
+                            L::OFF_A % 16 == 0 && L::OFF_SRC % 16 == 0,
+                        "16-byte aligned a-tile rows");
+          const R2 *ap_row = static_cast<const R2 *>(__builtin_assume_aligned(
+              smem + opaque_vgpr(static_cast<uint32_t>(L::OFF_A + lp * NC * sizeof(R2))), 16));
+          const R2 *aq_row = static_cast<const R2 *>(__builtin_assume_aligned(
+              smem + opaque_vgpr(static_cast<uint32_t>(L::OFF_A + lq * NC * sizeof(R2))), 16));
+          const R4 *src = static_cast<const R4 *>(__builtin_assume_aligned(
+              smem + opaque_vgpr(static_cast<uint32_t>(L::OFF_SRC)), 16));
+          if (gauss)
+            accumulate<R, NC, L::AST, true>(cnt, ap_row, aq_row, src, du, dv, gqs, in);
+          else
+            accumulate<R, NC, L::AST, false>(cnt, ap_row, aq_row, src, du, dv, gqs, in);
+        }
 #pragma unroll
         for (int c = 0; c < NC; ++c)
 #pragma unroll
@@ -576,16 +666,6 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
 
     // ---- pass 2: adjoint ----------------------------------------------------
     if (MODE == MODE_GRAD) {
-      {
-        R4 g;
-        g.x = du;
-        g.y = dv;
-        g.z = dw;
-        g.w = R(0);
-        s_geo[tid] = g;
-        s_off[tid] = make_int2(lp * NC * static_cast<int>(sizeof(R2)),
-                               lq * NC * static_cast<int>(sizeof(R2)));
-      }
       const int lane = tid % kWave;
       // wavefront index, uniform across the wavefront (scalar loop counters)
       const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
@@ -593,9 +673,14 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
       const bool lane_ok_c = cl < ncv;
       const double nuc_l = lane_ok_c ? p.nu_c[c0 + cl] : 0.0;
       const R tpnc = static_cast<R>(2.0 * kPi * nuc_l);
-      const R gq_l = static_cast<R>(-kGauss * nuc_l * nuc_l);
-      const R gq2_l = static_cast<R>(-kGauss * kLog2e * nuc_l * nuc_l);
+      // Gaussian lanes scale the shape coefficients by kap = sqrt(kGauss
+      // kExpScale) nu/c, so that S = expb(-(A^2 + B^2)); 2 gq / kap with
+      // gq = -kGauss (nu/c)^2 turns the accumulated sums into d chi^2 / d shape
+      const double kap_l = sqrt(kGauss * N::kExpScale) * nuc_l;
+      const double dsc_l = -2.0 * kap_l / N::kExpScale;
       const double lnfr_l = lane_ok_c ? p.lnfr[c0 + cl] : 0.0;
+      const RIME_CONST Quad<R> *rec =
+          const_ptr<Quad<R>>(p.bl_rec) + (static_cast<int64_t>(t) * p.ntile + tile) * NBT;
       // gradient partials: [set][item][nsrc][10], sets laid out by src_off
       double *gout = p.grad_part + sd.src_off * p.items_per_set * 10 +
                      static_cast<int64_t>(local_item) * nsrc * 10;
@@ -606,40 +691,49 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
         const int cnt = min(NS, (gauss ? nsrc : sd.npsrc) - s0);
         __syncthreads();
         stage_tile<R, NBT, NC, NS, MODE, true>(p, sd, tile, s0, cnt, gauss, c0, ncv, s_uvw,
-                                               s_pnt, s_a, s_beta, s_st, s_gs);
+                                               s_pnt, s_a, s_beta, s_src);
         __syncthreads();
         R gl[10];
 #pragma unroll
         for (int j = 0; j < 10; ++j) gl[j] = R(0);
         if (sl < cnt && lane_ok_c) {
-          const R4 st = s_st[sl * NC + cl];
+          const R4 st = s_src[sl * L::SREC + cl];
           const double2 lo = p.src_lon[sd.src_off + s0 + sl];
-          R4 gsh;
-          gsh.x = gsh.y = gsh.z = gsh.w = R(0);
-          if (gauss) gsh = s_gs[sl];
-          const char *arow = reinterpret_cast<const char *>(s_a + sl * L::AST + cl);
-          constexpr int BO = static_cast<int>(L::A_BYTES);
+          R4 e;
+          e.x = e.y = e.z = e.w = R(0);
+          if (gauss) {
+            const R4 gsh = s_src[sl * L::SREC + NC];
+            const R kap = static_cast<R>(kap_l);
+            e.x = kap * gsh.x;
+            e.y = kap * gsh.y;
+            e.z = kap * gsh.z;
+            e.w = kap * gsh.w;
+          }
+          // per-lane a-tile base with the region offset inside the register
+          const char *arow = smem + opaque_vgpr(static_cast<uint32_t>(
+                                        L::OFF_A + (sl * L::AST + cl) * sizeof(R2)));
+          constexpr int BO = static_cast<int>(L::OFF_BETA - L::OFF_A);
           R g[15];
 #pragma unroll
           for (int j = 0; j < 15; ++j) g[j] = R(0);
           if (p.beam) {
             if (gauss)
-              adjoint_loop<R, NC, true, true, BO>(wave, NW, nact, s_off, s_geo, s_rho, arow, st,
-                                                  gsh, gq_l, gq2_l, cl, g);
+              adjoint_loop<R, NC, true, true, BO>(wave, NW, nact, rec, s_rho, arow, st, e, cl, g);
             else
-              adjoint_loop<R, NC, false, true, BO>(wave, NW, nact, s_off, s_geo, s_rho, arow, st,
-                                                   gsh, gq_l, gq2_l, cl, g);
+              adjoint_loop<R, NC, false, true, BO>(wave, NW, nact, rec, s_rho, arow, st, e, cl, g);
           } else {
             if (gauss)
-              adjoint_loop<R, NC, true, false, BO>(wave, NW, nact, s_off, s_geo, s_rho, arow,
-                                                   st, gsh, gq_l, gq2_l, cl, g);
+              adjoint_loop<R, NC, true, false, BO>(wave, NW, nact, rec, s_rho, arow, st, e, cl, g);
             else
-              adjoint_loop<R, NC, false, false, BO>(wave, NW, nact, s_off, s_geo, s_rho, arow,
-                                                    st, gsh, gq_l, gq2_l, cl, g);
+              adjoint_loop<R, NC, false, false, BO>(wave, NW, nact, rec, s_rho, arow, st, e, cl,
+                                                    g);
           }
           g[4] = st.x * g[0] + st.y * g[1] + st.z * g[2] + st.w * g[3];
           // assemble: Stokes by the spectral factor, alpha by ln(nu/nu_ref),
-          // l and m from their beam and phase parts, shape by 2 gq.
+          // l and m from their beam and phase parts, shape by 2 gq / kap (the
+          // sums carry A = kap (du el + dv em) and B = kap R (du em - dv el)):
+          //   d/d el = 2 gq / kap (g10 - R g11),  d/d em = 2 gq / kap (g12 + R g13),
+          //   d/d R  = 2 gq / kap g14 / (kap R)
           const double al = sd.alpha[s0 + sl];
           const R f = static_cast<R>(exp(al * lnfr_l));
           const R lon = static_cast<R>(lo.x), mon = static_cast<R>(lo.y);
@@ -651,9 +745,13 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
           gl[5] = g[3] * f;
           gl[6] = g[4] * static_cast<R>(lnfr_l);
           if (gauss) {
-            gl[7] = R(2) * gq_l * (g[10] - gsh.z * g[11]);
-            gl[8] = R(2) * gq_l * (g[12] + gsh.z * g[13]);
-            gl[9] = R(2) * gq_l * gsh.w * g[14];
+            const double Rr = sd.gshape[3 * (s0 + sl - sd.npsrc) + 2];
+            const R dsc = static_cast<R>(dsc_l), Rf = static_cast<R>(Rr);
+            gl[7] = dsc * (g[10] - Rf * g[11]);
+            gl[8] = dsc * (g[12] + Rf * g[13]);
+            gl[9] = (Rr > 0.0 && kap_l > 0.0)
+                        ? static_cast<R>(dsc_l * static_cast<double>(g[14]) / (kap_l * Rr))
+                        : R(0);
           }
         }
         // sum the NC channel lanes of each source (adjacent lanes), then
@@ -662,7 +760,7 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
         for (int j = 0; j < 10; ++j)
 #pragma unroll
           for (int d = 1; d < NC; d <<= 1) gl[j] += __shfl_xor(gl[j], d, kWave);
-        __syncthreads();  // the reduction buffer aliases the a/beta tiles
+        __syncthreads();  // the reduction buffer aliases the beta, Stokes and shape tiles
         if (cl == 0) {
 #pragma unroll
           for (int j = 0; j < 10; ++j) s_red[(wave * NS + sl) * 10 + j] = gl[j];
@@ -762,6 +860,17 @@ hipError_t launch_prep(const KParams &p, bool fp64, int max_nsrc, hipStream_t st
     hipLaunchKernelGGL(prep_sources<double>, grid, dim3(256), 0, stream, p);
   else
     hipLaunchKernelGGL(prep_sources<float>, grid, dim3(256), 0, stream, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep_baselines(const KParams &p, bool fp64, int nc, hipStream_t stream) {
+  const int64_t n = static_cast<int64_t>(p.ntile) * p.nbt;
+  const int64_t nb = (n + 255) / 256;
+  dim3 grid(static_cast<unsigned>(nb < 1024 ? nb : 1024), p.ntime);
+  if (fp64)
+    hipLaunchKernelGGL(prep_baselines<double>, grid, dim3(256), 0, stream, p, nc);
+  else
+    hipLaunchKernelGGL(prep_baselines<float>, grid, dim3(256), 0, stream, p, nc);
   return hipGetLastError();
 }
 

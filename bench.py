@@ -67,12 +67,20 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--variant", type=int, default=None,
+                    help="pin the float32-mixed kernel variant (library index) instead of "
+                         "autotuning it")
     ap.add_argument("--modes", default="grad_mixed,grad_fp64,chi2_mixed,chi2_fp64",
                     help="comma list of timed evaluations (the first must be grad_mixed)")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="MiB copied device-to-device once before timing (a kernel of known "
                          "traffic for calibrating HBM counters)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    ap.add_argument("--write-traffic", nargs=2, action="append", metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="host only: write the --traffic summary from the counter_collection "
+                         "CSVs of a FETCH_SIZE and a WRITE_SIZE rocprofv3 pass of "
+                         "'bench.py --variant N --modes grad_mixed --calib-copy 1024' (one pair "
+                         "per variant) and exit")
     a = ap.parse_args()
     if a.config == "c1":
         a.config = "c2"
@@ -154,17 +162,20 @@ def kernel_source_digest():
 
 def measured_traffic(path, variant, workload):
     """HBM bytes per launch of the timed kernel, from the committed
-    FETCH_SIZE + WRITE_SIZE counter summary; None when that summary was taken
-    on other kernel sources, another variant or another workload."""
+    FETCH_SIZE + WRITE_SIZE counter summary (one entry per kernel variant);
+    None when that summary was taken on other kernel sources, or has no entry
+    for this variant and workload."""
     try:
         with open(path) as f:
             tr = json.load(f)
     except (OSError, ValueError):
         return None
-    if (tr.get("kernel_source_sha256") != kernel_source_digest() or tr.get("variant") != variant
-            or tr.get("workload", "c2") != workload):
+    if tr.get("kernel_source_sha256") != kernel_source_digest():
         return None
-    return tr.get("grad_mixed_bytes_per_launch")
+    for e in tr.get("entries", []):
+        if e.get("variant") == variant and e.get("workload") == workload:
+            return e.get("grad_mixed_bytes_per_launch")
+    return None
 
 
 def alg_flops(tp, tg):
@@ -320,7 +331,9 @@ def bench_single(args):
         chi2 = torch.empty(1, dtype=torch.float64, device="cuda")
         grad = torch.empty((sky.nsrc, 10), dtype=torch.float64, device="cuda")
         wsp = R.workspace(plan, mode, prec, 1, sky.nsrc)
-        if not args.no_autotune and (prec == R.MIXED or tune_fp64):
+        if prec == R.MIXED and args.variant is not None:
+            plan.set_variant(mode, prec, args.variant)
+        elif not args.no_autotune and (prec == R.MIXED or tune_fp64):
             # untimed: the library's autotuner picks the kernel variant
             R.rime_autotune(plan, dsky, mode, prec, D, W, wsp)
         variant = R.rime_variant_info(mode, prec, plan.get_variant(mode, prec))
@@ -568,8 +581,57 @@ def bench_latency(args):
     return rec
 
 
+def write_traffic(pairs, out_path):
+    """HBM bytes per launch of the chi^2 + gradient per-baseline kernel of the
+    c2 workload, from FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by
+    what the same counters read for the 1 GiB calibration copy; one entry per
+    (FETCH_SIZE, WRITE_SIZE) pair of counter files."""
+    import csv
+    import re
+    import statistics
+
+    pat = re.compile(r"rime_main<float, (\d+), (\d+), (\d+), 2>")
+
+    def read(path):
+        rows = list(csv.DictReader(open(path)))
+        kern, copy, names = [], [], set()
+        mc = any("pme_" in r["Kernel_Name"] for r in rows)
+        for r in rows:
+            m = pat.search(r["Kernel_Name"])
+            if m:
+                kern.append(float(r["Counter_Value"]))
+                names.add(m.groups())
+            elif "copyBuffer" in r["Kernel_Name"] and int(r["Grid_Size"]) == 131072:
+                copy.append(float(r["Counter_Value"]))
+        if len(names) != 1 or not copy:
+            raise SystemExit(f"{path}: expected one chi2+grad kernel variant and the 1 GiB copy")
+        return statistics.mean(kern), copy[0], [int(x) for x in names.pop()] + [int(mc)]
+
+    entries = []
+    for fetch_csv, write_csv in pairs:
+        fk, fc, var = read(fetch_csv)
+        wk, wc, var_w = read(write_csv)
+        if var != var_w:
+            raise SystemExit("the two passes ran different variants")
+        fscale, wscale = 1048576.0 / fc, 1048576.0 / wc
+        fb, wb = fk * 1024 * fscale, wk * 1024 * wscale
+        entries.append({"kernel": "rime_main<float, %d, %d, %d, 2>" % tuple(var[:3]),
+                        "variant": var, "workload": "c2", "fetch_kib_raw": fk,
+                        "write_kib_raw": wk, "fetch_scale": fscale, "write_scale": wscale,
+                        "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
+                        "grad_mixed_bytes_per_launch": fb + wb})
+    out = {"entries": entries, "kernel_source_sha256": kernel_source_digest()}
+    with open(out_path, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
+    if args.write_traffic:
+        write_traffic(args.write_traffic, args.traffic)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)

@@ -567,10 +567,13 @@ int default_variant(const rime_plan *plan, int mode, int prec) {
   // index layout of the compiled variants: 0 -> 64 threads, 1 -> 256, 2 -> 1024
   // (FP64 adjoint: 2 -> 256 threads x 4 channels, the fastest on 64 antennas);
   // float32-mixed 4 / 5 -> 1024 / 256 threads with the point sources on the
-  // matrix cores (measured faster from 64 antennas up)
+  // matrix cores (measured faster from 64 antennas up); the 1024-thread one
+  // only for the gradient of mid-sized arrays (2016 baselines: 22.7 vs 23.0 ms;
+  // 19306 baselines: 218.5 vs 212.7 ms)
   if (plan->nbl <= 96) return 0;
   if (prec == RIME_FP64) return 1 + (mode == RIME_MODE_CHI2_GRAD ? 1 : 0);
-  return plan->nbl >= 1024 ? 4 : 5;
+  if (mode == RIME_MODE_CHI2_GRAD && plan->nbl >= 1024 && plan->nbl < 8192) return 4;
+  return 5;
 }
 
 std::string sky_signature(const rime_sky *sky) {

@@ -29,6 +29,9 @@ shape:
   (50 t, 32 ch).  Batched in one graph launch, compared with a per-set loop
   and with the default kernel variant.
 - c4: 197 antennas (19306 baselines), 20 t, 256 ch, 1500 P + 500 G, beam.
+- c4p: the 1500 point sources of c4, beam-free (and, for chi^2, with the
+  beam), through every float32-mixed variant: the per-baseline VALU kernels
+  against the antenna x antenna contraction on the matrix cores.
 """
 from __future__ import annotations
 
@@ -55,7 +58,7 @@ PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6, "f16_mfma": 2500.0}
 FLOPS_FWD = {"p": 22, "g": 25}
 FLOPS_ADJ = {"p": 61, "g": 89}
 
-DEFAULT_STEPS = {"c0": 200, "c2": 10, "c3": 3, "c4": 3}
+DEFAULT_STEPS = {"c0": 200, "c2": 10, "c3": 3, "c4": 3, "c4p": 2}
 
 
 def parse():
@@ -63,7 +66,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="c2", choices=["c0", "c1", "c2", "c3", "c4"])
+    ap.add_argument("--config", default="c2", choices=["c0", "c1", "c2", "c3", "c4", "c4p"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
@@ -581,6 +584,76 @@ def bench_latency(args):
     return rec
 
 
+def bench_points(args):
+    """The c4 point-source comparison: the 1500 point sources of c4 (beam-free,
+    and with the beam for chi^2) through every float32-mixed variant; the best
+    per-baseline (VALU) variant against the best matrix-core variant."""
+    import torch
+
+    import paper_1501_07719_amd as R
+    from rime_synth import Observation, make_problem
+
+    pr = make_problem("c4", dense=False)
+    pts = pr.sky.subset(pr.sky.npsrc, 0)
+    obs_beam = pr.obs
+    obs_free = Observation(**{**pr.obs.__dict__, "beam": False, "pointing": None, "gains": None})
+    del pr
+    shp = (obs_free.ntime, obs_free.nbl, obs_free.nchan, 4)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1501)
+    nz = torch.randn(shp + (2,), dtype=torch.float32, device="cuda", generator=g) * 0.01
+    D = torch.view_as_complex(nz)
+    W = torch.full(shp, 1e4, dtype=torch.float32, device="cuda")
+    del nz
+    dsky = R.DeviceSky.from_host(pts)
+    chi2 = torch.empty(1, dtype=torch.float64, device="cuda")
+    grad = torch.empty((pts.nsrc, 10), dtype=torch.float64, device="cuda")
+    terms = obs_free.ntime * obs_free.nbl * obs_free.nchan * pts.nsrc
+
+    def compare(obs, mode):
+        plan = R.Plan(obs)
+        ws = R.workspace(plan, mode, R.MIXED, 1, pts.nsrc)
+        res = {"valu": (None, None), "mfma": (None, None)}
+        for vi in range(R.rime_variant_count(mode, R.MIXED)):
+            plan.set_variant(mode, R.MIXED, vi)
+            if mode == R.MODE_CHI2_GRAD:
+                call = lambda: R.rime_chi2_grad(plan, dsky, R.MIXED, D, W, chi2, grad, ws)
+            else:
+                call = lambda: R.rime_chi2(plan, dsky, R.MIXED, D, W, chi2, ws)
+            ms, _ = timed(call, args.steps, args.warmup)
+            kind = "mfma" if R.rime_variant_matrix_cores(mode, R.MIXED, vi) else "valu"
+            log(f"c4p beam={obs.beam} mode={mode} variant {vi} ({kind}): {ms:.2f} ms")
+            if res[kind][0] is None or ms < res[kind][0]:
+                res[kind] = (ms, list(R.rime_variant_info(mode, R.MIXED, vi)))
+        plan.close()
+        del ws
+        torch.cuda.empty_cache()
+        return {"valu_ms": res["valu"][0], "valu_variant": res["valu"][1],
+                "mfma_ms": res["mfma"][0], "mfma_variant": res["mfma"][1],
+                "speedup": res["valu"][0] / res["mfma"][0]}
+
+    cmp = {"chi2_beam_free": compare(obs_free, R.MODE_CHI2),
+           "chi2_with_beam": compare(obs_beam, R.MODE_CHI2),
+           "chi2_grad_beam_free": compare(obs_free, R.MODE_CHI2_GRAD)}
+    best = cmp["chi2_grad_beam_free"]["mfma_ms"]
+    rec = base_record(
+        args, "source x visibility terms/s (chi2+grad, FP32-mixed), 1 GPU", terms / (best * 1e-3),
+        best, "f32",
+        f"c4p: point subset of c4, {obs_free.na} antennas ({obs_free.nbl} baselines), "
+        f"{obs_free.ntime} timesteps, {obs_free.nchan} channels, {pts.nsrc} point sources, "
+        "beam-free; matrix-core variant against the per-baseline variants",
+        {"terms_per_eval": terms, "precision": "mixed (FP64 phase and sums)"})
+    flops = mfma_flops(obs_free, pts.nsrc)
+    achieved = flops / (best * 1e-3) / 1e12
+    rec["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS["f16_mfma"],
+                       "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS["f16_mfma"],
+                       "traffic": None,
+                       "kernel": "all kernels of the call (point sources on the matrix cores)",
+                       "kernel_ms": best, "flops_per_launch": flops}
+    rec["comparison"] = cmp
+    return rec
+
+
 def write_traffic(pairs, out_path):
     """HBM bytes per launch of the chi^2 + gradient per-baseline kernel of the
     c2 workload, from FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by
@@ -644,6 +717,8 @@ def main():
             rec = bench_batch(args)
         elif args.config == "c0":
             rec = bench_latency(args)
+        elif args.config == "c4p":
+            rec = bench_points(args)
         else:
             rec = bench_single(args)
     print(json.dumps(rec))

@@ -190,6 +190,12 @@ def _edge_problem(kind):
         g = sky.gshape.copy()
         g[:, :2] = 0
         sky = Sky(lm=sky.lm, stokes=sky.stokes, alpha=sky.alpha, gshape=g)
+    elif kind == "line_gauss":
+        # axis ratio 0 (a line; d S / d R vanishes) and a very thin ellipse
+        g = sky.gshape.copy()
+        g[0, 2] = 0.0
+        g[1, 2] = 1e-3
+        sky = Sky(lm=sky.lm, stokes=sky.stokes, alpha=sky.alpha, gshape=g)
     # observed data follow the benchmark recipe: the model at the sky's
     # parameters perturbed by 1 %, plus noise
     nz = np.random.default_rng(3).normal(0, 0.01, (obs.ntime, obs.nbl, obs.nchan, 4, 2))
@@ -201,7 +207,7 @@ def _edge_problem(kind):
 
 
 EDGES = ["gauss_only", "single_point", "one_channel", "two_antennas", "shuffled_baselines",
-         "no_beam_gains", "phase_centre", "zero_width_gauss"]
+         "no_beam_gains", "phase_centre", "zero_width_gauss", "line_gauss"]
 
 
 @pytest.mark.parametrize("kind", EDGES)

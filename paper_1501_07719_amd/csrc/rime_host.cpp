@@ -16,8 +16,8 @@
 #include "rime_internal.h"
 
 namespace rime {
-hipError_t launch_prep(const KParams &p, bool fp64, int max_nsrc, hipStream_t stream);
-hipError_t launch_prep_baselines(const KParams &p, bool fp64, int nc, hipStream_t stream);
+hipError_t launch_prep(const KParams &p, bool fp64, int max_nsrc, int rec_nc,
+                       hipStream_t stream);
 hipError_t launch_finalize(const KParams &p, int mode, int max_nsrc, hipStream_t stream);
 hipError_t launch_pme(const KParams &p, hipStream_t stream);
 hipError_t launch_pme_adjoint(const KParams &p, bool phase, hipStream_t stream);
@@ -501,9 +501,8 @@ rime_status enqueue(const rime_plan *plan, int mode, int prec, int vidx, int nse
       p.mscale = reinterpret_cast<float *>(w + L.mscale);
     }
   }
-  RIME_HIP(launch_prep(p, prec == RIME_FP64, max_nsrc, stream));
-  if (mode == RIME_MODE_CHI2_GRAD)
-    RIME_HIP(launch_prep_baselines(p, prec == RIME_FP64, v->nc, stream));
+  RIME_HIP(launch_prep(p, prec == RIME_FP64, max_nsrc,
+                       mode == RIME_MODE_CHI2_GRAD ? v->nc : 0, stream));
   if (events && plan->ev_start) RIME_HIP(hipEventRecord(plan->ev_start, stream));
   if (p.pme) {
     RIME_HIP(launch_pme_scale(p, stream));

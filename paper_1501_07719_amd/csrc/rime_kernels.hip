@@ -27,14 +27,24 @@
 namespace rime {
 
 
+template <class R>
+__device__ void prep_baselines(const KParams &p, int nc, int t);
+
 // ---------------------------------------------------------------------------
-// Per-source preparation: (l, m, n - 1), (l/n, m/n) and the spectrally scaled
-// Stokes vector per channel (eq. brightness_term).  One thread per source.
+// Per-call preparation, one launch.  Rows blockIdx.y < nset: per-source data,
+// (l, m, n - 1), (l/n, m/n), the spectrally scaled Stokes vector per channel
+// (eq. brightness_term) and the Gaussian shape coefficients, one thread per
+// source.  Rows nset + t (gradient mode, nc > 0): the adjoint's per-baseline
+// records of timestep t.
 // ---------------------------------------------------------------------------
 template <class R>
-__global__ __launch_bounds__(256) void prep_sources(const KParams p) {
+__global__ __launch_bounds__(256) void prep_sources(const KParams p, int nc) {
   using R4 = typename Num<R>::R4;
   const int set = blockIdx.y;
+  if (set >= p.nset) {
+    prep_baselines<R>(p, nc, set - p.nset);
+    return;
+  }
   const SetDesc sd = p.sets ? p.sets[set] : p.one;
   const int nsrc = sd.npsrc + sd.ngsrc;
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -83,11 +93,10 @@ __global__ __launch_bounds__(256) void prep_sources(const KParams p) {
 // The adjoint reads them with scalar loads.
 // ---------------------------------------------------------------------------
 template <class R>
-__global__ __launch_bounds__(256) void prep_baselines(const KParams p, int nc) {
+__device__ void prep_baselines(const KParams &p, int nc, int t) {
   using N = Num<R>;
   using R2 = typename N::R2;
   using R4 = typename N::R4;
-  const int t = blockIdx.y;
   const int64_t n = static_cast<int64_t>(p.ntile) * p.nbt;
   R4 *rec = static_cast<R4 *>(const_cast<void *>(p.bl_rec)) + t * n;
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < n;
@@ -217,7 +226,7 @@ __device__ inline void stage_tile(const KParams &p, const SetDesc &sd, int tile,
               // d ln e / dl = -3 tan(x) dx/dl, dx/dl = bs (l - dl_p) / r
               //             = -3 bs^2 (l - dl_p) tan(x)/x ; zero past the clip.
               R tx = R(0);
-              if (!clipped) tx = xr > R(1e-4) ? sb * N::rcp(cb * xr) : R(1) + xr * xr / R(3);
+              if (!clipped) tx = xr > R(1e-4) ? sb * N::rcp(cb * xr) : R(1) + xr * xr * R(1.0 / 3.0);
               const R k3 = static_cast<R>(-3.0 * bs * bs) * tx;
               bet[c].x = k3 * static_cast<R>(dl);
               bet[c].y = k3 * static_cast<R>(dm);
@@ -854,23 +863,15 @@ static hipError_t launch_main(const KParams &p, int nitems, hipStream_t stream) 
   return hipGetLastError();
 }
 
-hipError_t launch_prep(const KParams &p, bool fp64, int max_nsrc, hipStream_t stream) {
-  dim3 grid((max_nsrc + 255) / 256, p.nset);
+hipError_t launch_prep(const KParams &p, bool fp64, int max_nsrc, int rec_nc,
+                       hipStream_t stream) {
+  // rec_nc > 0: also the per-baseline records of every timestep (one grid row
+  // per timestep after the per-set rows)
+  dim3 grid((max_nsrc + 255) / 256, p.nset + (rec_nc > 0 ? p.ntime : 0));
   if (fp64)
-    hipLaunchKernelGGL(prep_sources<double>, grid, dim3(256), 0, stream, p);
+    hipLaunchKernelGGL(prep_sources<double>, grid, dim3(256), 0, stream, p, rec_nc);
   else
-    hipLaunchKernelGGL(prep_sources<float>, grid, dim3(256), 0, stream, p);
-  return hipGetLastError();
-}
-
-hipError_t launch_prep_baselines(const KParams &p, bool fp64, int nc, hipStream_t stream) {
-  const int64_t n = static_cast<int64_t>(p.ntile) * p.nbt;
-  const int64_t nb = (n + 255) / 256;
-  dim3 grid(static_cast<unsigned>(nb < 1024 ? nb : 1024), p.ntime);
-  if (fp64)
-    hipLaunchKernelGGL(prep_baselines<double>, grid, dim3(256), 0, stream, p, nc);
-  else
-    hipLaunchKernelGGL(prep_baselines<float>, grid, dim3(256), 0, stream, p, nc);
+    hipLaunchKernelGGL(prep_sources<float>, grid, dim3(256), 0, stream, p, rec_nc);
   return hipGetLastError();
 }
 

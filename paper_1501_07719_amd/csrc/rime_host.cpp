@@ -284,7 +284,7 @@ Geometry geometry(const rime_plan *plan, const Variant &v, int nset) {
 struct WsLayout {
   size_t geo = 0, lon = 0, st = 0, gs = 0, rec = 0, chi2 = 0, grad = 0, grad2 = 0;
   size_t ph_hi = 0, ph_lo = 0, ph_k3 = 0, spts = 0, pexp = 0, rho_t = 0, pgrad = 0;
-  size_t src_f = 0, mfrag = 0, mscale = 0;
+  size_t src_f = 0, mfrag = 0, mscale = 0, rho_g = 0;
   int32_t pme_tchunk = 0;  // timesteps per phase-plane pass (0: engine off)
   bool pme_adj = false;    // point-source adjoint on the matrix cores
   size_t total = 0;
@@ -333,6 +333,10 @@ WsLayout ws_layout(const rime_plan *plan, int mode, int prec, const Geometry &g,
   L.grad2 = off;
   if (mode == RIME_MODE_CHI2_GRAD)
     off += align_up(static_cast<size_t>(g.grad_nchunk) * total_src * 10 * sizeof(double2));
+  L.rho_g = off;
+  if (mode == RIME_MODE_CHI2_GRAD && prec == RIME_FP64 && v.nc == 2 && v.threads >= 256)
+    off += align_up(static_cast<size_t>(nset) * g.items_per_set * v.threads * v.nc * 4 *
+                    sizeof(double2));
   if (pme_active(v, prec, nset)) {
     const bool adj = mode == RIME_MODE_CHI2_GRAD && plan->pme_adj_ok;
     const bool k3 = adj && plan->beam;
@@ -467,6 +471,7 @@ rime_status enqueue(const rime_plan *plan, int mode, int prec, int vidx, int nse
   p.vis = vis;
   p.chi2_part = reinterpret_cast<double2 *>(w + L.chi2);
   p.grad_part = reinterpret_cast<double *>(w + L.grad);
+  p.rho_g = w + L.rho_g;
   p.grad_part2 = reinterpret_cast<double *>(w + L.grad2);
   p.grad_chunks = kGradChunk;
   p.grad_nchunk = g.grad_nchunk;
@@ -564,13 +569,15 @@ rime_status single(const rime_plan *plan, int mode, rime_precision prec, const r
 
 int default_variant(const rime_plan *plan, int mode, int prec) {
   // index layout of the compiled variants: 0 -> 64 threads, 1 -> 256, 2 -> 1024
-  // (FP64 adjoint: 2 -> 256 threads x 4 channels, the fastest on 64 antennas);
+  // (FP64 adjoint: 1 -> 256 threads x 2 channels with the residual tile in
+  // global memory, the fastest on 64 antennas: 93 ms against 137 ms for
+  // 2 -> 256 threads x 4 channels);
   // float32-mixed 4 / 5 -> 1024 / 256 threads with the point sources on the
   // matrix cores (measured faster from 64 antennas up); the 1024-thread one
   // only for the gradient of mid-sized arrays (2016 baselines: 22.7 vs 23.0 ms;
   // 19306 baselines: 218.5 vs 212.7 ms)
   if (plan->nbl <= 96) return 0;
-  if (prec == RIME_FP64) return 1 + (mode == RIME_MODE_CHI2_GRAD ? 1 : 0);
+  if (prec == RIME_FP64) return 1;
   if (mode == RIME_MODE_CHI2_GRAD && plan->nbl >= 1024 && plan->nbl < 8192) return 4;
   return 5;
 }

@@ -77,6 +77,8 @@ struct KParams {
   void *vis;               // predict output
   double2 *chi2_part;      // [total items] (sum, compensation)
   double *grad_part;       // gradient partials [set][item][nsrc][10]
+  void *rho_g;             // float64 gradient: residual tile per work item
+                           //   [item][nbt][nc][4] double2
   double *grad_part2;      // second-level partials [set][chunk][nsrc][10]
   int32_t grad_chunks;     // items per second-level chunk, and chunk count
   int32_t grad_nchunk;

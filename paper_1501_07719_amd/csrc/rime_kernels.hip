@@ -141,7 +141,17 @@ struct Layout {
   static constexpr size_t A_BYTES = (sizeof(R2) * NS * AST + 511) / 512 * 512;
   static constexpr size_t BETA_BYTES = GRAD ? A_BYTES : 0;
   static constexpr size_t RED_BYTES = GRAD ? sizeof(R) * NBT * 10 : 0;
-  static constexpr size_t RHO_BYTES = GRAD ? sizeof(R2) * NBT * NC * 4 : 0;
+  // The float64 gradient with two channels per thread and at least 256
+  // threads keeps the residual tile of its work item in global memory (the
+  // workspace): the adjoint reads it as a broadcast (the lanes of a wavefront
+  // need NC distinct 64-byte rows per baseline, served by the vector cache),
+  // and without its 32 KiB the kernel fits two workgroups per CU instead of
+  // one (measured at 64 antennas: 140 -> 93 ms).  The other variants keep it
+  // in LDS: the float32 ones, and the float64 ones whose registers already
+  // allow one wavefront per SIMD only, where the global reads cost time.
+  static constexpr bool RHO_GLOBAL = GRAD && sizeof(R) == 8 && NC == 2 && NBT >= 256;
+  static constexpr size_t RHO_TILE = GRAD ? sizeof(R2) * NBT * NC * 4 : 0;
+  static constexpr size_t RHO_BYTES = RHO_GLOBAL ? 0 : RHO_TILE;
   static_assert(!GRAD || NS * NC == kWave, "the adjoint maps one wavefront to NS x NC");
   // LDS byte offsets.  The residual tile comes first: the adjoint addresses it
   // per lane plus constant offsets, which fold into the 16-bit offset field of
@@ -413,7 +423,10 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
 
   // one LDS block, laid out by Layout
   __shared__ __attribute__((aligned(16))) char smem[L::LDS_BYTES];
-  R2 *s_rho = reinterpret_cast<R2 *>(smem + L::OFF_RHO);
+  R2 *s_rho = L::RHO_GLOBAL
+                  ? static_cast<R2 *>(p.rho_g) +
+                        static_cast<int64_t>(blockIdx.x) * (L::RHO_TILE / sizeof(R2))
+                  : reinterpret_cast<R2 *>(smem + L::OFF_RHO);
   R2 *s_a = reinterpret_cast<R2 *>(smem + L::OFF_A);
   R2 *s_beta = reinterpret_cast<R2 *>(smem + L::OFF_BETA);
   R *s_red = reinterpret_cast<R *>(smem + L::OFF_RED);

@@ -83,7 +83,8 @@ def parse():
                     help="host only: write the --traffic summary from the counter_collection "
                          "CSVs of a FETCH_SIZE and a WRITE_SIZE rocprofv3 pass of "
                          "'bench.py --variant N --modes grad_mixed --calib-copy 1024' (one pair "
-                         "per variant) and exit")
+                         "per variant) for the workload given by --config, merged into an "
+                         "existing summary of the same kernel sources, and exit")
     a = ap.parse_args()
     if a.config == "c1":
         a.config = "c2"
@@ -654,11 +655,13 @@ def bench_points(args):
     return rec
 
 
-def write_traffic(pairs, out_path):
-    """HBM bytes per launch of the chi^2 + gradient per-baseline kernel of the
-    c2 workload, from FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by
+def write_traffic(pairs, out_path, workload="c2"):
+    """HBM bytes per launch of the chi^2 + gradient per-baseline kernel of
+    `workload`, from FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by
     what the same counters read for the 1 GiB calibration copy; one entry per
-    (FETCH_SIZE, WRITE_SIZE) pair of counter files."""
+    (FETCH_SIZE, WRITE_SIZE) pair of counter files.  Entries of an existing
+    summary taken on the same kernel sources are kept unless replaced (same
+    variant and workload)."""
     import csv
     import re
     import statistics
@@ -689,11 +692,21 @@ def write_traffic(pairs, out_path):
         fscale, wscale = 1048576.0 / fc, 1048576.0 / wc
         fb, wb = fk * 1024 * fscale, wk * 1024 * wscale
         entries.append({"kernel": "rime_main<float, %d, %d, %d, 2>" % tuple(var[:3]),
-                        "variant": var, "workload": "c2", "fetch_kib_raw": fk,
+                        "variant": var, "workload": workload, "fetch_kib_raw": fk,
                         "write_kib_raw": wk, "fetch_scale": fscale, "write_scale": wscale,
                         "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
                         "grad_mixed_bytes_per_launch": fb + wb})
-    out = {"entries": entries, "kernel_source_sha256": kernel_source_digest()}
+    digest = kernel_source_digest()
+    try:
+        with open(out_path) as f:
+            old = json.load(f)
+    except (OSError, ValueError):
+        old = {}
+    if old.get("kernel_source_sha256") == digest:
+        new_keys = {(tuple(e["variant"]), e["workload"]) for e in entries}
+        entries = [e for e in old.get("entries", [])
+                   if (tuple(e["variant"]), e["workload"]) not in new_keys] + entries
+    out = {"entries": entries, "kernel_source_sha256": digest}
     with open(out_path, "w") as f:
         json.dump(out, f, indent=1)
         f.write("\n")
@@ -703,7 +716,7 @@ def write_traffic(pairs, out_path):
 def main():
     args = parse()
     if args.write_traffic:
-        write_traffic(args.write_traffic, args.traffic)
+        write_traffic(args.write_traffic, args.traffic, args.config)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))

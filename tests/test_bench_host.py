@@ -60,6 +60,17 @@ def test_traffic_round_trip(tmp_path):
         e5["grad_mixed_bytes_per_launch"])
     assert bench.measured_traffic(str(out), [256, 2, 32, 0], "c2") is None
     assert bench.measured_traffic(str(out), [1024, 2, 32, 1], "c4") is None
+    # a second workload is merged in; the c2 entries stay
+    fetch6, write6 = tmp_path / "f6.csv", tmp_path / "w6.csv"
+    write_counters(fetch6, "FETCH_SIZE", 524288.0, [700.0], threads=256)
+    write_counters(write6, "WRITE_SIZE", 1048576.0, [100.0], threads=256)
+    bench.write_traffic([(str(fetch6), str(write6))], str(out), "c4")
+    assert bench.measured_traffic(str(out), [256, 2, 32, 1], "c4") == pytest.approx(
+        (700.0 * 2 + 100.0) * 1024)
+    assert bench.measured_traffic(str(out), [256, 2, 32, 1], "c2") == pytest.approx(
+        e5["grad_mixed_bytes_per_launch"])
+    tr = json.loads(out.read_text())
+    assert len(tr["entries"]) == 3
     # another kernel source: the summary no longer applies
     tr["kernel_source_sha256"] = "0" * 64
     out.write_text(json.dumps(tr))

@@ -58,14 +58,16 @@ PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6, "f16_mfma": 2500.0}
 FLOPS_FWD = {"p": 22, "g": 25}
 FLOPS_ADJ = {"p": 61, "g": 89}
 
-DEFAULT_STEPS = {"c0": 200, "c2": 10, "c3": 3, "c4": 3, "c4p": 2}
+# timed repetitions per workload (at least 20 where a step is short) after
+# --warmup untimed ones
+DEFAULT_STEPS = {"c0": 200, "c2": 20, "c3": 10, "c4": 20, "c4p": 2}
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="c2", choices=["c0", "c1", "c2", "c3", "c4", "c4p"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
@@ -220,11 +222,14 @@ def rooflines(g, tp, tg, obs, sky, traffic):
     return {"roofline": main, "roofline_other": mc}
 
 
-def timed(call, steps, warmup, events_fns=()):
+def timed(call, steps, warmup, events_fns=(), per_step=False):
     """Mean ms per call over `steps` timed calls after `warmup` untimed ones.
     Each of `events_fns` is a setter `fn(start, stop)` installing a pair of
-    per-call timing events in the library (None, None removes it); returns
-    (ms, [mean ms between each pair])."""
+    per-call timing events in the library (None, None removes it).  Returns
+    (ms, [mean ms between each pair], per-call ms or None).  With `per_step`,
+    a second pass of `steps` calls records an event after every call (kept
+    out of the first pass, where the extra records would add to a launch-bound
+    mean) and gives the per-call times."""
     import torch
     for _ in range(warmup):
         call()
@@ -251,7 +256,23 @@ def timed(call, steps, warmup, events_fns=()):
         fn(None, None)
     ms = start.elapsed_time(stop) / steps
     kms = [float(np.mean([ks[i].elapsed_time(ke[i]) for i in range(steps)])) for ks, ke in evs]
-    return ms, kms
+    step_ms = None
+    if per_step:
+        marks = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        marks[0].record()
+        for i in range(steps):
+            call()
+            marks[i + 1].record()
+        torch.cuda.synchronize()
+        step_ms = [marks[i].elapsed_time(marks[i + 1]) for i in range(steps)]
+    return ms, kms, step_ms
+
+
+def step_stats(step_ms):
+    """Median and 10th/90th percentiles of per-call times (ms)."""
+    a = np.asarray(step_ms, dtype=np.float64)
+    return {"n": int(a.size), "median": float(np.median(a)),
+            "p10": float(np.percentile(a, 10)), "p90": float(np.percentile(a, 90))}
 
 
 def mfma_flops(obs, npsrc):
@@ -348,10 +369,12 @@ def bench_single(args):
             else:
                 R.rime_chi2(plan, dsky, prec, D, W, chi2, wsp)
 
-        ms, (kms, mms) = timed(call, steps, warmup,
-                               (plan.set_timing_events, plan.set_main_events))
+        ms, (kms, mms), step_ms = timed(call, steps, warmup,
+                                        (plan.set_timing_events, plan.set_main_events),
+                                        per_step=True)
         mc = R.rime_variant_matrix_cores(mode, prec, plan.get_variant(mode, prec))
-        return {"ms_per_step": ms, "kernel_ms": kms, "main_ms": mms, "chi2": chi2.item(),
+        return {"ms_per_step": ms, "step_ms": step_stats(step_ms), "kernel_ms": kms,
+                "main_ms": mms, "chi2": chi2.item(),
                 "variant": variant, "matrix_cores": mc,
                 "terms_per_s": terms / (ms * 1e-3), "evals_per_s": 1e3 / ms}
 
@@ -380,6 +403,7 @@ def bench_single(args):
         f"Gaussian sources, beam",
         {"terms_per_eval": terms, "precision": "mixed (FP64 phase and sums)"})
     rec["evals_per_s"] = g["evals_per_s"]
+    rec["step_ms"] = g["step_ms"]
     rec["variant"] = {"per_baseline": list(g["variant"]), "matrix_cores": g["matrix_cores"]}
     rec.update(rooflines(g, tp, tg, obs, sky, traffic))
     if "grad_fp64" in out:
@@ -453,11 +477,11 @@ def bench_batch(args):
     v_tuned = R.rime_batch_get_variant(batch, R.MODE_CHI2_GRAD, R.MIXED)
     variant = R.rime_variant_info(R.MODE_CHI2_GRAD, R.MIXED, v_tuned)
     call, ws = batched(R.MIXED, True)
-    res["graph_tuned"] = timed(call, args.steps, 1)[0]
+    res["graph_tuned"], _, tuned_steps = timed(call, args.steps, 1, per_step=True)
     log("graph tuned", variant, res["graph_tuned"])
     # the same launches without the graph, with the main kernel timed alone
     call, ws = batched(R.MIXED, False)
-    res["stream_tuned"], (kms,) = timed(call, args.steps, 1, (plan.set_timing_events,))
+    res["stream_tuned"], (kms,), _ = timed(call, args.steps, 1, (plan.set_timing_events,))
     log("stream tuned", res["stream_tuned"], "kernel", kms)
     del ws, call
     # per-set loop: one rime_chi2_grad call per proposal, same variant
@@ -487,6 +511,7 @@ def bench_batch(args):
         f"{obs.ntime} timesteps, {obs.nchan} channels, beam; one hipGraph launch",
         {"terms_per_eval": terms, "sets": nset, "precision": "mixed (FP64 phase and sums)"})
     rec["evals_per_s"] = nset * 1e3 / ms
+    rec["step_ms"] = step_stats(tuned_steps)
     mc = R.rime_variant_matrix_cores(R.MODE_CHI2_GRAD, R.MIXED, v_tuned)
     rec["roofline"] = roofline(alg_flops(tp, tg), kms, variant, None)
     if mc:
@@ -547,8 +572,8 @@ def bench_latency(args):
     def plain_call():
         R.rime_chi2_grad(plan, dsky, R.FP64, D64, W64, chi2, grad, ws)
 
-    ms_graph, _ = timed(graph_call, args.steps, args.warmup)
-    ms_plain, (kms,) = timed(plain_call, args.steps, args.warmup, (plan.set_timing_events,))
+    ms_graph, _, graph_steps = timed(graph_call, args.steps, args.warmup, per_step=True)
+    ms_plain, (kms,), _ = timed(plain_call, args.steps, args.warmup, (plan.set_timing_events,))
     variant = R.rime_variant_info(R.MODE_CHI2_GRAD, R.FP64,
                                   plan.get_variant(R.MODE_CHI2_GRAD, R.FP64))
     rec = base_record(
@@ -558,6 +583,7 @@ def bench_latency(args):
         f"{obs.nchan} channels, {sky.npsrc} point sources, no beam; one hipGraph launch",
         {"terms_per_eval": terms, "precision": "fp64"})
     rec["evals_per_s"] = 1e3 / ms_graph
+    rec["step_ms"] = step_stats(graph_steps)
     rec["latency_us"] = {"graph": ms_graph * 1e3, "stream": ms_plain * 1e3,
                          "main_kernel": kms * 1e3}
     flops = alg_flops(terms, 0)
@@ -621,7 +647,7 @@ def bench_points(args):
                 call = lambda: R.rime_chi2_grad(plan, dsky, R.MIXED, D, W, chi2, grad, ws)
             else:
                 call = lambda: R.rime_chi2(plan, dsky, R.MIXED, D, W, chi2, ws)
-            ms, _ = timed(call, args.steps, args.warmup)
+            ms, _, _ = timed(call, args.steps, args.warmup)
             kind = "mfma" if R.rime_variant_matrix_cores(mode, R.MIXED, vi) else "valu"
             log(f"c4p beam={obs.beam} mode={mode} variant {vi} ({kind}): {ms:.2f} ms")
             if res[kind][0] is None or ms < res[kind][0]:

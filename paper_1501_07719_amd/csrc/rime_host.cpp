@@ -284,7 +284,7 @@ Geometry geometry(const rime_plan *plan, const Variant &v, int nset) {
 struct WsLayout {
   size_t geo = 0, lon = 0, st = 0, gs = 0, rec = 0, chi2 = 0, grad = 0, grad2 = 0;
   size_t ph_hi = 0, ph_lo = 0, ph_k3 = 0, spts = 0, pexp = 0, rho_t = 0, pgrad = 0;
-  size_t src_f = 0, mfrag = 0, mscale = 0, rho_g = 0;
+  size_t src_f = 0, mfrag = 0, mscale = 0, rho_g = 0, pfin = 0;
   int32_t pme_tchunk = 0;  // timesteps per phase-plane pass (0: engine off)
   bool pme_adj = false;    // point-source adjoint on the matrix cores
   size_t total = 0;
@@ -370,6 +370,10 @@ WsLayout ws_layout(const rime_plan *plan, int mode, int prec, const Geometry &g,
       L.pgrad = off;
       off += align_up(static_cast<size_t>((total_src + kPmeSR - 1) / kPmeSR) * plan->ntime *
                       pme_ncg(plan) * plan->nblk * pme_nqr(plan) * kPmeSR * 7 * sizeof(float));
+      L.pfin = off;
+      off += align_up(static_cast<size_t>(std::max<int64_t>(kPmeFinWG, (total_src + kPmeSR - 1) /
+                                                                           kPmeSR)) *
+                      kPmeSR * 7 * sizeof(double2));
       L.src_f = off;
       off += align_up(static_cast<size_t>(total_src) * plan->nchan * sizeof(float));
       const size_t nfrag = static_cast<size_t>(L.pme_tchunk) * plan->nchan * plan->nblk *
@@ -501,6 +505,9 @@ rime_status enqueue(const rime_plan *plan, int mode, int prec, int vidx, int nse
       p.pme_ncg = pme_ncg(plan);
       p.pme_nqr = pme_nqr(plan);
       p.pme_nsr = (one.npsrc + kPmeSR - 1) / kPmeSR;
+      p.pfin = reinterpret_cast<double2 *>(w + L.pfin);
+      p.pme_fchunk = pme_fin_nchunk(
+          p.pme_nsr, static_cast<int64_t>(plan->ntime) * p.pme_ncg * plan->nblk * p.pme_nqr);
       p.src_f = reinterpret_cast<float *>(w + L.src_f);
       p.mfrag = reinterpret_cast<uint4 *>(w + L.mfrag);
       p.mscale = reinterpret_cast<float *>(w + L.mscale);

@@ -109,6 +109,9 @@ struct KParams {
                            //   Stokes form (conjugated for baselines stored as (q, p))
   float *pgrad;            // adjoint partials [nsr][ntime][ncg][nblk][nqr][kPmeSR][7]
   int32_t pme_ncg, pme_nqr, pme_nsr;
+  double2 *pfin;           // float64 sums of pgrad over item chunks
+                           //   [nsr][pme_fchunk][kPmeSR * 7] (sum, compensation)
+  int32_t pme_fchunk;      // item chunks of those sums
   uint4 *mfrag;            // [pme_nt][nchan][nblk][nqr][4][8][64][2] fp16 fragments of M
   float *mscale;           // [pme_nt][nchan][nblk][nqr] 2^e undoing the fragment scale
 };
@@ -120,6 +123,15 @@ constexpr int kPmeBlk = 32;
 constexpr int kPmeNQ = 2;
 constexpr int kPmeSR = 512;
 constexpr int kPmeNCW = 8;
+
+// The sums of the adjoint partials over items run as about kPmeFinWG
+// workgroups of 256 columns (kPmeSR * 7 = 14 x 256) before one pass over the
+// chunks: nsr * chunks <= max(kPmeFinWG, nsr) chunk rows of kPmeSR * 7.
+constexpr int kPmeFinWG = 2048 / (kPmeSR * 7 / 256);
+inline int pme_fin_nchunk(int nsr, int64_t nper) {
+  const int64_t n = kPmeFinWG / (nsr > 0 ? nsr : 1);
+  return static_cast<int>(n < 1 ? 1 : n < nper ? n : (nper > 0 ? nper : 1));
+}
 
 // Padding (in records) after the per-baseline records of the adjoint, which
 // reads one record ahead.

@@ -25,7 +25,8 @@
 //   pme_mfrag    the residual matrices of the adjoint as fp16 MFMA fragments;
 //   pme_adjoint  the gradient of chi^2 with respect to the point-source
 //                parameters (see the comment there);
-//   pme_finalize float64 sums of the adjoint's per-workgroup partials.
+//   pme_fin_items, pme_finalize
+//                float64 sums of the adjoint's per-workgroup partials.
 // Operand fragments follow the gfx950 lane layout of the 32x32x16 fp16
 // instruction: A[i][k] in lane i + 32 (k / 8), element k % 8; B[k][j] in lane
 // j + 32 (k / 8), element k % 8; D[i][j] in lane j + 32 ((i / 4) % 2),
@@ -726,23 +727,51 @@ __global__ __launch_bounds__(256, 2) void pme_adjoint(const KParams p) {
   for (int i = tid; i < (send - sbeg) * 7; i += 256) dst[i] = (&s_acc[0][0])[i];
 }
 
-// Point-source gradient rows from the adjoint partials: one workgroup per
-// source, float64 sums in a fixed order; columns 7..9 (shape) are zero.
-__global__ __launch_bounds__(256) void pme_finalize(const KParams p) {
-  __shared__ double2 scr[256 / kWave];
-  const int s = blockIdx.x;
-  const int sr = s / kPmeSR, sl = s % kPmeSR;
-  const int nper = p.ntime * p.pme_ncg * p.nblk * p.pme_nqr;
-  const float *src = p.pgrad + static_cast<int64_t>(sr) * nper * (kPmeSR * 7) + sl * 7;
-  for (int j = 0; j < 7; ++j) {
-    Comp acc;
-    for (int i = threadIdx.x; i < nper; i += 256)
-      acc.add(static_cast<double>(src[static_cast<int64_t>(i) * (kPmeSR * 7) + j]));
-    const Comp r = block_reduce<256>(acc, scr);
-    if (threadIdx.x == 0) p.grad_out[(p.one.src_off + s) * 10 + j] = 2.0 * (r.s + r.c);
-    __syncthreads();
+// Point-source gradient rows from the adjoint partials, in two float64 passes
+// with a fixed order.  pme_fin_items: thread = one column (source, component)
+// of the partial rows, workgroup = 256 contiguous columns of one source range
+// and one chunk of items, so every item row is read as one contiguous 1 KiB
+// run.  pme_finalize: thread = (source, gradient column), summing the chunks;
+// columns 7..9 (shape) are zero.
+__global__ __launch_bounds__(256) void pme_fin_items(const KParams p) {
+  constexpr int kRow = kPmeSR * 7;
+  const int sr = blockIdx.y, ch = blockIdx.z;
+  const int col = blockIdx.x * 256 + threadIdx.x;
+  if (col >= min(kPmeSR, p.one.npsrc - sr * kPmeSR) * 7) return;
+  const int64_t nper = static_cast<int64_t>(p.ntime) * p.pme_ncg * p.nblk * p.pme_nqr;
+  const int64_t cs = (nper + p.pme_fchunk - 1) / p.pme_fchunk;
+  const int64_t i1 = min(nper, (ch + 1) * cs);
+  const float *src = p.pgrad + static_cast<int64_t>(sr) * nper * kRow + col;
+  Comp acc;
+  int64_t i = ch * cs;
+  for (; i + 4 <= i1; i += 4) {
+    float v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = src[(i + k) * kRow];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc.add(static_cast<double>(v[k]));
   }
-  if (threadIdx.x < 3) p.grad_out[(p.one.src_off + s) * 10 + 7 + threadIdx.x] = 0.0;
+  for (; i < i1; ++i) acc.add(static_cast<double>(src[i * kRow]));
+  p.pfin[(static_cast<int64_t>(sr) * p.pme_fchunk + ch) * kRow + col] = make_double2(acc.s, acc.c);
+}
+
+__global__ __launch_bounds__(256) void pme_finalize(const KParams p) {
+  constexpr int kRow = kPmeSR * 7;
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (idx >= static_cast<int64_t>(p.one.npsrc) * 10) return;
+  const int s = static_cast<int>(idx / 10), j = static_cast<int>(idx % 10);
+  double out = 0.0;
+  if (j < 7) {
+    const int sr = s / kPmeSR, sl = s % kPmeSR;
+    const double2 *src = p.pfin + static_cast<int64_t>(sr) * p.pme_fchunk * kRow + sl * 7 + j;
+    Comp r;
+    for (int ch = 0; ch < p.pme_fchunk; ++ch) {
+      const double2 v = src[static_cast<int64_t>(ch) * kRow];
+      r.merge(v.x, v.y);
+    }
+    out = 2.0 * (r.s + r.c);
+  }
+  p.grad_out[p.one.src_off * 10 + idx] = out;
 }
 
 // ---------------------------------------------------------------------------
@@ -787,7 +816,14 @@ hipError_t launch_pme_adjoint(const KParams &p, bool phase, hipStream_t stream) 
 
 hipError_t launch_pme_finalize(const KParams &p, hipStream_t stream) {
   if (p.one.npsrc <= 0) return hipSuccess;
-  hipLaunchKernelGGL(pme_finalize, dim3(p.one.npsrc), dim3(256), 0, stream, p);
+  const dim3 g1(kPmeSR * 7 / 256, static_cast<unsigned>(p.pme_nsr),
+                static_cast<unsigned>(p.pme_fchunk));
+  hipLaunchKernelGGL(pme_fin_items, g1, dim3(256), 0, stream, p);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t n = static_cast<int64_t>(p.one.npsrc) * 10;
+  hipLaunchKernelGGL(pme_finalize, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0,
+                     stream, p);
   return hipGetLastError();
 }
 

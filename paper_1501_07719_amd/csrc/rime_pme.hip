@@ -383,18 +383,16 @@ __global__ __launch_bounds__(256, 2) void pme_forward(const KParams p) {
 // ---------------------------------------------------------------------------
 constexpr int kPmeBRow = 2 * kPmeBlk * kPmeNQ + 8;  // fp16 per B row: (q, re/im) + pad
 
-__device__ inline float2 rho_at(const KParams &p, int64_t base, int pair, int i, int j) {
-  if (pair < 0) return make_float2(0.0f, 0.0f);
-  if (!((p.pair_mask[pair * kPmeBlk + i] >> j) & 1u)) return make_float2(0.0f, 0.0f);
-  return p.rho_t[base + static_cast<int64_t>(pair) * 4 * kPmeBlk * kPmeBlk + i * kPmeBlk + j];
-}
-
 // Fragments of M_k (rows of block P, columns of the q range) for one
 // (timestep, channel): workgroup = (timestep, channel, P, q range),
 // wavefront = k.  Element e of K-step st of lane (row, g) is (q, re/im) with
-// q = 8 st + 4 g + e / 2 local to the range.
+// q = 8 st + 4 g + e / 2 local to the range.  Each wavefront first copies the
+// residual tiles of its q blocks into LDS with contiguous 16-byte loads
+// (slots that hold no baseline read as zero), so that the row-wise and the
+// transposed reads of the fragment layout come from LDS.
 __global__ __launch_bounds__(256) void pme_mfrag(const KParams p) {
   __shared__ float s_gmax[4];
+  __shared__ float2 s_t[4][kPmeNQ][kPmeBlk][kPmeBlk + 1];  // [k][q block][i][j]
   const int nP = p.nblk, nQR = p.pme_nqr;
   const int item = blockIdx.x;  // ((tt * nchan + c) * nP + P) * nQR + qr
   int rest = item;
@@ -412,38 +410,52 @@ __global__ __launch_bounds__(256) void pme_mfrag(const KParams p) {
   const int row = lane & 31, g = lane >> 5;
   const int64_t base =
       ((static_cast<int64_t>(t) * p.nchan + c) * p.npair * 4 + k) * (kPmeBlk * kPmeBlk);
+#pragma unroll
+  for (int b = 0; b < kPmeNQ; ++b) {
+    const int qb = Q0 + b;
+    const int pr = b < nq ? p.pair_of[min(P, qb) * nP + max(P, qb)] : -1;
+    const float4 *src = reinterpret_cast<const float4 *>(
+        p.rho_t + base + static_cast<int64_t>(max(pr, 0)) * 4 * kPmeBlk * kPmeBlk);
+#pragma unroll
+    for (int it = 0; it < kPmeBlk * kPmeBlk / 2 / kWave; ++it) {
+      const int idx = it * kWave + lane;  // float4 index: row i, columns j, j + 1
+      const int i = idx / (kPmeBlk / 2), j = (idx % (kPmeBlk / 2)) * 2;
+      float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      uint32_t m = 0u;
+      if (pr >= 0) {
+        v = src[idx];
+        m = p.pair_mask[pr * kPmeBlk + i] >> j;
+      }
+      s_t[k][b][i][j] = (m & 1u) ? make_float2(v.x, v.y) : make_float2(0.0f, 0.0f);
+      s_t[k][b][i][j + 1] = (m & 2u) ? make_float2(v.z, v.w) : make_float2(0.0f, 0.0f);
+    }
+  }
+  __syncthreads();
   float2 m[kPmeNQ * 4][4];
   float mx = 0.0f;
 #pragma unroll
   for (int st = 0; st < kPmeNQ * 4; ++st) {
     const int ql = 8 * st + 4 * g;
-    const int qb = Q0 + ql / kPmeBlk;
+    const int b = ql / kPmeBlk;
+    const int qb = Q0 + b;
     const int j0 = ql % kPmeBlk;
-    int pr = -1, mode = 0;  // 0: T[P][qb], 1: T + T^H (P == qb), 2: T[qb][P]^H
-    if (st < nq * 4) {
-      if (qb == P) {
-        pr = p.pair_of[P * nP + P];
-        mode = 1;
-      } else if (P < qb) {
-        pr = p.pair_of[P * nP + qb];
-      } else {
-        pr = p.pair_of[qb * nP + P];
-        mode = 2;
-      }
-    }
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int j = j0 + e;
       float2 v = make_float2(0.0f, 0.0f);
-      if (mode == 0) {
-        v = rho_at(p, base, pr, row, j);
-      } else if (mode == 1) {
-        const float2 a = rho_at(p, base, pr, row, j);
-        const float2 b = rho_at(p, base, pr, j, row);
-        v = make_float2(a.x + b.x, a.y - b.y);
-      } else {
-        const float2 b = rho_at(p, base, pr, j, row);
-        v = make_float2(b.x, -b.y);
+      if (st < nq * 4) {
+        if (qb == P) {
+          // T + T^H on the diagonal block
+          const float2 x = s_t[k][b][row][j];
+          const float2 y = s_t[k][b][j][row];
+          v = make_float2(x.x + y.x, x.y - y.y);
+        } else if (P < qb) {
+          v = s_t[k][b][row][j];
+        } else {
+          // the tile is stored as (qb, P): conjugate transpose
+          const float2 y = s_t[k][b][j][row];
+          v = make_float2(y.x, -y.y);
+        }
       }
       m[st][e] = v;
       mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));

@@ -99,6 +99,7 @@ struct KParams {
   const int32_t *groups;   // [ngroup][5] (Q, Pa, Pb or -1, pair of (Pa, Q), pair of (Pb, Q))
   int32_t *pme_exp;        // [nchan][4] exponent of max_s |St'_k| (forward scale 2^-e)
   int32_t pme_t0, pme_nt;  // timesteps held by the phase planes
+  int32_t phase_nc;        // channels per workgroup of the phase planes (set at launch)
   double2 *spts;           // [ntime][nchan][npair][4][kPmeBlk][kPmeBlk] Stokes sums
   // matrix-core adjoint of the point sources
   int32_t pme_adj;         // 1: point-source gradient from the antenna-pair product

@@ -6,7 +6,9 @@ gradient to the mixed tolerance (1e-5 of F_nu, 1e-5 relative).
 The observations span several 32-antenna blocks with a ragged last block,
 baselines in arbitrary order with swapped antenna pairs across blocks (the
 engine then takes the conjugate of the stored pair), a duplicate baseline and
-an autocorrelation, with and without the beam.
+an autocorrelation, with and without the beam. Two cases end the channel
+blocks of the phase planes with a partial block: 16 + 3 channels for small
+planes, and 4 + 3 for planes of 1 MiB and more.
 """
 import numpy as np
 import pytest
@@ -54,6 +56,20 @@ def problem(kind):
     elif kind == "gauss_only":
         pr = make_problem("c1", ntime=1, nchan=2, npsrc=0, ngsrc=10, na=34, key=34)
         obs, sky = pr.obs, pr.sky
+    elif kind == "ragged_channel_blocks":
+        # small phase planes are written in blocks of 16 channels: 16 + 3
+        pr = make_problem("c1", ntime=2, nchan=19, npsrc=40, ngsrc=8, na=40, key=35)
+        obs, sky = pr.obs, pr.sky
+    elif kind == "wide_planes":
+        # 1200 sources x 224 padded antennas: 1.08 MB planes, written in blocks
+        # of 4 channels (7 channels: 4 + 3); 60 of the baselines keep the
+        # oracle small (the plane size depends on the antennas only)
+        pr = make_problem("c4", ntime=1, nchan=7, npsrc=1200, ngsrc=0, na=197, key=36,
+                          dense=False)
+        obs, sky = pr.obs, pr.sky
+        keep = np.sort(rng.choice(obs.nbl, 60, replace=False))
+        obs = Observation(**{**obs.__dict__, "ant1": obs.ant1[keep].copy(),
+                             "ant2": obs.ant2[keep].copy()})
     else:
         raise ValueError(kind)
     nz = np.random.default_rng(3).normal(0, 0.01, (obs.ntime, obs.nbl, obs.nchan, 4, 2))
@@ -64,7 +80,8 @@ def problem(kind):
     return obs, sky, D, W
 
 
-KINDS = ["three_blocks", "shuffled_swapped", "points_no_beam", "gauss_only"]
+KINDS = ["three_blocks", "shuffled_swapped", "points_no_beam", "gauss_only",
+         "ragged_channel_blocks", "wide_planes"]
 
 
 @pytest.mark.parametrize("kind", KINDS)

@@ -820,7 +820,17 @@ __global__ __launch_bounds__(256) void finalize_chi2(const KParams p) {
   const int set = blockIdx.x;
   Comp acc;
   const double2 *part = p.chi2_part + static_cast<int64_t>(set) * p.items_per_set;
-  for (int i = threadIdx.x; i < p.items_per_set; i += 256) {
+  // each thread merges items tid, tid + 256, ... in that order; four loads are
+  // issued before they are merged
+  int i = threadIdx.x;
+  for (; i + 3 * 256 < p.items_per_set; i += 4 * 256) {
+    double2 v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = part[i + k * 256];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc.merge(v[k].x, v[k].y);
+  }
+  for (; i < p.items_per_set; i += 256) {
     const double2 v = part[i];
     acc.merge(v.x, v.y);
   }
@@ -842,7 +852,16 @@ __global__ __launch_bounds__(256) void finalize_grad1(const KParams p) {
   const int64_t stride = static_cast<int64_t>(nsrc) * 10;
   const double *src = p.grad_part + sd.src_off * p.items_per_set * 10 + idx;
   Comp acc;
-  for (int i = i0; i < i1; ++i) acc.add(src[i * stride]);
+  // items in order; eight loads are issued before they are added
+  int i = i0;
+  for (; i + 8 <= i1; i += 8) {
+    double v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = src[(i + k) * stride];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc.add(v[k]);
+  }
+  for (; i < i1; ++i) acc.add(src[i * stride]);
   double2 *dst = reinterpret_cast<double2 *>(p.grad_part2) +
                  sd.src_off * p.grad_nchunk * 10 + static_cast<int64_t>(chunk) * stride + idx;
   *dst = make_double2(acc.s, acc.c);
@@ -859,7 +878,16 @@ __global__ __launch_bounds__(256) void finalize_grad2(const KParams p) {
   const double2 *src = reinterpret_cast<const double2 *>(p.grad_part2) +
                        sd.src_off * p.grad_nchunk * 10 + idx;
   Comp acc;
-  for (int j = 0; j < p.grad_nchunk; ++j) {
+  // chunks in order; eight loads are issued before they are merged
+  int j = 0;
+  for (; j + 8 <= p.grad_nchunk; j += 8) {
+    double2 v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = src[(j + k) * stride];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc.merge(v[k].x, v[k].y);
+  }
+  for (; j < p.grad_nchunk; ++j) {
     const double2 v = src[j * stride];
     acc.merge(v.x, v.y);
   }

@@ -119,11 +119,14 @@ struct KParams {
 
 // Antenna block of the matrix-core engine (rows and columns of one MFMA tile),
 // and the work split of its adjoint: antenna blocks per Q range, sources per
-// source range, channels per workgroup.
+// source range, channels per workgroup.  Four channels per workgroup rather
+// than eight halve the idle tail of the last round of workgroups on small
+// arrays: 64 antennas, 100 timesteps, 64 channels and 1000 sources take
+// 3.33 ms against 3.58 ms; 197 antennas are unchanged.
 constexpr int kPmeBlk = 32;
 constexpr int kPmeNQ = 2;
 constexpr int kPmeSR = 512;
-constexpr int kPmeNCW = 8;
+constexpr int kPmeNCW = 4;
 
 // The sums of the adjoint partials over items run as about kPmeFinWG
 // workgroups of 256 columns (kPmeSR * 7 = 14 x 256) before one pass over the

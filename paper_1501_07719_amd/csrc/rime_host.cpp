@@ -584,8 +584,8 @@ int default_variant(const rime_plan *plan, int mode, int prec) {
   // only for the gradient of mid-sized arrays (2016 baselines: 22.7 vs 23.0 ms;
   // 19306 baselines: 218.5 vs 212.7 ms); small arrays take 1 in both
   // precisions (7 antennas, 10 timesteps, 16 channels, 20 sources, one graph
-  // launch of chi2 + gradient: FP64 32 us against 37 us for 0, float32-mixed
-  // 29 us against 31 us for 0 and 87 us for 5)
+  // launch of chi2 + gradient: FP64 30 us against 34 us for 0, float32-mixed
+  // 26 us against 28 us for 0 and 75 us for 5)
   if (prec == RIME_FP64 || plan->nbl <= 96) return 1;
   if (mode == RIME_MODE_CHI2_GRAD && plan->nbl >= 1024 && plan->nbl < 8192) return 4;
   return 5;

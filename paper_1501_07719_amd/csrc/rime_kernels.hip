@@ -815,9 +815,9 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
 // ---------------------------------------------------------------------------
 // Finalize: deterministic compensated sums of the per-item partials.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void finalize_chi2(const KParams p) {
-  __shared__ double2 scr[256 / kWave];
-  const int set = blockIdx.x;
+// chi^2 of one set from its per-item (sum, compensation) partials, in a fixed
+// order; all 256 threads of the workgroup take part.
+__device__ inline void chi2_reduce(const KParams &p, int set, double2 *scr) {
   Comp acc;
   const double2 *part = p.chi2_part + static_cast<int64_t>(set) * p.items_per_set;
   // each thread merges items tid, tid + 256, ... in that order; four loads are
@@ -838,10 +838,22 @@ __global__ __launch_bounds__(256) void finalize_chi2(const KParams p) {
   if (threadIdx.x == 0) p.chi2_out[set] = r.s + r.c;
 }
 
+__global__ __launch_bounds__(256) void finalize_chi2(const KParams p) {
+  __shared__ double2 scr[256 / kWave];
+  chi2_reduce(p, blockIdx.x, scr);
+}
+
 // Level 1: grid (source-parameter blocks, item chunks, sets); each thread
 // sums `grad_chunks` consecutive items of one (source, parameter).
+// In gradient mode the grid has one more row of chunks (blockIdx.y ==
+// grad_nchunk) whose first workgroup forms chi^2 instead, which saves a launch.
 __global__ __launch_bounds__(256) void finalize_grad1(const KParams p) {
+  __shared__ double2 scr[256 / kWave];
   const int set = blockIdx.z;
+  if (static_cast<int>(blockIdx.y) == p.grad_nchunk) {
+    if (blockIdx.x == 0) chi2_reduce(p, set, scr);
+    return;
+  }
   const SetDesc sd = p.sets ? p.sets[set] : p.one;
   const int nsrc = sd.npsrc + sd.ngsrc;
   const int idx = blockIdx.x * 256 + threadIdx.x;
@@ -918,12 +930,15 @@ hipError_t launch_prep(const KParams &p, bool fp64, int max_nsrc, int rec_nc,
 
 hipError_t launch_finalize(const KParams &p, int mode, int max_nsrc, hipStream_t stream) {
   if (mode == MODE_PREDICT) return hipSuccess;
-  hipLaunchKernelGGL(finalize_chi2, dim3(p.nset), dim3(256), 0, stream, p);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || mode != MODE_GRAD) return e;
+  if (mode != MODE_GRAD) {
+    hipLaunchKernelGGL(finalize_chi2, dim3(p.nset), dim3(256), 0, stream, p);
+    return hipGetLastError();
+  }
+  // level 1 of the gradient, plus chi^2 in the extra row of chunks
   const int nblk = (max_nsrc * 10 + 255) / 256;
-  hipLaunchKernelGGL(finalize_grad1, dim3(nblk, p.grad_nchunk, p.nset), dim3(256), 0, stream, p);
-  e = hipGetLastError();
+  hipLaunchKernelGGL(finalize_grad1, dim3(nblk, p.grad_nchunk + 1, p.nset), dim3(256), 0, stream,
+                     p);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(finalize_grad2, dim3(nblk, p.nset), dim3(256), 0, stream, p);
   return hipGetLastError();

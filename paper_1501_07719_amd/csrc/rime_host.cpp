@@ -123,6 +123,10 @@ struct rime_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int32_t variant[3][2] = {{-1, -1}, {-1, -1}, {-1, -1}};  // -1: the plan's
+  // second lane of the per-set pipelines (matrix-core variants): a stream of
+  // the library's own, forked from and joined to the caller's by two events
+  hipStream_t lane = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
 };
 
 namespace {
@@ -883,6 +887,9 @@ void rime_batch_destroy(rime_batch *b) {
   if (!b) return;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->lane) (void)hipStreamDestroy(b->lane);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  if (b->join) (void)hipEventDestroy(b->join);
   (void)hipFree(b->d_sets);
   (void)hipFree(b->d_order);
   delete b;
@@ -929,12 +936,22 @@ rime_status rime_batch_create(const rime_plan *plan, int32_t nset, const rime_sk
   return RIME_OK;
 }
 
+// Per-set pipelines of the matrix-core variants run in two lanes: sets
+// 0, 2, 4, ... on the caller's stream and 1, 3, 5, ... on the batch's own, so
+// that the kernels of one set overlap those of the next (small sets leave
+// most of the chip idle).
+constexpr int kBatchLanes = 2;
+
+int batch_lanes(const rime_batch *b) { return std::min(kBatchLanes, b->nset); }
+
 // Workspace of one batched call with variant v: a matrix-core variant runs
-// the single-sky pipeline once per set (one set's layout, reused in stream
-// order); the others run all sets in one launch sequence.
+// the single-sky pipeline once per set, with one set's layout per lane (each
+// reused in stream order); the others run all sets in one launch sequence.
 size_t batch_ws(const rime_batch *b, int mode, int prec, const Variant &v) {
   if (pme_active(v, prec, 1) && mode != RIME_MODE_PREDICT)
-    return ws_layout(b->plan, mode, prec, geometry(b->plan, v, 1), 1, b->max_nsrc, v).total;
+    return batch_lanes(b) *
+           align_up(ws_layout(b->plan, mode, prec, geometry(b->plan, v, 1), 1, b->max_nsrc, v)
+                        .total);
   return ws_layout(b->plan, mode, prec, geometry(b->plan, v, b->nset), b->nset, b->total_src, v)
       .total;
 }
@@ -962,23 +979,43 @@ rime_status rime_chi2_batched(rime_batch *b, rime_precision prec, const void *da
   SetDesc dummy;
   std::memset(&dummy, 0, sizeof(dummy));
   const bool per_set = pme_active(*v, prec, 1);
+  const int lanes = per_set ? batch_lanes(b) : 1;
+  if (lanes > 1 && !b->lane) {
+    // created outside any capture; default priority
+    RIME_HIP(hipStreamCreateWithFlags(&b->lane, hipStreamNonBlocking));
+    RIME_HIP(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+    RIME_HIP(hipEventCreateWithFlags(&b->join, hipEventDisableTiming));
+  }
   auto run = [&]() {
     if (!per_set)
       return enqueue(plan, mode, prec, vidx, b->nset, b->d_sets, dummy, b->d_order,
                      b->max_nsrc, b->total_src, data, weight, nullptr, chi2, grad, ws,
                      ws_bytes, s);
-    // matrix-core variant: the single-sky pipeline per set, in stream order;
-    // the timing events (if any) bracket the whole sequence
+    // matrix-core variant: the single-sky pipeline per set, set i in lane
+    // i % lanes with that lane's part of the workspace; the timing events (if
+    // any) bracket the whole sequence on the caller's stream
+    const size_t lane_bytes = batch_ws(b, mode, prec, *v) / lanes;
     if (plan->ev_start) RIME_HIP(hipEventRecord(plan->ev_start, s));
+    if (lanes > 1) {
+      RIME_HIP(hipEventRecord(b->fork, s));
+      RIME_HIP(hipStreamWaitEvent(b->lane, b->fork, 0));
+    }
     for (int i = 0; i < b->nset; ++i) {
       SetDesc one = b->h_sets[i];
       const int64_t off = one.src_off;
       one.src_off = 0;
       const int n = one.npsrc + one.ngsrc;
+      const int l = i % lanes;
+      void *lws = static_cast<char *>(ws) + l * lane_bytes;
       const rime_status st =
           enqueue(plan, mode, prec, vidx, 1, nullptr, one, nullptr, n, n, data, weight, nullptr,
-                  chi2 + i, grad ? grad + off * 10 : nullptr, ws, ws_bytes, s, false);
+                  chi2 + i, grad ? grad + off * 10 : nullptr, lws, lane_bytes,
+                  l == 0 ? s : b->lane, false);
       if (st != RIME_OK) return st;
+    }
+    if (lanes > 1) {
+      RIME_HIP(hipEventRecord(b->join, b->lane));
+      RIME_HIP(hipStreamWaitEvent(s, b->join, 0));
     }
     if (plan->ev_stop) RIME_HIP(hipEventRecord(plan->ev_stop, s));
     return RIME_OK;

@@ -152,7 +152,11 @@ void rime_batch_destroy(rime_batch *batch);
  * chi2 DEVICE double[nset]; grad DEVICE double [sum nsrc][10], set-major in
  * the order the sets were given.  With use_graph != 0 the launch sequence is
  * captured into a hipGraph on the first call for a given (data, weight, chi2,
- * grad, ws, stream, precision) and replayed afterwards. */
+ * grad, ws, stream, precision) and replayed afterwards.  With a matrix-core
+ * variant the sets alternate between `stream` and a stream that the batch
+ * creates on first use (default priority, destroyed with the batch); it is
+ * forked from and joined back to `stream` by events, so all work of the call
+ * is ordered after earlier work on `stream` and before later work on it. */
 rime_status rime_chi2_batched(rime_batch *batch, rime_precision prec, const void *data,
                               const void *weight, double *chi2, double *grad,
                               void *ws, size_t ws_bytes, void *stream, int32_t use_graph);

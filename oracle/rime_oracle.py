@@ -65,27 +65,71 @@ def _t(x, dtype=_F64):
 def n_minus_one(l, m):
     """n - 1 with n = sqrt(1 - l^2 - m^2) (Section 2.1, after eq. k_term),
     written as -(l^2 + m^2) / (1 + n), which is the same number without the
-    cancellation of sqrt(...) - 1 near the phase centre."""
+    cancellation of sqrt(...) - 1 near the phase centre.  Directions with
+    l^2 + m^2 >= 1 lie outside the domain of n and raise ValueError."""
     r2 = l * l + m * m
+    if bool((r2.detach() >= 1.0).any()):
+        raise ValueError("source direction outside the domain l^2 + m^2 < 1")
     return -r2 / (1.0 + torch.sqrt(1.0 - r2))
 
 
+# Error-free transformations (float64 arithmetic only, no fused multiply-add):
+# they carry the phase of eq. k_term without rounding (reading R12).
+
+def _split(a):
+    """Veltkamp's split a = hi + lo, hi with at most 26 significant bits, so
+    that every product of two halves is exact in float64."""
+    c = 134217729.0 * a  # 2^27 + 1
+    hi = c - (c - a)
+    return hi, a - hi
+
+
+def _two_prod(a, b):
+    """Dekker's product: (p, e) with p = fl(a b) and p + e = a b exactly."""
+    p = a * b
+    ah, al = _split(a)
+    bh, bl = _split(b)
+    e = ((ah * bh - p) + ah * bl + al * bh) + al * bl
+    return p, e
+
+
+def _two_sum(a, b):
+    """Knuth's sum: (s, e) with s = fl(a + b) and s + e = a + b exactly."""
+    s = a + b
+    bv = s - a
+    e = (a - (s - bv)) + (b - bv)
+    return s, e
+
+
 def phase_turns(uvw, lm, freq):
-    """(u l + v m + w (n - 1)) * nu / c in turns, shape [T][A][S][F]
-    (eq. k_term with 1/lambda = nu/c)."""
+    """The phase of eq. k_term in turns, x = (u l + v m + w (n - 1)) nu / c
+    (1/lambda = nu/c), with its integer part removed (exp(-2 pi i x) has
+    period 1 in x): shape [T][A][S][F], values in [-1/2, 1/2] up to rounding.
+
+    x reaches hundreds to thousands of turns on the benchmark arrays, so the
+    path length tau and its product with nu / c are carried as float64 pairs
+    (hi + lo) through error-free sums and products; the fraction is then the
+    exact fraction of the products of the float64 inputs to about 1e-16
+    turns (reading R12)."""
     l, m = lm[:, 0], lm[:, 1]
     nm1 = n_minus_one(l, m)
-    u, v, w = uvw[..., 0], uvw[..., 1], uvw[..., 2]
-    tau = (u[..., None] * l + v[..., None] * m + w[..., None] * nm1)  # [T][A][S] metres
-    return tau[..., None] * (freq / C_LIGHT)                           # [T][A][S][F]
+    u, v, w = uvw[..., 0][..., None], uvw[..., 1][..., None], uvw[..., 2][..., None]
+    p1, e1 = _two_prod(u, l)                                          # [T][A][S]
+    p2, e2 = _two_prod(v, m)
+    p3, e3 = _two_prod(w, nm1)
+    s, es1 = _two_sum(p1, p2)
+    s, es2 = _two_sum(s, p3)
+    th, tl = _two_sum(s, (e1 + e2 + e3) + (es1 + es2))               # tau = th + tl
+    nuc = freq / C_LIGHT                                               # [F]
+    xh, xe = _two_prod(th[..., None], nuc)                             # [T][A][S][F]
+    xl = xe + tl[..., None] * nuc
+    return (xh - torch.round(xh)) + xl
 
 
 def phase_K(uvw, lm, freq):
-    """K_tps = exp(-2 pi i x), x = phase_turns (eq. k_term, sign reading '-').
-    The integer part of x is removed first (exp(-2 pi i x) has period 1 in
-    x), so the angle passed to exp stays within [-pi, pi]."""
-    x = phase_turns(uvw, lm, freq)
-    frac = x - torch.round(x)
+    """K_tps = exp(-2 pi i x), x = phase_turns (eq. k_term, sign reading '-');
+    the angle passed to exp stays within [-pi, pi]."""
+    frac = phase_turns(uvw, lm, freq)
     return torch.exp(torch.complex(torch.zeros_like(frac), -2.0 * math.pi * frac))
 
 

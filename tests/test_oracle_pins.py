@@ -217,9 +217,38 @@ def pin_brute_force():
                                rtol=1e-11, atol=1e-12)
 
 
+def pin_phase_exact_fraction():
+    """The phase fraction of eq. k_term equals the exact fraction of
+    (u l + v m + w (n - 1)) nu / c over the float64 inputs, evaluated in
+    rational arithmetic, to 1e-15 turns at phases of about a thousand turns
+    (u, v up to 8 km as on the large array, 1.76 GHz)."""
+    import torch
+    from fractions import Fraction as Fr
+    rng = np.random.default_rng(9)
+    uvw = rng.uniform(-8000.0, 8000.0, (2, 4, 3))
+    uvw[..., 2] /= 40.0
+    lm = rng.uniform(-0.03, 0.03, (5, 2))
+    freq = np.linspace(0.95e9, 1.76e9, 3)
+    r = O.phase_turns(torch.tensor(uvw), torch.tensor(lm), torch.tensor(freq)).numpy()
+    nm1 = O.n_minus_one(torch.tensor(lm[:, 0]), torch.tensor(lm[:, 1])).numpy()
+    big = 0.0
+    for t in range(2):
+        for a in range(4):
+            for s in range(5):
+                tau = (Fr(uvw[t, a, 0]) * Fr(lm[s, 0]) + Fr(uvw[t, a, 1]) * Fr(lm[s, 1])
+                       + Fr(uvw[t, a, 2]) * Fr(float(nm1[s])))
+                for f in range(3):
+                    x = tau * Fr(float(freq[f] / C))
+                    frac = x - round(x)
+                    big = max(big, abs(float(x)))
+                    assert abs(r[t, a, s, f] - float(frac)) <= 1e-15, (t, a, s, f)
+    assert big > 300.0
+
+
 PINS = [pin_phase_centre, pin_single_point_closed_form, pin_sign, pin_hermitian_swap,
         pin_zero_width_gaussian, pin_gaussian_dft, pin_gaussian_half_power,
-        pin_beam_values, pin_spectral, pin_gain_placement, pin_brute_force]
+        pin_beam_values, pin_spectral, pin_gain_placement, pin_brute_force,
+        pin_phase_exact_fraction]
 
 
 @pytest.mark.parametrize("pin", PINS, ids=[p.__name__ for p in PINS])
@@ -319,6 +348,18 @@ def _mut_sign(monkeypatch):
     monkeypatch.setattr(O, "phase_turns", lambda *a: -orig(*a))
 
 
+def _mut_plain_phase(monkeypatch):
+    # the phase as plain float64 products and sums (rounded), not error-free
+    def pt(uvw, lm, freq):
+        nm1 = O.n_minus_one(lm[:, 0], lm[:, 1])
+        tau = (uvw[..., 0][..., None] * lm[:, 0] + uvw[..., 1][..., None] * lm[:, 1]
+               + uvw[..., 2][..., None] * nm1)
+        x = tau[..., None] * (freq / O.C_LIGHT)
+        return x - torch.round(x)
+    import torch
+    monkeypatch.setattr(O, "phase_turns", pt)
+
+
 def _mut_drop_w(monkeypatch):
     def pt(uvw, lm, freq):
         u2 = uvw.clone()
@@ -383,7 +424,7 @@ def _mut_gain_conj(monkeypatch):
     monkeypatch.setattr(O, "jones_A", ja)
 
 
-MUTATIONS = [_mut_sign, _mut_drop_w, _mut_transpose_B, _mut_half_B, _mut_alpha_sign,
+MUTATIONS = [_mut_sign, _mut_plain_phase, _mut_drop_w, _mut_transpose_B, _mut_half_B, _mut_alpha_sign,
              _mut_gauss_swap, _mut_gauss_R, _mut_beam_square, _mut_beam_noclip,
              _mut_gain_conj]
 
@@ -406,3 +447,12 @@ def test_synth_config_c0_shapes():
     assert pr.sky.nsrc == 20 and pr.sky.ngsrc == 0
     assert pr.noise.shape == (10, 21, 16, 4)
     np.testing.assert_allclose(pr.obs.freq[[0, -1]], [1.36e9, 1.44e9])
+
+
+def test_domain_error():
+    """Directions with l^2 + m^2 >= 1 are outside the domain of
+    n = sqrt(1 - l^2 - m^2) (Section 2.1): the oracle refuses them."""
+    obs = tiny_obs()
+    sky = Sky(lm=np.array([[0.8, 0.6]]), stokes=np.array([[1.0, 0, 0, 0]]), alpha=np.zeros(1))
+    with pytest.raises(ValueError):
+        O.model_vis(obs, sky)

@@ -33,9 +33,19 @@ function that uses it):
 * (V - D)^2 on complex numbers is |V - D|^2, summed over the four
   correlations xx, xy, yx, yy, each with its own real weight.
 
-Gradients with respect to (l, m, I, Q, U, V, alpha, el, em, R) come from
-torch.autograd applied to the same direct sum.  ``brute_force_vis`` restates
-eq. 1 with scalar Python loops for tiny problems.
+* The direction-independent term G of eq. 1 (optional, a full 2x2 complex
+  matrix per timestep, antenna and channel) multiplies the source sum from
+  both sides: V_pq = G_p X_pq G_q^H.
+* A third morphology after points and Gaussians: the elliptical exponential
+  disk (Sersic index 1), parameterised like the Gaussian with the major-axis
+  scale length h in place of the FWHM (disk_shape).
+* Brightness may be given per timestep (Table rime_input lists an
+  ntime x nsrc brightness array); the spectral index stays per source.
+
+Gradients with respect to (l, m, I, Q, U, V, alpha, el, em, R), to G and to
+the per-timestep brightness come from torch.autograd applied to the same
+direct sum.  ``brute_force_vis`` restates eq. 1 with scalar Python loops for
+tiny problems.
 
 Inputs are the dataclasses of ``rime_synth`` (plain numpy arrays).
 """
@@ -139,7 +149,12 @@ def beam_e(lm, pointing, freq, k, ref_freq, clip):
     source from the antenna's pointing centre)."""
     dl = lm[None, None, :, 0] - pointing[..., 0][..., None]
     dm = lm[None, None, :, 1] - pointing[..., 1][..., None]
-    r = torch.sqrt(dl * dl + dm * dm)                                   # [T][A][S]
+    # r = |(dl, dm)|; at r = 0 (a source on the pointing centre) e is smooth
+    # with zero derivative, which the square root's infinite slope would turn
+    # into NaN under autograd: the derivative there is taken as its limit, 0
+    r2 = dl * dl + dm * dm
+    on = r2 > 0
+    r = torch.sqrt(torch.where(on, r2, torch.ones_like(r2))) * on       # [T][A][S]
     arg = torch.clamp(k * r[..., None] * (freq / ref_freq), max=clip)  # [T][A][S][F]
     return torch.cos(arg) ** 3
 
@@ -175,6 +190,28 @@ def gauss_shape(duvw, gshape, freq):
     a = up * el_ + vp * em_
     b = up * em_ - vp * el_
     return torch.exp(-GAUSS_K * (a * a + R_ * R_ * b * b))
+
+
+def disk_shape(duvw, xshape, freq):
+    """Shape factor of an elliptical exponential disk (a Sersic profile of
+    index 1), shape [T][B][X][F].  The sky-plane profile is
+    exp(-sqrt((x / h)^2 + (y / (R h))^2)) with scale length h (rad) along the
+    major axis x at position angle pa (from +m towards +l) and axis ratio R;
+    parameters (el, em, R) = (h sin pa, h cos pa, R) as for the Gaussian.  Its
+    normalised 2-D Fourier transform at baseline (u', v') = (u_p - u_q,
+    v_p - v_q) nu / c is
+        S = (1 + (2 pi)^2 [(u' el + v' em)^2 + R^2 (u' em - v' el)^2])^(-3/2)
+    (the circular case is the textbook transform of exp(-r/h),
+    2 pi h^2 (1 + (2 pi h k)^2)^(-3/2); the ellipse stretches k along the
+    axes).  The w component does not enter."""
+    el, em, R = xshape[:, 0], xshape[:, 1], xshape[:, 2]
+    s = freq / C_LIGHT
+    up = duvw[..., 0][..., None, None] * s            # [T][B][1][F]
+    vp = duvw[..., 1][..., None, None] * s
+    el_, em_, R_ = el[:, None], em[:, None], R[:, None]
+    a = up * el_ + vp * em_
+    b = up * em_ - vp * el_
+    return (1.0 + (2.0 * math.pi) ** 2 * (a * a + R_ * R_ * b * b)) ** -1.5
 
 
 def jones_A(obs_t, lm, freq):
@@ -213,14 +250,18 @@ def _obs_tensors(obs, t0, t1):
     return d
 
 
-def _vis_block(obs, t0, t1, lm, stokes, alpha, gshape, ngsrc, src_chunk):
-    """Model visibilities for timesteps [t0, t1): [T][B][F][2][2] complex128."""
+def _vis_block(obs, t0, t1, lm, stokes, alpha, gshape, ngsrc, src_chunk, xshape=None,
+               nxsrc=0):
+    """Source-summed coherency for timesteps [t0, t1): [T][B][F][2][2]
+    complex128.  Sources are points, then ngsrc Gaussians (gshape), then
+    nxsrc exponential disks (xshape); stokes is [S][4]."""
     freq = _t(obs.freq)
     ant1 = torch.as_tensor(np.asarray(obs.ant1, dtype=np.int64))
     ant2 = torch.as_tensor(np.asarray(obs.ant2, dtype=np.int64))
     ot = _obs_tensors(obs, t0, t1)
     nsrc = lm.shape[0]
-    npsrc = nsrc - ngsrc
+    npsrc = nsrc - ngsrc - nxsrc
+    nx0 = npsrc + ngsrc                                                  # first disk
     T, Bn, F = t1 - t0, ant1.shape[0], freq.shape[0]
     duvw = ot["uvw"][:, ant1] - ot["uvw"][:, ant2]                       # [T][B][3]
     vis = torch.zeros((T, Bn, F, 2, 2), dtype=_C128)
@@ -231,24 +272,52 @@ def _vis_block(obs, t0, t1, lm, stokes, alpha, gshape, ngsrc, src_chunk):
         Ap = A[:, ant1]                                                  # [T][B][s][F][2][2]
         Aq = A[:, ant2]
         X = Ap @ Bm[None, None] @ Aq.conj().transpose(-1, -2)            # source coherency
-        g0, g1 = max(s0, npsrc), s1
+        parts = []
+        if min(s1, npsrc) > s0:                                          # points: S = 1
+            parts.append(torch.ones((T, Bn, min(s1, npsrc) - s0, F), dtype=_F64))
+        g0, g1 = max(s0, npsrc), min(s1, nx0)
         if g1 > g0:
-            S = gauss_shape(duvw, gshape[g0 - npsrc:g1 - npsrc], freq)    # [T][B][g][F]
-            scale = torch.ones((T, Bn, s1 - s0, F), dtype=_F64)
-            scale = torch.cat([scale[:, :, :g0 - s0], S], dim=2)
-            X = X * scale[..., None, None].to(_C128)
+            parts.append(gauss_shape(duvw, gshape[g0 - npsrc:g1 - npsrc], freq))
+        x0, x1 = max(s0, nx0), s1
+        if x1 > x0:
+            parts.append(disk_shape(duvw, xshape[x0 - nx0:x1 - nx0], freq))
+        if s1 > npsrc:
+            X = X * torch.cat(parts, dim=2)[..., None, None].to(_C128)
         vis = vis + X.sum(dim=2)
     return vis
 
 
-def model_vis(obs, sky, src_chunk: int = 64):
+def apply_die(vis, G, ant1, ant2):
+    """V_tpq(nu) = G_tp(nu) X_tpq(nu) G_tq(nu)^H: the direction-independent
+    2x2 term of eq. 1, applied outside the source sum.  vis [T][B][F][2][2],
+    G [T][A][F][2][2] complex."""
+    a1 = torch.as_tensor(np.asarray(ant1, dtype=np.int64))
+    a2 = torch.as_tensor(np.asarray(ant2, dtype=np.int64))
+    Gp = G[:, a1]
+    Gq = G[:, a2]
+    return Gp @ vis @ Gq.conj().transpose(-1, -2)
+
+
+def _sky_tensors(sky):
+    xs = getattr(sky, "xshape", None)
+    return (_t(sky.lm), _t(sky.stokes), _t(sky.alpha), _t(sky.gshape),
+            _t(xs) if xs is not None else torch.zeros((0, 3), dtype=_F64))
+
+
+def model_vis(obs, sky, src_chunk: int = 64, die=None, stokes_t=None):
     """Model visibilities V_tpq(nu) as [T][B][F][4] complex128 numpy, correlations
-    ordered xx, xy, yx, yy (eq. 1 with the source coherency and its sum)."""
-    lm, stokes = _t(sky.lm), _t(sky.stokes)
-    alpha, gshape = _t(sky.alpha), _t(sky.gshape)
+    ordered xx, xy, yx, yy (eq. 1 with the source coherency and its sum).
+    die: optional [T][A][F][2][2] complex direction-independent term;
+    stokes_t: optional [T][S][4] brightness per timestep (replaces
+    sky.stokes; Table rime_input gives the brightness per timestep)."""
+    lm, stokes, alpha, gshape, xshape = _sky_tensors(sky)
+    nx = getattr(sky, "nxsrc", 0)
     out = np.empty((obs.ntime, obs.nbl, obs.nchan, 4), dtype=np.complex128)
     for t in range(obs.ntime):
-        v = _vis_block(obs, t, t + 1, lm, stokes, alpha, gshape, sky.ngsrc, src_chunk)
+        st = _t(stokes_t[t]) if stokes_t is not None else stokes
+        v = _vis_block(obs, t, t + 1, lm, st, alpha, gshape, sky.ngsrc, src_chunk, xshape, nx)
+        if die is not None:
+            v = apply_die(v, _t(die[t:t + 1], _C128), obs.ant1, obs.ant2)
         out[t] = v.reshape(obs.nbl, obs.nchan, 4).numpy()
     return out
 
@@ -273,16 +342,38 @@ def chi2_and_grad(obs, sky, data, weight, src_chunk: int = 64, t_chunk: int = 1)
     """(chi^2, grad) with grad[s] = d chi^2 / d(l, m, I, Q, U, V, alpha, el, em, R)
     for every source (shape columns zero for point sources), by autograd of the
     direct sum, accumulated over time chunks (chi^2 is additive over time)."""
-    lm = _t(sky.lm).requires_grad_(True)
-    stokes = _t(sky.stokes).requires_grad_(True)
-    alpha = _t(sky.alpha).requires_grad_(True)
-    gshape = _t(sky.gshape).requires_grad_(True)
+    r = chi2_and_grad_ext(obs, sky, data, weight, src_chunk=src_chunk, t_chunk=t_chunk)
+    return r["chi2"], r["grad"]
+
+
+def chi2_and_grad_ext(obs, sky, data, weight, die=None, stokes_t=None, src_chunk: int = 64,
+                      t_chunk: int = 1):
+    """chi^2 and its gradients by autograd of the direct sum, with the optional
+    direction-independent term `die` [T][A][F][2][2] complex and brightness
+    per timestep `stokes_t` [T][S][4].  Returns a dict:
+      chi2;
+      grad [S][10]: d chi^2 / d(l, m, I, Q, U, V, alpha, shape) (with stokes_t,
+        the Stokes columns are d chi^2 / d(a common offset of all timesteps),
+        i.e. the sum over t of grad_stokes_t);
+      grad_die [T][A][F][2][2] complex: d chi^2 / d Re G + i d chi^2 / d Im G;
+      grad_stokes_t [T][S][4]."""
+    lm, stokes, alpha, gshape, xshape = _sky_tensors(sky)
+    for x in (lm, stokes, alpha, gshape, xshape):
+        x.requires_grad_(True)
+    nx = getattr(sky, "nxsrc", 0)
+    G = _t(die, _C128).requires_grad_(True) if die is not None else None
+    St = _t(stokes_t).requires_grad_(True) if stokes_t is not None else None
+    if St is not None:
+        t_chunk = 1
     D = np.asarray(data)
     W = np.asarray(weight, dtype=np.float64)
     total = 0.0
     for t0 in range(0, obs.ntime, t_chunk):
         t1 = min(obs.ntime, t0 + t_chunk)
-        v = _vis_block(obs, t0, t1, lm, stokes, alpha, gshape, sky.ngsrc, src_chunk)
+        st = St[t0] if St is not None else stokes
+        v = _vis_block(obs, t0, t1, lm, st, alpha, gshape, sky.ngsrc, src_chunk, xshape, nx)
+        if G is not None:
+            v = apply_die(v, G[t0:t1], obs.ant1, obs.ant2)
         v = v.reshape(t1 - t0, obs.nbl, obs.nchan, 4)
         r = v - torch.as_tensor(D[t0:t1], dtype=_C128)
         c = (torch.as_tensor(W[t0:t1]) * (r.real ** 2 + r.imag ** 2)).sum()
@@ -290,11 +381,21 @@ def chi2_and_grad(obs, sky, data, weight, src_chunk: int = 64, t_chunk: int = 1)
         total += float(c.detach())
     g = np.zeros((sky.nsrc, 10))
     g[:, 0:2] = lm.grad.numpy()
-    g[:, 2:6] = stokes.grad.numpy()
     g[:, 6] = alpha.grad.numpy()
+    npsrc = sky.nsrc - sky.ngsrc - nx
     if sky.ngsrc:
-        g[sky.npsrc:, 7:10] = gshape.grad.numpy()
-    return total, g
+        g[npsrc:npsrc + sky.ngsrc, 7:10] = gshape.grad.numpy()
+    if nx:
+        g[npsrc + sky.ngsrc:, 7:10] = xshape.grad.numpy()
+    out = {"chi2": total, "grad": g}
+    if St is not None:
+        out["grad_stokes_t"] = St.grad.numpy()
+        g[:, 2:6] = St.grad.numpy().sum(axis=0)
+    else:
+        g[:, 2:6] = stokes.grad.numpy()
+    if G is not None:
+        out["grad_die"] = G.grad.numpy()
+    return out
 
 
 # --------------------------------------------------------------------------- #

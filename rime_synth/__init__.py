@@ -16,9 +16,12 @@ Array conventions (all float64 / complex128 numpy arrays):
 * ``lm``       [nsrc][2]        direction cosines; point sources first
 * ``stokes``   [nsrc][4]        I, Q, U, V in Jy at the reference frequency
 * ``alpha``    [nsrc]           spectral index
-* ``gshape``   [ngsrc][3]       Gaussian (el, em, R) for the trailing ngsrc
-                                sources: el = theta_maj sin(pa),
+* ``gshape``   [ngsrc][3]       Gaussian (el, em, R) for the ngsrc sources after
+                                the points: el = theta_maj sin(pa),
                                 em = theta_maj cos(pa), R = theta_min/theta_maj
+* ``xshape``   [nxsrc][3]       exponential-disk (el, em, R) for the trailing
+                                nxsrc sources: el = h sin(pa), em = h cos(pa),
+                                h the major-axis scale length, R the axis ratio
 * data / weight [ntime][nbl][nchan][4] with correlations (xx, xy, yx, yy)
 """
 from __future__ import annotations
@@ -107,6 +110,7 @@ class Sky:
     stokes: np.ndarray
     alpha: np.ndarray
     gshape: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))
+    xshape: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))
 
     @property
     def nsrc(self) -> int:
@@ -117,8 +121,12 @@ class Sky:
         return int(self.gshape.shape[0])
 
     @property
+    def nxsrc(self) -> int:
+        return int(self.xshape.shape[0])
+
+    @property
     def npsrc(self) -> int:
-        return self.nsrc - self.ngsrc
+        return self.nsrc - self.ngsrc - self.nxsrc
 
     def params(self) -> np.ndarray:
         """[nsrc][10] parameter table (l, m, I, Q, U, V, alpha, el, em, R)."""
@@ -126,23 +134,31 @@ class Sky:
         out[:, 0:2] = self.lm
         out[:, 2:6] = self.stokes
         out[:, 6] = self.alpha
+        n0 = self.npsrc
         if self.ngsrc:
-            out[self.npsrc:, 7:10] = self.gshape
+            out[n0:n0 + self.ngsrc, 7:10] = self.gshape
+        if self.nxsrc:
+            out[n0 + self.ngsrc:, 7:10] = self.xshape
         return out
 
     @staticmethod
-    def from_params(p: np.ndarray, ngsrc: int) -> "Sky":
+    def from_params(p: np.ndarray, ngsrc: int, nxsrc: int = 0) -> "Sky":
         p = np.asarray(p, dtype=np.float64)
         nsrc = p.shape[0]
+        n0 = nsrc - ngsrc - nxsrc
         return Sky(lm=p[:, 0:2].copy(), stokes=p[:, 2:6].copy(), alpha=p[:, 6].copy(),
-                   gshape=p[nsrc - ngsrc:, 7:10].copy() if ngsrc else np.zeros((0, 3)))
+                   gshape=p[n0:n0 + ngsrc, 7:10].copy() if ngsrc else np.zeros((0, 3)),
+                   xshape=p[n0 + ngsrc:, 7:10].copy() if nxsrc else np.zeros((0, 3)))
 
-    def subset(self, np_keep: int, ng_keep: int) -> "Sky":
-        """The first np_keep point sources and first ng_keep Gaussian sources."""
-        npnt = self.npsrc
-        idx = np.concatenate([np.arange(np_keep), npnt + np.arange(ng_keep)]).astype(np.int64)
+    def subset(self, np_keep: int, ng_keep: int, nx_keep: int = 0) -> "Sky":
+        """The first np_keep point sources, first ng_keep Gaussian sources and
+        first nx_keep exponential disks."""
+        npnt, ng = self.npsrc, self.ngsrc
+        idx = np.concatenate([np.arange(np_keep), npnt + np.arange(ng_keep),
+                              npnt + ng + np.arange(nx_keep)]).astype(np.int64)
         return Sky(lm=self.lm[idx].copy(), stokes=self.stokes[idx].copy(),
-                   alpha=self.alpha[idx].copy(), gshape=self.gshape[:ng_keep].copy())
+                   alpha=self.alpha[idx].copy(), gshape=self.gshape[:ng_keep].copy(),
+                   xshape=self.xshape[:nx_keep].copy())
 
 
 def canonical_baselines(na: int) -> tuple[np.ndarray, np.ndarray]:
@@ -196,7 +212,7 @@ def perturb(sky: Sky, rng: np.random.Generator, frac: float = PERTURB_FRAC) -> S
     """Every scalar parameter multiplied by (1 + frac * N(0, 1))."""
     p = sky.params()
     p = p * (1.0 + frac * rng.standard_normal(p.shape))
-    return Sky.from_params(p, sky.ngsrc)
+    return Sky.from_params(p, sky.ngsrc, sky.nxsrc)
 
 
 def make_observation(cfg: dict, rng_uvw: np.random.Generator,

@@ -456,3 +456,241 @@ def test_domain_error():
     sky = Sky(lm=np.array([[0.8, 0.6]]), stokes=np.array([[1.0, 0, 0, 0]]), alpha=np.zeros(1))
     with pytest.raises(ValueError):
         O.model_vis(obs, sky)
+
+
+# --------------------------------------------------------------------------- #
+# The pointing centre, the direction-independent term G, exponential disks and
+# brightness per timestep
+# --------------------------------------------------------------------------- #
+
+def _fd(f, x0, h):
+    return (f(x0 + h) - f(x0 - h)) / (2 * h)
+
+
+def test_beam_gradient_at_pointing_centre():
+    """A source exactly on the pointing centres (r = 0): e = cos^3(k r nu/nu_b)
+    is smooth there, so the gradient with respect to l and m is finite and
+    equals central differences (the beam part of it is 0)."""
+    obs = tiny_obs(na=4, nchan=3, beam=True, seed=5)
+    obs.pointing = np.zeros_like(obs.pointing)
+    sky = Sky(lm=np.zeros((1, 2)), stokes=np.array([[2.0, 0.3, -0.2, 0.1]]),
+              alpha=np.array([-0.5]))
+    rng = np.random.default_rng(6)
+    D = O.model_vis(obs, sky) + 0.05 * (rng.standard_normal((2, 6, 3, 4))
+                                        + 1j * rng.standard_normal((2, 6, 3, 4)))
+    W = np.full(D.shape, 1e2)
+    c, g = O.chi2_and_grad(obs, sky, D, W)
+    assert np.all(np.isfinite(g))
+    for k in (0, 1):
+        def f(x):
+            p = sky.params()
+            p[0, k] = x
+            return O.chi2(obs, Sky.from_params(p, 0), D, W)
+        fd = _fd(f, 0.0, 1e-8)
+        assert abs(fd - g[0, k]) <= 1e-6 * max(abs(g[0, k]), 1.0), (k, fd, g[0, k])
+
+
+def _rand_die(rng, T, A, F):
+    g = (1 + 0.1 * rng.standard_normal((T, A, F, 2, 2))) * np.exp(
+        1j * rng.normal(0, 0.3, (T, A, F, 2, 2)))
+    g[..., 0, 1] *= 0.1
+    g[..., 1, 0] *= 0.1
+    return g
+
+
+def test_die_identity_and_closed_form():
+    """G = 1 reproduces the model; for one source at the phase centre with no
+    beam and unit gains the coherency is B, so V_pq = G_p B G_q^H (eq. 1),
+    written out with numpy; the p <-> q swap gives the Hermitian transpose."""
+    obs = tiny_obs(na=4, nchan=3, seed=7)
+    sky = rand_sky(3, 1, seed=8)
+    eye = np.broadcast_to(np.eye(2, dtype=complex), (2, 4, 3, 2, 2)).copy()
+    np.testing.assert_array_equal(O.model_vis(obs, sky, die=eye), O.model_vis(obs, sky))
+    rng = np.random.default_rng(9)
+    G = _rand_die(rng, 2, 4, 3)
+    I, Q, U, V, a = 1.7, 0.2, -0.3, 0.05, -0.6
+    one = Sky(lm=np.zeros((1, 2)), stokes=np.array([[I, Q, U, V]]), alpha=np.array([a]))
+    vis = O.model_vis(obs, one, die=G)
+    f = (obs.freq / obs.ref_freq) ** a
+    B = np.zeros((3, 2, 2), dtype=complex)
+    B[:, 0, 0], B[:, 0, 1], B[:, 1, 0], B[:, 1, 1] = f * (I + Q), f * (U + 1j * V), \
+        f * (U - 1j * V), f * (I - Q)
+    for t in range(2):
+        for b, (p, q) in enumerate(zip(obs.ant1, obs.ant2)):
+            for c in range(3):
+                exp = G[t, p, c] @ B[c] @ G[t, q, c].conj().T
+                np.testing.assert_allclose(vis[t, b, c], exp.reshape(4), rtol=1e-13, atol=1e-13)
+    sw = Observation(**{**obs.__dict__, "ant1": obs.ant2, "ant2": obs.ant1})
+    vs = O.model_vis(sw, sky, die=G).reshape(2, 6, 3, 2, 2)
+    vv = O.model_vis(obs, sky, die=G).reshape(2, 6, 3, 2, 2)
+    np.testing.assert_allclose(vs, vv.conj().swapaxes(-1, -2), rtol=1e-13, atol=1e-13)
+
+
+def test_die_gradient_matches_central_fd():
+    """d chi^2 / d Re G + i d chi^2 / d Im G from autograd against central
+    differences of chi^2 in the real and imaginary part of single entries."""
+    obs = tiny_obs(na=3, nchan=2, beam=True, gains=True, seed=10)
+    obs.pointing = np.random.default_rng(1).normal(0, 1e-3, (2, 3, 2))
+    sky = rand_sky(2, 1, seed=11)
+    rng = np.random.default_rng(12)
+    G = _rand_die(rng, 2, 3, 2)
+    D = O.model_vis(obs, sky, die=_rand_die(rng, 2, 3, 2))
+    W = np.full(D.shape, 3.0)
+    r = O.chi2_and_grad_ext(obs, sky, D, W, die=G)
+    gd = r["grad_die"]
+    assert abs(r["chi2"] - O.chi2_from_vis(O.model_vis(obs, sky, die=G), D, W)) <= 1e-12 * r["chi2"]
+    for idx in [(0, 0, 0, 0, 0), (1, 2, 1, 0, 1), (0, 1, 1, 1, 0), (1, 0, 0, 1, 1)]:
+        for part, unit in ((np.real, 1.0), (np.imag, 1j)):
+            def f(x):
+                G2 = G.copy()
+                G2[idx] += unit * x
+                return O.chi2_from_vis(O.model_vis(obs, sky, die=G2), D, W)
+            fd = _fd(f, 0.0, 1e-6)
+            assert abs(fd - part(gd[idx])) <= 1e-6 * max(abs(gd[idx]), 1.0), (idx, fd, gd[idx])
+
+
+def _disk_dft(u, v, h, R, pa, n=3200, extent=40.0):
+    """Normalised 2-D transform of exp(-sqrt((x/h)^2 + (y/(R h))^2)) with x the
+    major axis at position angle pa (from +m towards +l), by a direct sum on a
+    grid of the principal axes (spacing h extent 2 / n and R times that)."""
+    x = (np.arange(n) - (n - 1) / 2) * (2 * extent * h / n)
+    y = x * R
+    prof = np.exp(-np.sqrt((x[:, None] / h) ** 2 + (y[None, :] / (R * h)) ** 2))
+    kx = u * math.sin(pa) + v * math.cos(pa)       # along the major axis
+    ky = u * math.cos(pa) - v * math.sin(pa)       # along the minor axis
+    ex = np.exp(-2j * math.pi * kx * x)
+    ey = np.exp(-2j * math.pi * ky * y)
+    return (ex @ prof @ ey) / prof.sum()
+
+
+def test_disk_shape_is_the_profile_transform():
+    """The exponential-disk shape factor equals a direct 2-D transform of the
+    sky-plane profile (reading of the Sersic index-1 morphology)."""
+    import torch
+    h, R, pa = 1.0, 0.55, 0.7
+    for (u, v) in [(0.0, 0.0), (0.05, 0.02), (0.1, -0.2), (-0.25, 0.15), (0.4, 0.3)]:
+        ref = _disk_dft(u, v, h, R, pa)
+        xs = torch.tensor([[h * math.sin(pa), h * math.cos(pa), R]], dtype=torch.float64)
+        # duvw in metres with nu / c = 1
+        duvw = torch.tensor([[[u, v, 0.0]]], dtype=torch.float64)
+        got = O.disk_shape(duvw, xs, torch.tensor([O.C_LIGHT], dtype=torch.float64))
+        assert abs(float(got.reshape(-1)[0]) - ref.real) <= 2e-6, (u, v, float(got), ref)
+        assert abs(ref.imag) <= 1e-9
+
+
+def test_disk_limits_and_gradient():
+    """A zero-size disk is a point source; the shape gradient matches central
+    differences."""
+    obs = tiny_obs(na=4, nchan=3, beam=True, gains=True, seed=13)
+    obs.pointing = np.random.default_rng(2).normal(0, 1e-3, (2, 4, 2))
+    base = rand_sky(3, 0, seed=14)
+    xs = np.array([[2e-5, -1e-5, 0.6]])
+    disk = Sky(lm=base.lm, stokes=base.stokes, alpha=base.alpha, xshape=np.zeros((1, 3)))
+    np.testing.assert_allclose(O.model_vis(obs, disk), O.model_vis(obs, base), rtol=0, atol=1e-14)
+    disk = Sky(lm=base.lm, stokes=base.stokes, alpha=base.alpha, xshape=xs)
+    assert disk.nxsrc == 1 and disk.npsrc == 2
+    D = O.model_vis(obs, Sky.from_params(disk.params() * 1.01, 0, 1))
+    W = np.full(D.shape, 5.0)
+    c, g = O.chi2_and_grad(obs, disk, D, W)
+    for k in (7, 8, 9):
+        def f(x):
+            p = disk.params()
+            p[2, k] = x
+            return O.chi2(obs, Sky.from_params(p, 0, 1), D, W)
+        x0 = disk.params()[2, k]
+        fd = _fd(f, x0, 1e-6 * abs(x0))
+        assert abs(fd - g[2, k]) <= 1e-6 * max(abs(g[2, k]), 1e-3 * np.abs(g).max()), (k, fd, g[2, k])
+
+
+def test_brightness_per_timestep():
+    """Brightness per timestep (Table rime_input's ntime x nsrc array): a
+    constant one reproduces the static model and gradient; timestep t depends
+    only on stokes_t[t]; its gradient matches central differences."""
+    obs = tiny_obs(na=4, nchan=3, beam=True, gains=True, seed=15)
+    obs.pointing = np.random.default_rng(3).normal(0, 1e-3, (2, 4, 2))
+    sky = rand_sky(2, 1, seed=16)
+    st_c = np.broadcast_to(sky.stokes, (2,) + sky.stokes.shape).copy()
+    np.testing.assert_array_equal(O.model_vis(obs, sky, stokes_t=st_c), O.model_vis(obs, sky))
+    rng = np.random.default_rng(17)
+    st = sky.stokes[None] * (1 + 0.1 * rng.standard_normal((2, 3, 4)))
+    vis = O.model_vis(obs, sky, stokes_t=st)
+    for t in range(2):
+        s_t = Sky(lm=sky.lm, stokes=st[t], alpha=sky.alpha, gshape=sky.gshape)
+        np.testing.assert_array_equal(vis[t], O.model_vis(obs.time_slice(t, t + 1), s_t)[0])
+    D = O.model_vis(obs, sky) + 0.01 * rng.standard_normal(vis.shape)
+    W = np.full(D.shape, 1e2)
+    r = O.chi2_and_grad_ext(obs, sky, D, W, stokes_t=st)
+    c0, g0 = O.chi2_and_grad(obs, sky, D, W)
+    r0 = O.chi2_and_grad_ext(obs, sky, D, W, stokes_t=st_c)
+    np.testing.assert_allclose(r0["grad"], g0, rtol=1e-12, atol=1e-12 * np.abs(g0).max())
+    gs = r["grad_stokes_t"]
+    for idx in [(0, 0, 0), (1, 2, 1), (0, 1, 3), (1, 0, 2)]:
+        def f(x):
+            s2 = st.copy()
+            s2[idx] = x
+            return O.chi2_from_vis(O.model_vis(obs, sky, stokes_t=s2), D, W)
+        fd = _fd(f, st[idx], 1e-6 * abs(st[idx]))
+        assert abs(fd - gs[idx]) <= 1e-6 * max(abs(gs[idx]), 1e-3 * np.abs(gs).max()), (idx, fd)
+
+
+# planted mistakes in the extensions: each must fail one of their pins
+EXT_PINS = [test_beam_gradient_at_pointing_centre, test_die_identity_and_closed_form,
+            test_die_gradient_matches_central_fd, test_disk_shape_is_the_profile_transform,
+            test_disk_limits_and_gradient, test_brightness_per_timestep]
+
+
+def _mut_die_no_conj(monkeypatch):
+    def ad(vis, G, ant1, ant2):
+        a1 = np.asarray(ant1, dtype=np.int64)
+        a2 = np.asarray(ant2, dtype=np.int64)
+        return G[:, a1] @ vis @ G[:, a2].transpose(-1, -2)
+    monkeypatch.setattr(O, "apply_die", ad)
+
+
+def _mut_die_order(monkeypatch):
+    def ad(vis, G, ant1, ant2):
+        a1 = np.asarray(ant1, dtype=np.int64)
+        a2 = np.asarray(ant2, dtype=np.int64)
+        return G[:, a2] @ vis @ G[:, a1].conj().transpose(-1, -2)
+    monkeypatch.setattr(O, "apply_die", ad)
+
+
+def _mut_disk_exponent(monkeypatch):
+    orig = O.disk_shape
+    monkeypatch.setattr(O, "disk_shape", lambda *a: orig(*a) ** (2.0 / 3.0))
+
+
+def _mut_disk_axes(monkeypatch):
+    orig = O.disk_shape
+
+    def ds(duvw, xs, freq):
+        x2 = xs.clone()
+        x2[:, 2] = 1.0
+        return orig(duvw, x2, freq)
+    monkeypatch.setattr(O, "disk_shape", ds)
+
+
+def _mut_beam_nan_centre(monkeypatch):
+    def be(lm, pointing, freq, k, ref, clip):
+        import torch
+        dl = lm[None, None, :, 0] - pointing[..., 0][..., None]
+        dm = lm[None, None, :, 1] - pointing[..., 1][..., None]
+        r = torch.sqrt(dl * dl + dm * dm)
+        return torch.cos(torch.clamp(k * r[..., None] * (freq / ref), max=clip)) ** 3
+    monkeypatch.setattr(O, "beam_e", be)
+
+
+EXT_MUTATIONS = [_mut_die_no_conj, _mut_die_order, _mut_disk_exponent, _mut_disk_axes,
+                 _mut_beam_nan_centre]
+
+
+@pytest.mark.parametrize("mut", EXT_MUTATIONS, ids=[m.__name__ for m in EXT_MUTATIONS])
+def test_planted_mistakes_extensions(mut, monkeypatch):
+    mut(monkeypatch)
+    failed = []
+    for pin in EXT_PINS:
+        try:
+            pin()
+        except AssertionError:
+            failed.append(pin.__name__)
+    assert failed, f"no pin caught mutation {mut.__name__}"

@@ -75,7 +75,7 @@ def parse():
     ap.add_argument("--variant", type=int, default=None,
                     help="pin the float32-mixed kernel variant (library index) instead of "
                          "autotuning it")
-    ap.add_argument("--modes", default="grad_mixed,grad_fp64,chi2_mixed,chi2_fp64",
+    ap.add_argument("--modes", default="grad_mixed,grad_res64,grad_fp64,chi2_mixed,chi2_fp64",
                     help="comma list of timed evaluations (the first must be grad_mixed)")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="MiB copied device-to-device once before timing (a kernel of known "
@@ -358,7 +358,7 @@ def bench_single(args):
         wsp = R.workspace(plan, mode, prec, 1, sky.nsrc)
         if prec == R.MIXED and args.variant is not None:
             plan.set_variant(mode, prec, args.variant)
-        elif not args.no_autotune and (prec == R.MIXED or tune_fp64):
+        elif not args.no_autotune and (prec != R.FP64 or tune_fp64):
             # untimed: the library's autotuner picks the kernel variant
             R.rime_autotune(plan, dsky, mode, prec, D, W, wsp)
         variant = R.rime_variant_info(mode, prec, plan.get_variant(mode, prec))
@@ -386,7 +386,8 @@ def bench_single(args):
     spec = {"grad_mixed": (R.MODE_CHI2_GRAD, R.MIXED, args.steps, args.warmup),
             "grad_fp64": (R.MODE_CHI2_GRAD, R.FP64, fp_steps, 1),
             "chi2_mixed": (R.MODE_CHI2, R.MIXED, args.steps, 1),
-            "chi2_fp64": (R.MODE_CHI2, R.FP64, fp_steps, 1)}
+            "chi2_fp64": (R.MODE_CHI2, R.FP64, fp_steps, 1),
+            "grad_res64": (R.MODE_CHI2_GRAD, R.MIXED_RES64, args.steps, 1)}
     for m in modes:
         log("timing", m)
         out[m] = run(*spec[m])
@@ -412,6 +413,15 @@ def bench_single(args):
                        "evals_per_s": out["grad_fp64"]["evals_per_s"],
                        "variant": out["grad_fp64"]["variant"]}
         rec["speedup_mixed_vs_fp64"] = out["grad_fp64"]["ms_per_step"] / g["ms_per_step"]
+    if "grad_res64" in out:
+        r64 = out["grad_res64"]
+        rec["res64"] = {"terms_per_s": r64["terms_per_s"], "ms_per_step": r64["ms_per_step"],
+                        "step_ms": r64["step_ms"], "evals_per_s": r64["evals_per_s"],
+                        "variant": r64["variant"], "matrix_cores": r64["matrix_cores"],
+                        "main_ms": r64["main_ms"], "kernel_ms": r64["kernel_ms"]}
+        if "grad_fp64" in out:
+            rec["res64"]["speedup_vs_fp64"] = (out["grad_fp64"]["ms_per_step"] /
+                                               r64["ms_per_step"])
     if "chi2_mixed" in out and "chi2_fp64" in out:
         rec["chi2_only"] = {
             "mixed_terms_per_s": out["chi2_mixed"]["terms_per_s"],

@@ -14,7 +14,9 @@
  *   e_tps     = cos^3(min(beam_k * |(l,m) - pointing_tp| * nu / beam_ref_freq, beam_clip))
  *   G_p       = diag(g_p0, g_p1)          (constant diagonal complex gain)
  *   S_tpqs    = exp(-(pi^2 / (4 ln 2)) [(u' el + v' em)^2 + R^2 (u' em - v' el)^2])
- *               for Gaussian sources (u' = (u_p - u_q) nu / c), 1 for point sources
+ *               for Gaussian sources (u' = (u_p - u_q) nu / c),
+ *               (1 + (2 pi)^2 [(u' el + v' em)^2 + R^2 (u' em - v' el)^2])^(-3/2)
+ *               for exponential disks, 1 for point sources
  *   chi^2     = sum_{t, baseline, nu, corr} w |V - D|^2
  *
  * Conventions shared by every entry point:
@@ -30,13 +32,27 @@
  *    this boundary.
  *  - Precision RIME_FP64: data/weight/vis are complex128/float64 and all
  *    arithmetic is float64.  RIME_MIXED: data/weight/vis are
- *    complex64/float32; the phase argument and the chi-squared (and gradient)
- *    sums are float64, everything else float32.  Sky parameters are float64
- *    in both.
- *  - Sources with l^2 + m^2 >= 1 are outside the domain of the equation;
- *    they are not checked (sky parameters live on the device) and turn the
- *    result into NaN.
- *  - Calls are re-entrant when given distinct workspaces.
+ *    complex64/float32; the phase argument (formed error-free and reduced to
+ *    [-1/2, 1/2] turns) and the chi-squared and gradient sums across
+ *    workgroups are float64; the per-term work is float32, except that the
+ *    matrix-core variants (rime_variant_matrix_cores) form the point-source
+ *    products from fp16 hi + lo operand pairs (hi*hi + hi*lo + lo*hi, about
+ *    22 significant bits) with float32 accumulation.
+ *    RIME_MIXED_RES64 (chi-squared and gradient only): data/weight as for
+ *    RIME_MIXED; the forward pass (model, residual, chi-squared) is float64
+ *    throughout and the adjoint is the float32 one of RIME_MIXED, fed with
+ *    the float64 residual.  Its gradient keeps the float32 relative accuracy
+ *    when the model fits the data to the noise level, where the float32
+ *    model error would otherwise dominate the residual.
+ *    Sky parameters are float64 in every precision.
+ *  - Sources with l^2 + m^2 >= 1 lie outside the domain of
+ *    n = sqrt(1 - l^2 - m^2) (Section 2.1, after eq. k_term).  The sky lives
+ *    on the device, so a call does not reject them on the host: their
+ *    geometry becomes NaN, which propagates to every output of the call, and
+ *    the call records the fact in its workspace; rime_domain_status reports
+ *    it (RIME_ERR_DOMAIN) once the call has completed.
+ *  - Calls are re-entrant when given distinct workspaces; one batch must not
+ *    be used from two host threads at once.
  */
 #ifndef RIME_H
 #define RIME_H
@@ -54,12 +70,14 @@ typedef enum rime_status {
   RIME_ERR_WORKSPACE = 2,    /* ws_bytes smaller than rime_workspace_size()    */
   RIME_ERR_HIP = 3,          /* a HIP runtime call failed (see rime_last_hip_error) */
   RIME_ERR_UNSUPPORTED = 4,  /* no kernel variant for this request             */
-  RIME_ERR_NOMEM = 5         /* device allocation inside a create call failed  */
+  RIME_ERR_NOMEM = 5,        /* device allocation inside a create call failed  */
+  RIME_ERR_DOMAIN = 6        /* a source has l^2 + m^2 >= 1 (rime_domain_status) */
 } rime_status;
 
 typedef enum rime_precision {
   RIME_FP64 = 0,
-  RIME_MIXED = 1
+  RIME_MIXED = 1,
+  RIME_MIXED_RES64 = 2       /* float64 forward and residual, float32 adjoint */
 } rime_precision;
 
 typedef enum rime_mode {
@@ -92,19 +110,26 @@ typedef struct rime_obs_desc {
   double beam_clip;          /* 1.0881 rad                                        */
 } rime_obs_desc;
 
-/* One sky model (one sampler proposal).  Point sources first, then Gaussians.
- * All arrays are DEVICE float64 arrays. */
+/* One sky model (one sampler proposal).  Point sources first, then
+ * Gaussians, then exponential disks.  All arrays are DEVICE float64 arrays. */
 typedef struct rime_sky {
   int32_t npsrc;             /* point sources, >= 0                               */
-  int32_t ngsrc;             /* Gaussian sources, >= 0; npsrc + ngsrc >= 1        */
-  const double *lm;          /* device [nsrc][2] direction cosines, rad; l^2 + m^2  */
-                             /* < 1 is not checked (device data): n - 1 becomes   */
-                             /* NaN and propagates to every output                */
+  int32_t ngsrc;             /* Gaussian sources, >= 0                            */
+  const double *lm;          /* device [nsrc][2] direction cosines, rad, with      */
+                             /* l^2 + m^2 < 1 (see rime_domain_status)            */
   const double *stokes;      /* device [nsrc][4] I, Q, U, V in Jy at ref_freq     */
   const double *alpha;       /* device [nsrc] spectral index                      */
   const double *gshape;      /* device [ngsrc][3] (el, em, R): el = theta_maj sin(pa), */
                              /* em = theta_maj cos(pa), R = theta_min / theta_maj; */
                              /* FWHM in rad; may be NULL when ngsrc == 0          */
+  int32_t nxsrc;             /* exponential disks (Sersic index 1), >= 0;         */
+                             /* npsrc + ngsrc + nxsrc >= 1                        */
+  const double *xshape;      /* device [nxsrc][3] (el, em, R) = (h sin(pa),       */
+                             /* h cos(pa), minor/major) with h the scale length   */
+                             /* (rad) of exp(-r/h) along the major axis; the shape */
+                             /* factor is (1 + (2 pi)^2 [(u' el + v' em)^2 +      */
+                             /* R^2 (u' em - v' el)^2])^(-3/2); may be NULL when  */
+                             /* nxsrc == 0                                        */
 } rime_sky;
 
 typedef struct rime_plan rime_plan;    /* observation resident on one device */
@@ -122,7 +147,8 @@ size_t rime_workspace_size(const rime_plan *plan, rime_mode mode, rime_precision
                            int32_t nset, int64_t total_src);
 
 /* Model visibilities, eq. 1: vis is DEVICE [ntime][nbl][nchan][4] complex
- * (complex128 for RIME_FP64, complex64 for RIME_MIXED). */
+ * (complex128 for RIME_FP64, complex64 for RIME_MIXED; RIME_MIXED_RES64
+ * returns RIME_ERR_UNSUPPORTED). */
 rime_status rime_predict(const rime_plan *plan, const rime_sky *sky, rime_precision prec,
                          void *vis, void *ws, size_t ws_bytes, void *stream);
 
@@ -134,11 +160,52 @@ rime_status rime_chi2(const rime_plan *plan, const rime_sky *sky, rime_precision
                       void *ws, size_t ws_bytes, void *stream);
 
 /* chi^2 and its gradient: grad is DEVICE double [nsrc][10] with columns
- * d chi^2 / d(l, m, I, Q, U, V, alpha, el, em, R); the shape columns of point
- * sources are 0.  The model visibilities are never written to memory. */
+ * d chi^2 / d(l, m, I, Q, U, V, alpha, el, em, R) (the shape columns are the
+ * Gaussian's or the disk's, and 0 for point sources).  The model
+ * visibilities are never written to memory. */
 rime_status rime_chi2_grad(const rime_plan *plan, const rime_sky *sky, rime_precision prec,
                            const void *data, const void *weight, double *chi2, double *grad,
                            void *ws, size_t ws_bytes, void *stream);
+
+/* Out-of-core chi^2 (grad == NULL) or chi^2 and gradient, streaming the
+ * observed data through the device in time chunks: the paper's subdivision
+ * of a problem too large for device memory along time (Section 4 "Scaling the
+ * RIME", Fig. async_overlap), with the upload of each chunk overlapping the
+ * computation of the previous one.
+ *  data_host   HOST [ntime][nbl][nchan][4] complex (complex128 for RIME_FP64,
+ *              complex64 otherwise), weight_host HOST [ntime][nbl][nchan][4]
+ *              real, read during the call's execution on the device: they
+ *              must stay valid and unchanged until `stream` has completed the
+ *              call's work.  Page-locked host memory (hipHostMalloc) lets the
+ *              uploads run asynchronously; pageable memory gives the same
+ *              results without the overlap.
+ *  chunk_t     timesteps per chunk (>= 1; clamped to ntime).  Two staging
+ *              buffers of chunk_t timesteps live in the workspace, filled on
+ *              a stream of the plan's own and consumed on `stream`.
+ *  chi2, grad  DEVICE outputs as for rime_chi2_grad: chi^2 is additive over
+ *              time, so each chunk's chi^2 and gradient land in the workspace
+ *              and one final launch sums them in chunk order (compensated).
+ *  ws          DEVICE, rime_streamed_workspace_size bytes.
+ * The kernel variant is the plan's for (mode, prec).  Streamed calls on one
+ * plan must not be issued from two host threads at once (they share the
+ * plan's upload stream and events).  Asynchronous on `stream`. */
+size_t rime_streamed_workspace_size(const rime_plan *plan, rime_mode mode, rime_precision prec,
+                                    int64_t nsrc, int32_t chunk_t);
+rime_status rime_chi2_streamed(const rime_plan *plan, const rime_sky *sky, rime_precision prec,
+                               const void *data_host, const void *weight_host, double *chi2,
+                               double *grad, int32_t chunk_t, void *ws, size_t ws_bytes,
+                               void *stream);
+
+/* Domain check of the last call that used workspace `ws` (Section 2.1: n =
+ * sqrt(1 - l^2 - m^2) needs l^2 + m^2 < 1).  Synchronises `stream` (the
+ * call's stream), then reads the flags the call wrote at the start of its
+ * workspace: RIME_ERR_DOMAIN when a source of any set was outside the domain
+ * (that call's outputs are NaN), RIME_OK when none was, RIME_ERR_ARG when
+ * `ws` holds no flags (never used by a compute call, or too small),
+ * RIME_ERR_HIP on a HIP failure.  Covers rime_predict, rime_chi2,
+ * rime_chi2_grad, rime_chi2_streamed and rime_chi2_batched (every set of the
+ * batch). */
+rime_status rime_domain_status(const void *ws, size_t ws_bytes, void *stream);
 
 /* Batched proposals over one observation.  `skies` is a HOST array of nset
  * sky descriptions whose device pointers and source counts are fixed for the
@@ -153,10 +220,11 @@ void rime_batch_destroy(rime_batch *batch);
  * the order the sets were given.  With use_graph != 0 the launch sequence is
  * captured into a hipGraph on the first call for a given (data, weight, chi2,
  * grad, ws, stream, precision) and replayed afterwards.  With a matrix-core
- * variant the sets alternate between `stream` and a stream that the batch
- * creates on first use (default priority, destroyed with the batch); it is
+ * variant the sets alternate between `stream` and a stream that
+ * rime_batch_create makes (default priority, destroyed with the batch); it is
  * forked from and joined back to `stream` by events, so all work of the call
- * is ordered after earlier work on `stream` and before later work on it. */
+ * is ordered after earlier work on `stream` and before later work on it,
+ * also when the call fails part-way. */
 rime_status rime_chi2_batched(rime_batch *batch, rime_precision prec, const void *data,
                               const void *weight, double *chi2, double *grad,
                               void *ws, size_t ws_bytes, void *stream, int32_t use_graph);
@@ -203,7 +271,12 @@ rime_status rime_variant_info(rime_mode mode, rime_precision prec, int32_t index
  * float32 accumulation within 32 sources, float64 across), 0 when every
  * source goes through the per-baseline kernel, -1 for an invalid index.
  * A batched call with such a variant runs the single-sky pipeline once per
- * set in stream order (workspace: one set's, from rime_batch_workspace_size). */
+ * set, alternating between two streams (workspace: one set's per stream, as
+ * rime_batch_workspace_size counts it; rime_workspace_size with the batch's
+ * nset and total source count is never smaller).  For RIME_MIXED_RES64 the
+ * chi-squared variants are the float64 forwards and the gradient variants
+ * the float32 adjoints (the forward of a gradient call is the plan's
+ * RIME_MODE_CHI2 variant of that precision). */
 int32_t rime_variant_matrix_cores(rime_mode mode, rime_precision prec, int32_t index);
 rime_status rime_set_variant(rime_plan *plan, rime_mode mode, rime_precision prec,
                              int32_t index);

@@ -1,8 +1,7 @@
 // Device-side numeric helpers shared by the kernels of librime.so: the
 // precision traits of the two arithmetic paths (float64, and float32 with the
-// gfx950 hardware transcendentals), definition-order products for the phase
-// argument, and float64 compensated (two-sum) accumulation with wavefront and
-// workgroup reductions.
+// gfx950 hardware transcendentals), the error-free phase argument, and float64
+// compensated (two-sum) accumulation with wavefront and workgroup reductions.
 #pragma once
 
 #include "rime_internal.h"
@@ -57,8 +56,10 @@ __device__ inline SetDesc load_set(const KParams &p, int set) {
   d.stokes = q->stokes;
   d.alpha = q->alpha;
   d.gshape = q->gshape;
+  d.xshape = q->xshape;
   d.npsrc = q->npsrc;
   d.ngsrc = q->ngsrc;
+  d.nxsrc = q->nxsrc;
   d.src_off = q->src_off;
   return d;
 }
@@ -72,8 +73,6 @@ template <> struct Num<double> {
   __device__ static inline void sincos_turns(double r, double *s, double *c) {
     sincospi(2.0 * r, s, c);
   }
-  // sin and cos of x radians, |x| <= 1.1.
-  __device__ static inline void sincos_rad(double x, double *s, double *c) { sincos(x, s, c); }
   // expb(y) = exp(y / kExpScale): the exponential in the base whose argument
   // scale is kExpScale (e here, 2 in the float version).
   static constexpr double kExpScale = 1.0;
@@ -85,55 +84,103 @@ template <> struct Num<double> {
   __device__ static inline double from_bits(uint32_t b) {
     return __longlong_as_double(static_cast<long long>(b));
   }
-  __device__ static inline double sqrt_(double x) { return sqrt(x); }
   __device__ static inline double rcp(double x) { return 1.0 / x; }
+  __device__ static inline double rsqrt_(double x) { return rsqrt(x); }
 };
 
 template <> struct Num<float> {
   using R2 = float2;
   using R4 = float4;
-  // v_sin_f32 / v_cos_f32 take the angle in turns.
+  // sin and cos of 2 pi r for r in [-1/2, 1/2] turns, to about one float32
+  // unit: the quarter-turn reduction r = q/4 + x is exact in float64, the
+  // angle 2 pi x (|2 pi x| <= pi/4) is rounded once to float32, and the Taylor
+  // series of sin to degree 9 and of cos to degree 10 leave truncation errors
+  // below 2e-9 there; the quadrant then permutes and negates the pair.  (The
+  // hardware v_sin_f32 / v_cos_f32 are several float32 units less accurate,
+  // which shows in sums that cancel.)
   __device__ static inline void sincos_turns(double r, float *s, float *c) {
-    const float rf = static_cast<float>(r);
-    *s = __builtin_amdgcn_sinf(rf);
-    *c = __builtin_amdgcn_cosf(rf);
-  }
-  __device__ static inline void sincos_rad(float x, float *s, float *c) {
-    const float t = x * static_cast<float>(kInvTwoPi);
-    *s = __builtin_amdgcn_sinf(t);
-    *c = __builtin_amdgcn_cosf(t);
+    const double q = rint(4.0 * r);
+    const float th = static_cast<float>((r - 0.25 * q) * (2.0 * 3.14159265358979323846));
+    const float t2 = th * th;
+    const float sn =
+        th * (1.0f + t2 * (-1.0f / 6.0f +
+                           t2 * (1.0f / 120.0f + t2 * (-1.0f / 5040.0f + t2 * (1.0f / 362880.0f)))));
+    const float cs =
+        1.0f + t2 * (-0.5f + t2 * (1.0f / 24.0f +
+                                   t2 * (-1.0f / 720.0f +
+                                         t2 * (1.0f / 40320.0f + t2 * (-1.0f / 3628800.0f)))));
+    // sin and cos of th + iq pi/2
+    const int iq = static_cast<int>(q) & 3;
+    const float ss = (iq & 1) ? cs : sn, cc = (iq & 1) ? sn : cs;
+    *s = (iq & 2) ? -ss : ss;
+    *c = ((iq + 1) & 2) ? -cc : cc;
   }
   static constexpr double kExpScale = kLog2e;
   __device__ static inline float expb(float y) { return __builtin_amdgcn_exp2f(y); }
   __device__ static inline uint32_t bits(float w) { return __float_as_uint(w); }
   __device__ static inline float from_bits(uint32_t b) { return __uint_as_float(b); }
-  __device__ static inline float sqrt_(double x) {
-    return __builtin_amdgcn_sqrtf(static_cast<float>(x));
-  }
   __device__ static inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+  __device__ static inline float rsqrt_(float x) { return __builtin_amdgcn_rsqf(x); }
 };
 
-// (a0 b0 + a1 b1) + a2 b2 with every product and sum rounded separately (no
-// fused multiply-add), i.e. in the order in which the definitions are written.
-// The phase argument is hundreds of turns, so the rounding of this sum is
-// visible in the phase; evaluating it in definition order keeps the FP64 path
-// rounding-compatible with a plain evaluation of the same formula.
-__device__ inline double dot3_rn(double a0, double b0, double a1, double b1, double a2,
-                                 double b2) {
-#pragma clang fp contract(off)
-  return (a0 * b0 + a1 * b1) + a2 * b2;
-}
+// Error-free transformations for the phase argument of eq. k_term.  The path
+// length tau = u l + v m + w (n - 1) times nu / c spans hundreds to thousands of
+// turns on the benchmark arrays; carried as an unevaluated float64 pair
+// (hi + lo) through exact products and sums, its fraction of a turn is the
+// exact fraction of the products of the float64 inputs to about 1e-16 turns,
+// whatever the rounding order of a plain evaluation would have been.
+// Every function here turns contraction off: fusing a product into a
+// following sum (hipcc contracts by default) would round differently from
+// the product that the error term is taken against, and break the identity.
 
-__device__ inline double sumsq_rn(double a, double b) {
-#pragma clang fp contract(off)
-  return a * a + b * b;
-}
-
-// Error-free sum: s + e == a + b exactly.
+// Error-free sum (Knuth): s + e == a + b exactly.
 __device__ inline void two_sum(double a, double b, double &s, double &e) {
+#pragma clang fp contract(off)
   s = a + b;
   const double bp = s - a;
   e = (a - (s - bp)) + (b - bp);
+}
+
+// Error-free product with one fused multiply-add: p + e == a b exactly.
+__device__ inline void two_prod(double a, double b, double &p, double &e) {
+#pragma clang fp contract(off)
+  p = a * b;
+  e = fma(a, b, -p);
+}
+
+struct Pair {
+  double hi, lo;
+};
+
+// tau = u l + v m + w (n - 1) (metres) as hi + lo.
+__device__ inline Pair path_length(double u, double v, double w, double l, double m,
+                                   double nm1) {
+#pragma clang fp contract(off)
+  double p1, e1, p2, e2, p3, e3, s, es1, es2;
+  two_prod(u, l, p1, e1);
+  two_prod(v, m, p2, e2);
+  two_prod(w, nm1, p3, e3);
+  two_sum(p1, p2, s, es1);
+  two_sum(s, p3, s, es2);
+  Pair t;
+  two_sum(s, (e1 + e2 + e3) + (es1 + es2), t.hi, t.lo);
+  return t;
+}
+
+// tau nu / c in turns minus its nearest integer (ties to even), in
+// [-1/2, 1/2] up to rounding: exp(-2 pi i x) has period 1 in x.
+__device__ inline double phase_frac(Pair tau, double nuc) {
+#pragma clang fp contract(off)
+  double xh, xe;
+  two_prod(tau.hi, nuc, xh, xe);
+  const double xl = xe + tau.lo * nuc;
+  return (xh - rint(xh)) + xl;
+}
+
+// a^2 + b^2 with each product rounded on its own (l^2 + m^2 as written).
+__device__ inline double sumsq_rn(double a, double b) {
+#pragma clang fp contract(off)
+  return a * a + b * b;
 }
 
 // Compensated float64 accumulator.

@@ -18,7 +18,8 @@
 namespace rime {
 hipError_t launch_prep(const KParams &p, bool fp64, int max_nsrc, int rec_nc,
                        hipStream_t stream);
-hipError_t launch_finalize(const KParams &p, int mode, int max_nsrc, hipStream_t stream);
+hipError_t launch_finalize(const KParams &p, int mode, int max_nsrc, hipStream_t stream,
+                           bool with_chi2);
 hipError_t launch_pme(const KParams &p, hipStream_t stream);
 hipError_t launch_pme_adjoint(const KParams &p, bool phase, hipStream_t stream);
 hipError_t launch_pme_finalize(const KParams &p, hipStream_t stream);
@@ -27,6 +28,10 @@ int variant_count(int mode, int prec);
 const Variant *variant_info(int mode, int prec, int index);
 hipError_t launch_variant(int mode, int prec, int index, const KParams &p, int nitems,
                           hipStream_t stream);
+hipError_t launch_resid(int index, const KParams &p, int nitems, hipStream_t stream);
+hipError_t launch_sum_chunks(const double *part, int nchunk, int64_t stride, int64_t n,
+                             double *chi2, double *grad, hipStream_t stream);
+hipError_t launch_adj(int index, const KParams &p, int nitems, hipStream_t stream);
 }  // namespace rime
 
 using namespace rime;
@@ -90,10 +95,14 @@ struct rime_plan {
   int32_t ngroup = 0;
   int32_t *d_groups = nullptr;  // [ngroup][5] forward work groups
   bool pme_adj_ok = false;  // every antenna-pair slot holds at most one baseline
-  int32_t variant[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+  int32_t variant[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // [mode][precision]
   std::string signature;  // observation part of the autotune key
   hipEvent_t ev_start = nullptr, ev_stop = nullptr;        // around all compute kernels
   hipEvent_t ev_main0 = nullptr, ev_main1 = nullptr;       // around the per-baseline kernel
+  // streamed calls: the upload stream, its fork event and, per staging
+  // buffer, "uploaded" and "consumed" events (made with the plan)
+  hipStream_t copy = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_up[2] = {nullptr, nullptr}, ev_done[2] = {nullptr, nullptr};
 };
 
 struct GraphKey {
@@ -122,7 +131,7 @@ struct rime_batch {
   GraphKey key{};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  int32_t variant[3][2] = {{-1, -1}, {-1, -1}, {-1, -1}};  // -1: the plan's
+  int32_t variant[3][3] = {{-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}};  // -1: the plan's
   // second lane of the per-set pipelines (matrix-core variants): a stream of
   // the library's own, forked from and joined to the caller's by two events
   hipStream_t lane = nullptr;
@@ -286,6 +295,7 @@ Geometry geometry(const rime_plan *plan, const Variant &v, int nset) {
 }
 
 struct WsLayout {
+  size_t dom = 0;
   size_t geo = 0, lon = 0, st = 0, gs = 0, rec = 0, chi2 = 0, grad = 0, grad2 = 0;
   size_t ph_hi = 0, ph_lo = 0, ph_k3 = 0, spts = 0, pexp = 0, rho_t = 0, pgrad = 0;
   size_t src_f = 0, mfrag = 0, mscale = 0, rho_g = 0, pfin = 0;
@@ -299,6 +309,8 @@ struct WsLayout {
 // the adjoint.
 constexpr size_t kPmePlaneBytes = size_t(48) << 30;
 
+constexpr int kRes64 = RIME_MIXED_RES64;
+
 int pme_ncg(const rime_plan *plan) { return (plan->nchan + kPmeNCW - 1) / kPmeNCW; }
 // bytes of one phase plane of one timestep (all channels)
 int64_t plane_bytes_t(const rime_plan *plan, int64_t npsrc) {
@@ -306,16 +318,27 @@ int64_t plane_bytes_t(const rime_plan *plan, int64_t npsrc) {
 }
 int pme_nqr(const rime_plan *plan) { return (plan->nblk + kPmeNQ - 1) / kPmeNQ; }
 
-// Whether a call runs the point sources on the matrix cores.
+// Whether a call runs point sources on the matrix cores (single sky, one of
+// the mixed precisions).
 bool pme_active(const Variant &v, int prec, int nset) {
-  return v.pme && prec == RIME_MIXED && nset == 1;
+  return v.pme && prec != RIME_FP64 && nset == 1;
 }
 
+// Words of the domain-flag header at the start of every workspace: a count,
+// then one flag per (set, preparation workgroup of 256 sources).
+int64_t dom_words(int nset, int64_t total_src) {
+  return 1 + static_cast<int64_t>(nset) * ((total_src + 255) / 256);
+}
+
+// fwd_sums = false: the point-source sums of the matrix-core forward are not
+// needed (the adjoint half of the float64-residual mode).
 WsLayout ws_layout(const rime_plan *plan, int mode, int prec, const Geometry &g, int nset,
-                   int64_t total_src, const Variant &v) {
+                   int64_t total_src, const Variant &v, bool fwd_sums = true) {
   WsLayout L;
   const size_t r4 = prec == RIME_FP64 ? 32 : 16;
   size_t off = 0;
+  L.dom = off;
+  off += align_up(static_cast<size_t>(dom_words(nset, total_src)) * sizeof(int32_t));
   L.geo = off;
   off += align_up(static_cast<size_t>(total_src) * sizeof(double4));
   L.lon = off;
@@ -357,11 +380,13 @@ WsLayout ws_layout(const rime_plan *plan, int mode, int prec, const Geometry &g,
     off += align_up(plane_t * L.pme_tchunk);
     L.ph_lo = off;
     off += align_up(plane_t * L.pme_tchunk);
-    L.spts = off;
-    off += align_up(static_cast<size_t>(plan->ntime) * plan->nchan * plan->npair * 4 *
-                    kPmeBlk * kPmeBlk * sizeof(double2));
-    L.pexp = off;
-    off += align_up(static_cast<size_t>(plan->nchan) * 4 * sizeof(int32_t));
+    if (fwd_sums) {
+      L.spts = off;
+      off += align_up(static_cast<size_t>(plan->ntime) * plan->nchan * plan->npair * 4 *
+                      kPmeBlk * kPmeBlk * sizeof(double2));
+      L.pexp = off;
+      off += align_up(static_cast<size_t>(plan->nchan) * 4 * sizeof(int32_t));
+    }
     if (adj) {
       L.pme_adj = true;
       if (k3) {
@@ -392,29 +417,112 @@ WsLayout ws_layout(const rime_plan *plan, int mode, int prec, const Geometry &g,
   return L;
 }
 
+// The float64-residual mode composes two layouts: the float64 forward's
+// (with the domain header at offset 0) and, in gradient mode, the float32
+// adjoint's, followed by the per-visibility residual of every set.
+struct Res64Layout {
+  WsLayout f, a;
+  Variant va{};            // the adjoint variant as run (matrix cores only when usable)
+  size_t a_off = 0, rho_b = 0, total = 0;
+};
+
+Res64Layout res64_layout(const rime_plan *plan, int mode, const Variant &vf,
+                         const Variant *va, int nset, int64_t total_src) {
+  Res64Layout R;
+  R.f = ws_layout(plan, RIME_MODE_CHI2, RIME_FP64, geometry(plan, vf, nset), nset, total_src,
+                  vf);
+  size_t off = R.f.total;
+  if (mode == RIME_MODE_CHI2_GRAD && va) {
+    R.va = *va;
+    // the point-source adjoint on the matrix cores needs single-baseline slots
+    if (!plan->pme_adj_ok) R.va.pme = 0;
+    R.a_off = off;
+    R.a = ws_layout(plan, RIME_MODE_CHI2_GRAD, RIME_MIXED, geometry(plan, R.va, nset), nset,
+                    total_src, R.va, false);
+    off += R.a.total;
+    R.rho_b = off;
+    off += align_up(static_cast<size_t>(nset) * plan->ntime * plan->nbl * plan->nchan * 4 *
+                    sizeof(float2));
+  }
+  R.total = off;
+  return R;
+}
+
+// Workspace of one call of (mode, prec) with kernel variant `vidx` and, for a
+// gradient in the float64-residual mode, forward variant `fidx`.
+size_t call_ws(const rime_plan *plan, int mode, int prec, int vidx, int fidx, int nset,
+               int64_t total_src) {
+  const Variant *v = variant_info(mode, prec, vidx);
+  if (!v) return 0;
+  if (prec != kRes64)
+    return ws_layout(plan, mode, prec, geometry(plan, *v, nset), nset, total_src, *v).total;
+  if (mode == RIME_MODE_CHI2) return res64_layout(plan, mode, *v, nullptr, nset, total_src).total;
+  const Variant *vf = variant_info(RIME_MODE_CHI2, kRes64, fidx);
+  if (!vf) return 0;
+  return res64_layout(plan, mode, *vf, v, nset, total_src).total;
+}
+
+// Whether a batched call with this variant runs the single-sky pipeline once
+// per set (the matrix-core engine works on one sky at a time).
+bool per_set_variant(const rime_plan *plan, int mode, int prec, const Variant &v) {
+  if (mode == RIME_MODE_PREDICT || !pme_active(v, prec, 1)) return false;
+  return prec == RIME_MIXED || (mode == RIME_MODE_CHI2_GRAD && plan->pme_adj_ok);
+}
+
+// Per-set pipelines of the matrix-core variants run in two lanes: sets
+// 0, 2, 4, ... on the caller's stream and 1, 3, 5, ... on the batch's own, so
+// that the kernels of one set overlap those of the next (small sets leave
+// most of the chip idle).
+constexpr int kBatchLanes = 2;
+
 size_t ws_max(const rime_plan *plan, int mode, int prec, int nset, int64_t total_src) {
   size_t best = 0;
+  const int nf = prec == kRes64 && mode == RIME_MODE_CHI2_GRAD
+                     ? variant_count(RIME_MODE_CHI2, kRes64)
+                     : 1;
   for (int i = 0; i < variant_count(mode, prec); ++i) {
     const Variant *v = variant_info(mode, prec, i);
-    best = std::max(best,
-                    ws_layout(plan, mode, prec, geometry(plan, *v, nset), nset, total_src, *v).total);
-    // a batched call with a matrix-core variant runs one set at a time; no
-    // set has more than total_src sources
-    if (nset > 1 && pme_active(*v, prec, 1) && mode != RIME_MODE_PREDICT)
-      best = std::max(best,
-                      ws_layout(plan, mode, prec, geometry(plan, *v, 1), 1, total_src, *v).total);
+    for (int f = 0; f < nf; ++f) {
+      best = std::max(best, call_ws(plan, mode, prec, i, f, nset, total_src));
+      // a batched call with a matrix-core variant runs one set at a time in
+      // up to kBatchLanes lanes after a header of domain flags; no set has
+      // more than total_src sources
+      if (nset > 1 && per_set_variant(plan, mode, prec, *v))
+        best = std::max(best, align_up(static_cast<size_t>(dom_words(nset, total_src)) *
+                                       sizeof(int32_t)) +
+                                  std::min(kBatchLanes, nset) *
+                                      align_up(call_ws(plan, mode, prec, i, f, 1, total_src)));
+    }
   }
   return best;
 }
 
+int64_t sky_nsrc(const rime_sky *sky) {
+  return static_cast<int64_t>(sky->npsrc) + sky->ngsrc + sky->nxsrc;
+}
+
 rime_status check_sky(const rime_sky *sky) {
   if (!sky) return RIME_ERR_ARG;
-  if (sky->npsrc < 0 || sky->ngsrc < 0) return RIME_ERR_ARG;
-  if (static_cast<int64_t>(sky->npsrc) + sky->ngsrc < 1) return RIME_ERR_ARG;
-  if (static_cast<int64_t>(sky->npsrc) + sky->ngsrc > (1 << 24)) return RIME_ERR_ARG;
+  if (sky->npsrc < 0 || sky->ngsrc < 0 || sky->nxsrc < 0) return RIME_ERR_ARG;
+  if (sky_nsrc(sky) < 1 || sky_nsrc(sky) > (1 << 24)) return RIME_ERR_ARG;
   if (!sky->lm || !sky->stokes || !sky->alpha) return RIME_ERR_ARG;
   if (sky->ngsrc > 0 && !sky->gshape) return RIME_ERR_ARG;
+  if (sky->nxsrc > 0 && !sky->xshape) return RIME_ERR_ARG;
   return RIME_OK;
+}
+
+SetDesc set_of(const rime_sky *sky) {
+  SetDesc d;
+  d.lm = sky->lm;
+  d.stokes = sky->stokes;
+  d.alpha = sky->alpha;
+  d.gshape = sky->gshape;
+  d.xshape = sky->xshape;
+  d.npsrc = sky->npsrc;
+  d.ngsrc = sky->ngsrc;
+  d.nxsrc = sky->nxsrc;
+  d.src_off = 0;
+  return d;
 }
 
 KParams base_params(const rime_plan *plan) {
@@ -437,20 +545,29 @@ KParams base_params(const rime_plan *plan) {
   return p;
 }
 
-// Enqueue prep + main + finalize for `nset` sets.
-rime_status enqueue(const rime_plan *plan, int mode, int prec, int vidx, int nset,
-                    const SetDesc *d_sets, const SetDesc &one, const int32_t *d_order,
-                    int max_nsrc, int64_t total_src, const void *data, const void *weight,
-                    void *vis, double *chi2, double *grad, void *ws, size_t ws_bytes,
-                    hipStream_t stream, bool events = true) {
-  const Variant *v = variant_info(mode, prec, vidx);
-  if (!v) return RIME_ERR_UNSUPPORTED;
-  const Geometry g = geometry(plan, *v, nset);
-  const WsLayout L = ws_layout(plan, mode, prec, g, nset, total_src, *v);
-  if (L.total > 0 && (!ws || ws_bytes < L.total)) return RIME_ERR_WORKSPACE;
-  const int64_t nitems = static_cast<int64_t>(nset) * g.items_per_set;
-  if (nitems <= 0 || nitems > 0x7fffffff) return RIME_ERR_UNSUPPORTED;
-  const TileSet &ts = plan->tiles[nbt_slot(v->threads)];
+// One compute call: the sets, the data and the outputs.
+struct Call {
+  int mode = 0, prec = 0, nset = 1;
+  const SetDesc *d_sets = nullptr;  // device [nset] (batched) or nullptr
+  SetDesc one{};                    // the single set when d_sets == nullptr
+  const int32_t *d_order = nullptr;
+  int max_nsrc = 0;
+  int64_t total_src = 0;
+  const void *data = nullptr, *weight = nullptr;
+  void *vis = nullptr;
+  double *chi2 = nullptr, *grad = nullptr;
+  // domain flags: nullptr for the header of the call's own workspace, else a
+  // batch-level header (per-set pipelines) with this call's first flag word
+  // and the batch's total word count
+  int32_t *dom = nullptr;
+  int32_t dom_off = 0, dom_count = 0;
+};
+
+// Kernel parameters of one launch geometry over workspace region `w` laid out
+// by L (matrix-core fields set when L enables the engine).
+KParams make_params(const rime_plan *plan, const Call &c, const Variant &v, const Geometry &g,
+                    const WsLayout &L, char *w) {
+  const TileSet &ts = plan->tiles[nbt_slot(v.threads)];
   KParams p = base_params(plan);
   p.nbt = ts.nbt;
   p.nat = ts.nat;
@@ -463,31 +580,39 @@ rime_status enqueue(const rime_plan *plan, int mode, int prec, int vidx, int nse
   p.tchunk = g.tchunk;
   p.ntc = g.ntc;
   p.items_per_set = g.items_per_set;
-  p.nset = nset;
-  p.sets = d_sets;
-  p.one = one;
-  p.order = d_order;
-  char *w = static_cast<char *>(ws);
+  p.nset = c.nset;
+  p.sets = c.d_sets;
+  p.one = c.one;
+  p.order = c.d_order;
   p.src_geo = reinterpret_cast<double4 *>(w + L.geo);
   p.src_lon = reinterpret_cast<double2 *>(w + L.lon);
   p.src_st = w + L.st;
   p.src_gs = w + L.gs;
-  if (mode == RIME_MODE_CHI2_GRAD) p.bl_rec = w + L.rec;
-  p.total_src = total_src;
-  p.data = data;
-  p.weight = weight;
-  p.vis = vis;
+  if (c.mode == RIME_MODE_CHI2_GRAD) p.bl_rec = w + L.rec;
+  p.total_src = c.total_src;
+  if (c.dom) {
+    p.dom = c.dom;
+    p.dom_off = c.dom_off;
+    p.dom_count = c.dom_count;
+  } else {
+    p.dom = reinterpret_cast<int32_t *>(w + L.dom);
+    p.dom_off = 0;
+    p.dom_count = c.nset * ((c.max_nsrc + 255) / 256);
+  }
+  p.data = c.data;
+  p.weight = c.weight;
+  p.vis = c.vis;
   p.chi2_part = reinterpret_cast<double2 *>(w + L.chi2);
   p.grad_part = reinterpret_cast<double *>(w + L.grad);
   p.rho_g = w + L.rho_g;
   p.grad_part2 = reinterpret_cast<double *>(w + L.grad2);
   p.grad_chunks = kGradChunk;
   p.grad_nchunk = g.grad_nchunk;
-  p.chi2_out = chi2;
-  p.grad_out = grad;
+  p.chi2_out = c.chi2;
+  p.grad_out = c.grad;
   p.pme = 0;
   p.pme_adj = 0;
-  if (L.pme_tchunk > 0 && one.npsrc > 0) {
+  if (L.pme_tchunk > 0 && c.one.npsrc > 0) {
     p.pme = 1;
     p.nap = plan->nap;
     p.npair = plan->npair;
@@ -508,7 +633,7 @@ rime_status enqueue(const rime_plan *plan, int mode, int prec, int vidx, int nse
       p.pgrad = reinterpret_cast<float *>(w + L.pgrad);
       p.pme_ncg = pme_ncg(plan);
       p.pme_nqr = pme_nqr(plan);
-      p.pme_nsr = (one.npsrc + kPmeSR - 1) / kPmeSR;
+      p.pme_nsr = (c.one.npsrc + kPmeSR - 1) / kPmeSR;
       p.pfin = reinterpret_cast<double2 *>(w + L.pfin);
       p.pme_fchunk = pme_fin_nchunk(
           p.pme_nsr, static_cast<int64_t>(plan->ntime) * p.pme_ncg * plan->nblk * p.pme_nqr);
@@ -517,7 +642,99 @@ rime_status enqueue(const rime_plan *plan, int mode, int prec, int vidx, int nse
       p.mscale = reinterpret_cast<float *>(w + L.mscale);
     }
   }
-  RIME_HIP(launch_prep(p, prec == RIME_FP64, max_nsrc,
+  return p;
+}
+
+// The point-source adjoint on the matrix cores, in passes over time that
+// each rebuild their phase planes unless `reuse` (one pass whose planes the
+// forward left in place).
+rime_status enqueue_pme_adjoint(const rime_plan *plan, KParams p, const WsLayout &L, char *w,
+                                bool reuse, hipStream_t stream) {
+  if (L.ph_k3) p.ph_k3 = reinterpret_cast<float *>(w + L.ph_k3);
+  for (int t0 = 0; t0 < plan->ntime; t0 += L.pme_tchunk) {
+    p.pme_t0 = t0;
+    p.pme_nt = std::min(L.pme_tchunk, plan->ntime - t0);
+    RIME_HIP(launch_pme_adjoint(p, !reuse, stream));
+  }
+  return RIME_OK;
+}
+
+// Enqueue one call of the float64-residual mode: float64 forward (chi^2 and,
+// for the gradient, the residual), then the float32 adjoint (per-baseline
+// kernel, plus the matrix-core engine for point sources).
+rime_status enqueue_res64(const rime_plan *plan, const Call &c, int vidx, void *ws,
+                          size_t ws_bytes, hipStream_t stream, bool events) {
+  const bool grad = c.mode == RIME_MODE_CHI2_GRAD;
+  const int fidx = grad ? plan->variant[RIME_MODE_CHI2][kRes64] : vidx;
+  const Variant *vf = variant_info(RIME_MODE_CHI2, kRes64, fidx);
+  const Variant *va = grad ? variant_info(RIME_MODE_CHI2_GRAD, kRes64, vidx) : nullptr;
+  if (!vf || (grad && !va)) return RIME_ERR_UNSUPPORTED;
+  const Res64Layout R = res64_layout(plan, c.mode, *vf, va, c.nset, c.total_src);
+  if (!ws || ws_bytes < R.total) return RIME_ERR_WORKSPACE;
+  const Geometry gf = geometry(plan, *vf, c.nset);
+  const Geometry ga = grad ? geometry(plan, R.va, c.nset) : Geometry{};
+  const int64_t nf = static_cast<int64_t>(c.nset) * gf.items_per_set;
+  const int64_t na = static_cast<int64_t>(c.nset) * ga.items_per_set;
+  if (nf <= 0 || nf > 0x7fffffff || (grad && (na <= 0 || na > 0x7fffffff)))
+    return RIME_ERR_UNSUPPORTED;
+  char *w = static_cast<char *>(ws);
+  Call cf = c;
+  cf.mode = RIME_MODE_CHI2;
+  KParams pf = make_params(plan, cf, *vf, gf, R.f, w);
+  KParams pa{};
+  if (grad) {
+    Call ca = c;
+    ca.dom = nullptr;
+    pa = make_params(plan, ca, R.va, ga, R.a, w + R.a_off);
+    pa.dom = nullptr;  // the forward's preparation records the domain
+    pa.pme = 0;        // no forward on the matrix cores
+    pa.rho_b = reinterpret_cast<float2 *>(w + R.rho_b);
+    pf.rho_b = pa.rho_b;
+    if (pa.pme_adj) {
+      // the forward also stores the residual in the antenna-pair slots
+      pf.pme_adj = 1;
+      pf.rho_t = pa.rho_t;
+      pf.bl_slot = plan->d_bl_slot;
+      pf.npair = plan->npair;
+    }
+  }
+  RIME_HIP(launch_prep(pf, true, c.max_nsrc, 0, stream));
+  if (grad) RIME_HIP(launch_prep(pa, false, c.max_nsrc, R.va.nc, stream));
+  if (events && plan->ev_start) RIME_HIP(hipEventRecord(plan->ev_start, stream));
+  if (events && plan->ev_main0) RIME_HIP(hipEventRecord(plan->ev_main0, stream));
+  RIME_HIP(launch_resid(fidx, pf, static_cast<int>(nf), stream));
+  if (events && plan->ev_main1) RIME_HIP(hipEventRecord(plan->ev_main1, stream));
+  if (grad) {
+    if (pa.pme_adj) {
+      const rime_status st = enqueue_pme_adjoint(plan, pa, R.a, w + R.a_off, false, stream);
+      if (st != RIME_OK) return st;
+    }
+    RIME_HIP(launch_adj(vidx, pa, static_cast<int>(na), stream));
+  }
+  if (events && plan->ev_stop) RIME_HIP(hipEventRecord(plan->ev_stop, stream));
+  RIME_HIP(launch_finalize(pf, RIME_MODE_CHI2, c.max_nsrc, stream, true));
+  if (grad) {
+    RIME_HIP(launch_finalize(pa, RIME_MODE_CHI2_GRAD, c.max_nsrc, stream, false));
+    if (pa.pme_adj) RIME_HIP(launch_pme_finalize(pa, stream));
+  }
+  return RIME_OK;
+}
+
+// Enqueue prep + main + finalize for the sets of `c`.
+rime_status enqueue(const rime_plan *plan, const Call &c, int vidx, void *ws, size_t ws_bytes,
+                    hipStream_t stream, bool events = true) {
+  if (c.prec == kRes64) return enqueue_res64(plan, c, vidx, ws, ws_bytes, stream, events);
+  const int mode = c.mode, prec = c.prec;
+  const Variant *v = variant_info(mode, prec, vidx);
+  if (!v) return RIME_ERR_UNSUPPORTED;
+  const Geometry g = geometry(plan, *v, c.nset);
+  const WsLayout L = ws_layout(plan, mode, prec, g, c.nset, c.total_src, *v);
+  if (L.total > 0 && (!ws || ws_bytes < L.total)) return RIME_ERR_WORKSPACE;
+  const int64_t nitems = static_cast<int64_t>(c.nset) * g.items_per_set;
+  if (nitems <= 0 || nitems > 0x7fffffff) return RIME_ERR_UNSUPPORTED;
+  char *w = static_cast<char *>(ws);
+  KParams p = make_params(plan, c, *v, g, L, w);
+  RIME_HIP(launch_prep(p, prec == RIME_FP64, c.max_nsrc,
                        mode == RIME_MODE_CHI2_GRAD ? v->nc : 0, stream));
   if (events && plan->ev_start) RIME_HIP(hipEventRecord(plan->ev_start, stream));
   if (p.pme) {
@@ -538,44 +755,96 @@ rime_status enqueue(const rime_plan *plan, int mode, int prec, int vidx, int nse
   RIME_HIP(launch_variant(mode, prec, vidx, p, static_cast<int>(nitems), stream));
   if (events && plan->ev_main1) RIME_HIP(hipEventRecord(plan->ev_main1, stream));
   if (p.pme_adj) {
-    if (L.ph_k3) p.ph_k3 = reinterpret_cast<float *>(w + L.ph_k3);
-    for (int t0 = 0; t0 < plan->ntime; t0 += L.pme_tchunk) {
-      p.pme_t0 = t0;
-      p.pme_nt = std::min(L.pme_tchunk, plan->ntime - t0);
-      RIME_HIP(launch_pme_adjoint(p, L.pme_tchunk < plan->ntime, stream));
-    }
+    const rime_status st =
+        enqueue_pme_adjoint(plan, p, L, w, L.pme_tchunk >= plan->ntime, stream);
+    if (st != RIME_OK) return st;
   }
   if (events && plan->ev_stop) RIME_HIP(hipEventRecord(plan->ev_stop, stream));
-  RIME_HIP(launch_finalize(p, mode, max_nsrc, stream));
+  RIME_HIP(launch_finalize(p, mode, c.max_nsrc, stream, true));
   if (p.pme_adj) RIME_HIP(launch_pme_finalize(p, stream));
   return RIME_OK;
 }
+
+bool valid_prec(int prec) { return prec == RIME_FP64 || prec == RIME_MIXED || prec == kRes64; }
 
 rime_status single(const rime_plan *plan, int mode, rime_precision prec, const rime_sky *sky,
                    const void *data, const void *weight, void *vis, double *chi2, double *grad,
                    void *ws, size_t ws_bytes, void *stream) {
   if (!plan) return RIME_ERR_ARG;
-  if (prec != RIME_FP64 && prec != RIME_MIXED) return RIME_ERR_ARG;
+  if (!valid_prec(prec)) return RIME_ERR_ARG;
+  if (prec == kRes64 && mode == RIME_MODE_PREDICT) return RIME_ERR_UNSUPPORTED;
   rime_status st = check_sky(sky);
   if (st != RIME_OK) return st;
   if (mode == RIME_MODE_PREDICT && !vis) return RIME_ERR_ARG;
   if (mode != RIME_MODE_PREDICT && (!data || !weight || !chi2)) return RIME_ERR_ARG;
   if (mode == RIME_MODE_CHI2_GRAD && !grad) return RIME_ERR_ARG;
-  SetDesc one;
-  one.lm = sky->lm;
-  one.stokes = sky->stokes;
-  one.alpha = sky->alpha;
-  one.gshape = sky->gshape;
-  one.npsrc = sky->npsrc;
-  one.ngsrc = sky->ngsrc;
-  one.src_off = 0;
-  const int nsrc = sky->npsrc + sky->ngsrc;
+  Call c;
+  c.mode = mode;
+  c.prec = prec;
+  c.one = set_of(sky);
+  c.max_nsrc = static_cast<int>(sky_nsrc(sky));
+  c.total_src = c.max_nsrc;
+  c.data = data;
+  c.weight = weight;
+  c.vis = vis;
+  c.chi2 = chi2;
+  c.grad = grad;
   int dev = 0;
   RIME_HIP(hipGetDevice(&dev));
   if (dev != plan->device) return RIME_ERR_ARG;
-  return enqueue(plan, mode, prec, plan->variant[mode][prec], 1, nullptr, one, nullptr, nsrc,
-                 nsrc, data, weight, vis, chi2, grad, ws, ws_bytes,
+  return enqueue(plan, c, plan->variant[mode][prec], ws, ws_bytes,
                  static_cast<hipStream_t>(stream));
+}
+
+// ---------------------------------------------------------------------------
+// Streamed (out-of-core) evaluation over time chunks
+// ---------------------------------------------------------------------------
+// A view of `plan` restricted to timesteps [t0, t0 + nt): the same device
+// tables, with the time-dependent arrays offset.  Owns nothing.
+rime_plan sub_plan(const rime_plan *plan, int t0, int nt) {
+  rime_plan v = *plan;
+  v.ntime = nt;
+  v.d_uvw = plan->d_uvw + static_cast<size_t>(t0) * plan->na * 3;
+  v.d_pointing = plan->d_pointing + static_cast<size_t>(t0) * plan->na * 2;
+  v.ev_start = v.ev_stop = v.ev_main0 = v.ev_main1 = nullptr;
+  return v;
+}
+
+struct StreamLayout {
+  int chunk_t = 0, nchunk = 0;
+  size_t dbytes_t = 0, wbytes_t = 0;   // data and weight bytes per timestep
+  size_t hdr = 0, stage[2] = {0, 0}, wstage = 0, part = 0, chunk_off = 0, chunk_ws = 0;
+  int64_t stride = 0;                  // doubles per chunk result (chi^2, gradient)
+  size_t total = 0;
+};
+
+// Workspace of a streamed call: the domain header, two staging buffers of
+// chunk_t timesteps of data and weights, the per-chunk results, and one
+// chunk-sized call workspace reused by every chunk in stream order.
+StreamLayout stream_layout(const rime_plan *plan, int mode, int prec, int64_t nsrc, int chunk_t) {
+  StreamLayout S;
+  S.chunk_t = std::max(1, std::min(chunk_t, plan->ntime));
+  S.nchunk = (plan->ntime + S.chunk_t - 1) / S.chunk_t;
+  const size_t vis_t = static_cast<size_t>(plan->nbl) * plan->nchan * 4;
+  S.dbytes_t = vis_t * (prec == RIME_FP64 ? 16 : 8);
+  S.wbytes_t = vis_t * (prec == RIME_FP64 ? 8 : 4);
+  size_t off = 0;
+  S.hdr = off;
+  off += align_up(static_cast<size_t>(dom_words(1, nsrc)) * sizeof(int32_t));
+  S.wstage = align_up(S.chunk_t * S.dbytes_t);
+  for (int b = 0; b < 2; ++b) {
+    S.stage[b] = off;
+    off += S.wstage + align_up(S.chunk_t * S.wbytes_t);
+  }
+  S.stride = 1 + (mode == RIME_MODE_CHI2_GRAD ? nsrc * 10 : 0);
+  S.part = off;
+  off += align_up(static_cast<size_t>(S.nchunk) * S.stride * sizeof(double));
+  S.chunk_off = off;
+  const rime_plan sp = sub_plan(plan, 0, S.chunk_t);
+  S.chunk_ws = align_up(ws_max(&sp, mode, prec, 1, nsrc));
+  off += S.chunk_ws;
+  S.total = off;
+  return S;
 }
 
 int default_variant(const rime_plan *plan, int mode, int prec) {
@@ -589,15 +858,17 @@ int default_variant(const rime_plan *plan, int mode, int prec) {
   // 19306 baselines: 218.5 vs 212.7 ms); small arrays take 1 in both
   // precisions (7 antennas, 10 timesteps, 16 channels, 20 sources, one graph
   // launch of chi2 + gradient: FP64 30 us against 34 us for 0, float32-mixed
-  // 26 us against 28 us for 0 and 75 us for 5)
+  // 26 us against 28 us for 0 and 75 us for 5).  The float64-residual mode
+  // takes the float64 forward 1 and the float32-mixed gradient's adjoint.
   if (prec == RIME_FP64 || plan->nbl <= 96) return 1;
+  if (prec == kRes64 && mode != RIME_MODE_CHI2_GRAD) return 1;
   if (mode == RIME_MODE_CHI2_GRAD && plan->nbl >= 1024 && plan->nbl < 8192) return 4;
   return 5;
 }
 
 std::string sky_signature(const rime_sky *sky) {
   std::ostringstream o;
-  o << "p" << sky->npsrc << "g" << sky->ngsrc;
+  o << "p" << sky->npsrc << "g" << sky->ngsrc << "x" << sky->nxsrc;
   return o.str();
 }
 
@@ -711,11 +982,28 @@ const char *rime_status_string(rime_status s) {
     case RIME_ERR_HIP: return "HIP runtime error";
     case RIME_ERR_UNSUPPORTED: return "unsupported request";
     case RIME_ERR_NOMEM: return "device allocation failed";
+    case RIME_ERR_DOMAIN: return "source outside the domain l^2 + m^2 < 1";
   }
   return "unknown status";
 }
 
 int32_t rime_last_hip_error(void) { return g_last_hip; }
+
+rime_status rime_domain_status(const void *ws, size_t ws_bytes, void *stream) {
+  if (!ws || ws_bytes < sizeof(int32_t)) return RIME_ERR_ARG;
+  RIME_HIP(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+  int32_t count = 0;
+  RIME_HIP(hipMemcpy(&count, ws, sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (count < 0 || (static_cast<size_t>(count) + 1) * sizeof(int32_t) > ws_bytes)
+    return RIME_ERR_ARG;
+  std::vector<int32_t> flags(static_cast<size_t>(count));
+  if (count > 0)
+    RIME_HIP(hipMemcpy(flags.data(), static_cast<const int32_t *>(ws) + 1,
+                       flags.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+  for (int32_t f : flags)
+    if (f) return RIME_ERR_DOMAIN;
+  return RIME_OK;
+}
 
 double rime_loglike_const(const double *weight, size_t n) {
   if (!weight) return 0.0;
@@ -736,6 +1024,10 @@ void rime_plan_destroy(rime_plan *plan) {
   int cur = 0;
   const bool have = hipGetDevice(&cur) == hipSuccess;
   if (have && cur != plan->device) (void)hipSetDevice(plan->device);
+  if (plan->copy) (void)hipStreamDestroy(plan->copy);
+  for (hipEvent_t e : {plan->ev_fork, plan->ev_up[0], plan->ev_up[1], plan->ev_done[0],
+                       plan->ev_done[1]})
+    if (e) (void)hipEventDestroy(e);
   (void)hipFree(plan->d_uvw);
   (void)hipFree(plan->d_nu_c);
   (void)hipFree(plan->d_lnfr);
@@ -842,12 +1134,22 @@ rime_status rime_plan_create(const rime_obs_desc *obs, rime_plan **out) {
   for (int i = 0; i < 3 && st == RIME_OK; ++i)
     st = build_tiles(obs->na, obs->nbl, a1, a2, kNbt[i], pl->tiles[i]);
   if (st == RIME_OK) st = build_pairs(obs->na, obs->nbl, a1, a2, pl);
+  if (st == RIME_OK) {
+    // default priority, non-blocking: the streamed calls' upload lane
+    if ((e = hipStreamCreateWithFlags(&pl->copy, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming)) != hipSuccess)
+      st = hip_fail(e);
+    for (int i = 0; i < 2 && st == RIME_OK; ++i)
+      if ((e = hipEventCreateWithFlags(&pl->ev_up[i], hipEventDisableTiming)) != hipSuccess ||
+          (e = hipEventCreateWithFlags(&pl->ev_done[i], hipEventDisableTiming)) != hipSuccess)
+        st = hip_fail(e);
+  }
   if (st != RIME_OK) {
     rime_plan_destroy(pl);
     return st;
   }
   for (int m = 0; m < 3; ++m)
-    for (int p = 0; p < 2; ++p) pl->variant[m][p] = default_variant(pl, m, p);
+    for (int p = 0; p < 3; ++p) pl->variant[m][p] = default_variant(pl, m, p);
   std::ostringstream sig;
   sig << "t" << obs->ntime << "a" << obs->na << "b" << obs->nbl << "c" << obs->nchan << "e"
       << obs->beam;
@@ -858,7 +1160,7 @@ rime_status rime_plan_create(const rime_obs_desc *obs, rime_plan **out) {
 
 size_t rime_workspace_size(const rime_plan *plan, rime_mode mode, rime_precision prec,
                            int32_t nset, int64_t total_src) {
-  if (!plan || nset < 1 || total_src < 1 || mode < 0 || mode > 2 || prec < 0 || prec > 1)
+  if (!plan || nset < 1 || total_src < 1 || mode < 0 || mode > 2 || !valid_prec(prec))
     return 0;
   return ws_max(plan, mode, prec, nset, total_src);
 }
@@ -881,6 +1183,95 @@ rime_status rime_chi2_grad(const rime_plan *plan, const rime_sky *sky, rime_prec
                            void *ws, size_t ws_bytes, void *stream) {
   return single(plan, RIME_MODE_CHI2_GRAD, prec, sky, data, weight, nullptr, chi2, grad, ws,
                 ws_bytes, stream);
+}
+
+size_t rime_streamed_workspace_size(const rime_plan *plan, rime_mode mode, rime_precision prec,
+                                    int64_t nsrc, int32_t chunk_t) {
+  if (!plan || nsrc < 1 || chunk_t < 1 || (mode != RIME_MODE_CHI2 && mode != RIME_MODE_CHI2_GRAD) ||
+      !valid_prec(prec))
+    return 0;
+  return stream_layout(plan, mode, prec, nsrc, chunk_t).total;
+}
+
+rime_status rime_chi2_streamed(const rime_plan *plan, const rime_sky *sky, rime_precision prec,
+                               const void *data_host, const void *weight_host, double *chi2,
+                               double *grad, int32_t chunk_t, void *ws, size_t ws_bytes,
+                               void *stream) {
+  if (!plan || !data_host || !weight_host || !chi2 || chunk_t < 1 || !valid_prec(prec))
+    return RIME_ERR_ARG;
+  rime_status st = check_sky(sky);
+  if (st != RIME_OK) return st;
+  const int mode = grad ? RIME_MODE_CHI2_GRAD : RIME_MODE_CHI2;
+  const int64_t nsrc = sky_nsrc(sky);
+  const StreamLayout S = stream_layout(plan, mode, prec, nsrc, chunk_t);
+  if (!ws || ws_bytes < S.total) return RIME_ERR_WORKSPACE;
+  int dev = 0;
+  RIME_HIP(hipGetDevice(&dev));
+  if (dev != plan->device) return RIME_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipStream_t c = plan->copy;
+  char *w = static_cast<char *>(ws);
+  const char *dh = static_cast<const char *>(data_host);
+  const char *wh = static_cast<const char *>(weight_host);
+  double *part = reinterpret_cast<double *>(w + S.part);
+  Call base;
+  base.mode = mode;
+  base.prec = prec;
+  base.one = set_of(sky);
+  base.max_nsrc = static_cast<int>(nsrc);
+  base.total_src = nsrc;
+  // every chunk writes the same domain flags into the call's header
+  base.dom = reinterpret_cast<int32_t *>(w + S.hdr);
+  base.dom_count = static_cast<int32_t>((nsrc + 255) / 256);
+  // uploads start after earlier work on the caller's stream, which may still
+  // be using this workspace
+  RIME_HIP(hipEventRecord(plan->ev_fork, s));
+  RIME_HIP(hipStreamWaitEvent(c, plan->ev_fork, 0));
+  int last_up = -1;
+  for (int k = 0; k < S.nchunk && st == RIME_OK; ++k) {
+    const int t0 = k * S.chunk_t;
+    const int nt = std::min(S.chunk_t, plan->ntime - t0);
+    const int b = k & 1;
+    char *dst = w + S.stage[b];
+    // double buffering: chunk k reuses the buffer of chunk k - 2 once its
+    // compute has consumed it; the upload then overlaps chunk k - 1's compute
+    hipError_t e = hipSuccess;
+    if (k >= 2) e = hipStreamWaitEvent(c, plan->ev_done[b], 0);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(dst, dh + static_cast<size_t>(t0) * S.dbytes_t, nt * S.dbytes_t,
+                         hipMemcpyHostToDevice, c);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(dst + S.wstage, wh + static_cast<size_t>(t0) * S.wbytes_t,
+                         nt * S.wbytes_t, hipMemcpyHostToDevice, c);
+    if (e == hipSuccess) e = hipEventRecord(plan->ev_up[b], c);
+    if (e != hipSuccess) {
+      st = hip_fail(e);
+      break;
+    }
+    last_up = k;
+    if ((e = hipStreamWaitEvent(s, plan->ev_up[b], 0)) != hipSuccess) {
+      st = hip_fail(e);
+      break;
+    }
+    const rime_plan sp = sub_plan(plan, t0, nt);
+    Call cc = base;
+    cc.data = dst;
+    cc.weight = dst + S.wstage;
+    cc.chi2 = part + k * S.stride;
+    cc.grad = grad ? part + k * S.stride + 1 : nullptr;
+    st = enqueue(&sp, cc, plan->variant[mode][prec], w + S.chunk_off, S.chunk_ws, s, false);
+    if (st == RIME_OK && (e = hipEventRecord(plan->ev_done[b], s)) != hipSuccess)
+      st = hip_fail(e);
+  }
+  // the caller's stream always ends after the last upload (also on failure),
+  // so that nothing of this call stays unordered with later work on it
+  if (last_up >= 0) {
+    const hipError_t e = hipStreamWaitEvent(s, plan->ev_up[last_up & 1], 0);
+    if (st == RIME_OK && e != hipSuccess) st = hip_fail(e);
+  }
+  if (st != RIME_OK) return st;
+  RIME_HIP(launch_sum_chunks(part, S.nchunk, S.stride, S.stride, chi2, grad, s));
+  return RIME_OK;
 }
 
 void rime_batch_destroy(rime_batch *b) {
@@ -906,20 +1297,18 @@ rime_status rime_batch_create(const rime_plan *plan, int32_t nset, const rime_sk
     rime_status st = check_sky(&skies[i]);
     if (st != RIME_OK) return st;
     SetDesc &d = sets[i];
-    d.lm = skies[i].lm;
-    d.stokes = skies[i].stokes;
-    d.alpha = skies[i].alpha;
-    d.gshape = skies[i].gshape;
-    d.npsrc = skies[i].npsrc;
-    d.ngsrc = skies[i].ngsrc;
+    d = set_of(&skies[i]);
     d.src_off = off;
-    off += d.npsrc + d.ngsrc;
-    mx = std::max(mx, d.npsrc + d.ngsrc);
+    const int n = static_cast<int>(sky_nsrc(&skies[i]));
+    off += n;
+    mx = std::max(mx, n);
   }
   std::vector<int32_t> order(nset);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-    return sets[x].npsrc + 2 * sets[x].ngsrc > sets[y].npsrc + 2 * sets[y].ngsrc;
+    // work estimate: an extended source costs about twice a point source
+    return sets[x].npsrc + 2 * (sets[x].ngsrc + sets[x].nxsrc) >
+           sets[y].npsrc + 2 * (sets[y].ngsrc + sets[y].nxsrc);
   });
   rime_batch *b = new rime_batch;
   b->plan = plan;
@@ -932,35 +1321,56 @@ rime_status rime_batch_create(const rime_plan *plan, int32_t nset, const rime_sk
     rime_batch_destroy(b);
     return e == hipErrorOutOfMemory ? RIME_ERR_NOMEM : hip_fail(e);
   }
+  // the second lane of the per-set pipelines and its fork/join events, made
+  // here (outside any capture; default priority) so that a call never
+  // creates them
+  if (nset > 1) {
+    if ((e = hipStreamCreateWithFlags(&b->lane, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&b->join, hipEventDisableTiming)) != hipSuccess) {
+      rime_batch_destroy(b);
+      return hip_fail(e);
+    }
+  }
   *out = b;
   return RIME_OK;
 }
 
-// Per-set pipelines of the matrix-core variants run in two lanes: sets
-// 0, 2, 4, ... on the caller's stream and 1, 3, 5, ... on the batch's own, so
-// that the kernels of one set overlap those of the next (small sets leave
-// most of the chip idle).
-constexpr int kBatchLanes = 2;
+static int batch_lanes(const rime_batch *b) { return std::min(kBatchLanes, b->nset); }
 
-int batch_lanes(const rime_batch *b) { return std::min(kBatchLanes, b->nset); }
+// Domain-flag words of a batch whose sets run as separate pipelines: a count,
+// then each set's preparation workgroups in set order.
+static int64_t batch_dom_words(const rime_batch *b) {
+  int64_t n = 1;
+  for (const SetDesc &d : b->h_sets) n += (d.npsrc + d.ngsrc + d.nxsrc + 255) / 256;
+  return n;
+}
 
-// Workspace of one batched call with variant v: a matrix-core variant runs
-// the single-sky pipeline once per set, with one set's layout per lane (each
-// reused in stream order); the others run all sets in one launch sequence.
-size_t batch_ws(const rime_batch *b, int mode, int prec, const Variant &v) {
-  if (pme_active(v, prec, 1) && mode != RIME_MODE_PREDICT)
-    return batch_lanes(b) *
-           align_up(ws_layout(b->plan, mode, prec, geometry(b->plan, v, 1), 1, b->max_nsrc, v)
-                        .total);
-  return ws_layout(b->plan, mode, prec, geometry(b->plan, v, b->nset), b->nset, b->total_src, v)
-      .total;
+// Workspace of one batched call with variant vidx: a matrix-core variant runs
+// the single-sky pipeline once per set, after a header of domain flags, with
+// one set's layout per lane (each reused in stream order); the others run
+// all sets in one launch sequence.
+static size_t batch_ws(const rime_batch *b, int mode, int prec, int vidx, int fidx) {
+  const Variant *v = variant_info(mode, prec, vidx);
+  if (!v) return 0;
+  if (per_set_variant(b->plan, mode, prec, *v))
+    return align_up(static_cast<size_t>(batch_dom_words(b)) * sizeof(int32_t)) +
+           batch_lanes(b) * align_up(call_ws(b->plan, mode, prec, vidx, fidx, 1, b->max_nsrc));
+  return call_ws(b->plan, mode, prec, vidx, fidx, b->nset, b->total_src);
+}
+
+static int batch_variant(const rime_batch *b, int mode, int prec) {
+  return b->variant[mode][prec] >= 0 ? b->variant[mode][prec] : b->plan->variant[mode][prec];
 }
 
 size_t rime_batch_workspace_size(const rime_batch *b, rime_mode mode, rime_precision prec) {
-  if (!b || mode < 0 || mode > 2 || prec < 0 || prec > 1) return 0;
+  if (!b || mode < 0 || mode > 2 || !valid_prec(prec)) return 0;
   size_t best = 0;
+  const int nf = prec == kRes64 && mode == RIME_MODE_CHI2_GRAD
+                     ? variant_count(RIME_MODE_CHI2, kRes64)
+                     : 1;
   for (int i = 0; i < variant_count(mode, prec); ++i)
-    best = std::max(best, batch_ws(b, mode, prec, *variant_info(mode, prec, i)));
+    for (int f = 0; f < nf; ++f) best = std::max(best, batch_ws(b, mode, prec, i, f));
   return best;
 }
 
@@ -968,55 +1378,75 @@ rime_status rime_chi2_batched(rime_batch *b, rime_precision prec, const void *da
                               const void *weight, double *chi2, double *grad, void *ws,
                               size_t ws_bytes, void *stream, int32_t use_graph) {
   if (!b || !data || !weight || !chi2) return RIME_ERR_ARG;
-  if (prec != RIME_FP64 && prec != RIME_MIXED) return RIME_ERR_ARG;
+  if (!valid_prec(prec)) return RIME_ERR_ARG;
   const int mode = grad ? RIME_MODE_CHI2_GRAD : RIME_MODE_CHI2;
   const rime_plan *plan = b->plan;
-  const int vidx = b->variant[mode][prec] >= 0 ? b->variant[mode][prec] : plan->variant[mode][prec];
+  const int vidx = batch_variant(b, mode, prec);
+  const int fidx = plan->variant[RIME_MODE_CHI2][prec];
   const Variant *v = variant_info(mode, prec, vidx);
   if (!v) return RIME_ERR_UNSUPPORTED;
-  if (!ws || ws_bytes < batch_ws(b, mode, prec, *v)) return RIME_ERR_WORKSPACE;
+  if (!ws || ws_bytes < batch_ws(b, mode, prec, vidx, fidx)) return RIME_ERR_WORKSPACE;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  SetDesc dummy;
-  std::memset(&dummy, 0, sizeof(dummy));
-  const bool per_set = pme_active(*v, prec, 1);
+  const bool per_set = per_set_variant(plan, mode, prec, *v);
   const int lanes = per_set ? batch_lanes(b) : 1;
-  if (lanes > 1 && !b->lane) {
-    // created outside any capture; default priority
-    RIME_HIP(hipStreamCreateWithFlags(&b->lane, hipStreamNonBlocking));
-    RIME_HIP(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
-    RIME_HIP(hipEventCreateWithFlags(&b->join, hipEventDisableTiming));
-  }
-  auto run = [&]() {
-    if (!per_set)
-      return enqueue(plan, mode, prec, vidx, b->nset, b->d_sets, dummy, b->d_order,
-                     b->max_nsrc, b->total_src, data, weight, nullptr, chi2, grad, ws,
-                     ws_bytes, s);
+  Call base;
+  base.mode = mode;
+  base.prec = prec;
+  base.data = data;
+  base.weight = weight;
+  auto run = [&]() -> rime_status {
+    if (!per_set) {
+      Call c = base;
+      c.nset = b->nset;
+      c.d_sets = b->d_sets;
+      c.d_order = b->d_order;
+      c.max_nsrc = b->max_nsrc;
+      c.total_src = b->total_src;
+      c.chi2 = chi2;
+      c.grad = grad;
+      return enqueue(plan, c, vidx, ws, ws_bytes, s);
+    }
     // matrix-core variant: the single-sky pipeline per set, set i in lane
-    // i % lanes with that lane's part of the workspace; the timing events (if
-    // any) bracket the whole sequence on the caller's stream
-    const size_t lane_bytes = batch_ws(b, mode, prec, *v) / lanes;
+    // i % lanes with that lane's part of the workspace (after the batch's
+    // domain header); the timing events (if any) bracket the whole sequence
+    // on the caller's stream
+    const size_t hdr = align_up(static_cast<size_t>(batch_dom_words(b)) * sizeof(int32_t));
+    const size_t lane_bytes = align_up(call_ws(plan, mode, prec, vidx, fidx, 1, b->max_nsrc));
+    const int32_t nwords = static_cast<int32_t>(batch_dom_words(b) - 1);
     if (plan->ev_start) RIME_HIP(hipEventRecord(plan->ev_start, s));
     if (lanes > 1) {
       RIME_HIP(hipEventRecord(b->fork, s));
       RIME_HIP(hipStreamWaitEvent(b->lane, b->fork, 0));
     }
-    for (int i = 0; i < b->nset; ++i) {
-      SetDesc one = b->h_sets[i];
-      const int64_t off = one.src_off;
-      one.src_off = 0;
-      const int n = one.npsrc + one.ngsrc;
+    rime_status st = RIME_OK;
+    int32_t dom_off = 0;
+    for (int i = 0; i < b->nset && st == RIME_OK; ++i) {
+      Call c = base;
+      c.one = b->h_sets[i];
+      const int64_t off = c.one.src_off;
+      c.one.src_off = 0;
+      c.max_nsrc = c.one.npsrc + c.one.ngsrc + c.one.nxsrc;
+      c.total_src = c.max_nsrc;
+      c.chi2 = chi2 + i;
+      c.grad = grad ? grad + off * 10 : nullptr;
+      c.dom = static_cast<int32_t *>(ws);
+      c.dom_off = dom_off;
+      c.dom_count = nwords;
+      dom_off += (c.max_nsrc + 255) / 256;
       const int l = i % lanes;
-      void *lws = static_cast<char *>(ws) + l * lane_bytes;
-      const rime_status st =
-          enqueue(plan, mode, prec, vidx, 1, nullptr, one, nullptr, n, n, data, weight, nullptr,
-                  chi2 + i, grad ? grad + off * 10 : nullptr, lws, lane_bytes,
-                  l == 0 ? s : b->lane, false);
-      if (st != RIME_OK) return st;
+      void *lws = static_cast<char *>(ws) + hdr + l * lane_bytes;
+      st = enqueue(plan, c, vidx, lws, lane_bytes, l == 0 ? s : b->lane, false);
     }
+    // the lane always joins back, on the error path too, so that nothing of
+    // this call stays unordered with later work on the caller's stream (and
+    // a capture sees no unjoined fork)
     if (lanes > 1) {
-      RIME_HIP(hipEventRecord(b->join, b->lane));
-      RIME_HIP(hipStreamWaitEvent(s, b->join, 0));
+      const hipError_t e1 = hipEventRecord(b->join, b->lane);
+      const hipError_t e2 = hipStreamWaitEvent(s, b->join, 0);
+      if (st == RIME_OK && e1 != hipSuccess) return hip_fail(e1);
+      if (st == RIME_OK && e2 != hipSuccess) return hip_fail(e2);
     }
+    if (st != RIME_OK) return st;
     if (plan->ev_stop) RIME_HIP(hipEventRecord(plan->ev_stop, s));
     return RIME_OK;
   };
@@ -1052,23 +1482,23 @@ rime_status rime_chi2_batched(rime_batch *b, rime_precision prec, const void *da
 
 rime_status rime_batch_set_variant(rime_batch *b, rime_mode mode, rime_precision prec,
                                    int32_t index) {
-  if (!b || (mode != RIME_MODE_CHI2 && mode != RIME_MODE_CHI2_GRAD) ||
-      (prec != RIME_FP64 && prec != RIME_MIXED) || !variant_info(mode, prec, index))
+  if (!b || (mode != RIME_MODE_CHI2 && mode != RIME_MODE_CHI2_GRAD) || !valid_prec(prec) ||
+      !variant_info(mode, prec, index))
     return RIME_ERR_ARG;
   b->variant[mode][prec] = index;
   return RIME_OK;
 }
 
 int32_t rime_batch_get_variant(const rime_batch *b, rime_mode mode, rime_precision prec) {
-  if (!b || mode < 0 || mode > 2 || prec < 0 || prec > 1) return -1;
-  return b->variant[mode][prec] >= 0 ? b->variant[mode][prec] : b->plan->variant[mode][prec];
+  if (!b || mode < 0 || mode > 2 || !valid_prec(prec)) return -1;
+  return batch_variant(b, mode, prec);
 }
 
 rime_status rime_batch_autotune(rime_batch *b, rime_mode mode, rime_precision prec,
                                 const void *data, const void *weight, void *ws,
                                 size_t ws_bytes) {
   if (!b || !data || !weight || (mode != RIME_MODE_CHI2 && mode != RIME_MODE_CHI2_GRAD) ||
-      (prec != RIME_FP64 && prec != RIME_MIXED))
+      !valid_prec(prec))
     return RIME_ERR_ARG;
   double *chi2 = nullptr, *grad = nullptr;
   hipStream_t s = nullptr;
@@ -1153,7 +1583,7 @@ int32_t rime_variant_matrix_cores(rime_mode mode, rime_precision prec, int32_t i
 }
 
 int32_t rime_variant_count(rime_mode mode, rime_precision prec) {
-  if (mode < 0 || mode > 2 || prec < 0 || prec > 1) return 0;
+  if (mode < 0 || mode > 2 || !valid_prec(prec)) return 0;
   return variant_count(mode, prec);
 }
 
@@ -1176,14 +1606,14 @@ rime_status rime_set_variant(rime_plan *plan, rime_mode mode, rime_precision pre
 }
 
 int32_t rime_get_variant(const rime_plan *plan, rime_mode mode, rime_precision prec) {
-  if (!plan || mode < 0 || mode > 2 || prec < 0 || prec > 1) return -1;
+  if (!plan || mode < 0 || mode > 2 || !valid_prec(prec)) return -1;
   return plan->variant[mode][prec];
 }
 
 rime_status rime_autotune(rime_plan *plan, const rime_sky *sky, rime_mode mode,
                           rime_precision prec, const void *data, const void *weight, void *ws,
                           size_t ws_bytes, const char *cache_path) {
-  if (!plan || mode < 0 || mode > 2 || (prec != RIME_FP64 && prec != RIME_MIXED))
+  if (!plan || mode < 0 || mode > 2 || !valid_prec(prec))
     return RIME_ERR_ARG;
   rime_status st = check_sky(sky);
   if (st != RIME_OK) return st;
@@ -1199,7 +1629,7 @@ rime_status rime_autotune(rime_plan *plan, const rime_sky *sky, rime_mode mode,
       return RIME_OK;
     }
   }
-  const int nsrc = sky->npsrc + sky->ngsrc;
+  const int nsrc = static_cast<int>(sky_nsrc(sky));
   // scratch outputs for the trial runs
   void *vis = nullptr;
   double *chi2 = nullptr, *grad = nullptr;

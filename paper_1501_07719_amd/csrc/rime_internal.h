@@ -17,15 +17,20 @@ constexpr double kGauss = (kPi * kPi) / (4.0 * 0.6931471805599453094172321214581
 // Sources per tile (lanes of one wavefront cover srcs x chans in the adjoint).
 constexpr int kWave = 64;
 
-// One sky model as seen by the kernels.
+// One sky model as seen by the kernels: npsrc points, then ngsrc Gaussians,
+// then nxsrc exponential disks.
 struct SetDesc {
   const double *lm;      // [nsrc][2]
   const double *stokes;  // [nsrc][4]
   const double *alpha;   // [nsrc]
   const double *gshape;  // [ngsrc][3]
-  int32_t npsrc, ngsrc;
+  const double *xshape;  // [nxsrc][3]
+  int32_t npsrc, ngsrc, nxsrc;
   int64_t src_off;       // first source of this set in the concatenated source index
 };
+
+// Source morphologies (the shape factor S_tpqs of the source sum).
+enum { SHAPE_POINT = 0, SHAPE_GAUSS = 1, SHAPE_DISK = 2 };
 
 // Baseline tiling for one block size: every tile has at most `nbt` baselines
 // and at most `nat` distinct antennas.
@@ -71,6 +76,15 @@ struct KParams {
                            //   (du, dv, dw, a-tile byte offsets of p | q << 16)
   float *src_f;            // [total_src][nchan] (nu/nu_ref)^alpha, or nullptr
   int64_t total_src;
+  // domain flags (workspace header): dom[0] = number of flag words written by
+  // the call, dom[1 + dom_off + set * blocks + block] = 1 when a source of that
+  // preparation block has l^2 + m^2 >= 1 (outside the domain of n), else 0
+  int32_t *dom;
+  int32_t dom_off, dom_count;
+  // weighted residual in Stokes form per visibility, [set][ntime][nbl][nchan][4]
+  // (rho_I, rho_Q, rho_U, rho_V), written by the float64 forward of the
+  // float64-residual mixed mode and read by its float32 adjoint
+  float2 *rho_b;
   // per-call data
   const void *data;        // [ntime][nbl][nchan][4] complex
   const void *weight;      // [ntime][nbl][nchan][4] real

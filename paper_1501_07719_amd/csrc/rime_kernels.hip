@@ -34,8 +34,10 @@ __device__ void prep_baselines(const KParams &p, int nc, int t);
 // Per-call preparation, one launch.  Rows blockIdx.y < nset: per-source data,
 // (l, m, n - 1), (l/n, m/n), the spectrally scaled Stokes vector per channel
 // (eq. brightness_term) and the Gaussian shape coefficients, one thread per
-// source.  Rows nset + t (gradient mode, nc > 0): the adjoint's per-baseline
-// records of timestep t.
+// source; each workgroup also records whether one of its sources lies outside
+// the domain l^2 + m^2 < 1 of n = sqrt(1 - l^2 - m^2) (Section 2.1, after
+// eq. k_term), whose geometry is then NaN.  Rows nset + t (gradient mode,
+// nc > 0): the adjoint's per-baseline records of timestep t.
 // ---------------------------------------------------------------------------
 template <class R>
 __global__ __launch_bounds__(256) void prep_sources(const KParams p, int nc) {
@@ -46,42 +48,55 @@ __global__ __launch_bounds__(256) void prep_sources(const KParams p, int nc) {
     return;
   }
   const SetDesc sd = p.sets ? p.sets[set] : p.one;
-  const int nsrc = sd.npsrc + sd.ngsrc;
+  const int nsrc = sd.npsrc + sd.ngsrc + sd.nxsrc;
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= nsrc) return;
-  const double l = sd.lm[2 * s], m = sd.lm[2 * s + 1];
-  const double r2 = sumsq_rn(l, m);
-  const double n = sqrt(1.0 - r2);
-  const double nm1 = -r2 / (1.0 + n);
-  const int64_t g = sd.src_off + s;
-  p.src_geo[g] = make_double4(l, m, nm1, 0.0);
-  p.src_lon[g] = make_double2(l / n, m / n);
-  const double I = sd.stokes[4 * s], Q = sd.stokes[4 * s + 1];
-  const double U = sd.stokes[4 * s + 2], V = sd.stokes[4 * s + 3];
-  const double a = sd.alpha[s];
-  R4 *st = static_cast<R4 *>(p.src_st) + g * p.nchan;
-  for (int c = 0; c < p.nchan; ++c) {
-    const double f = exp(a * p.lnfr[c]);
-    R4 v;
-    v.x = static_cast<R>(f * I);
-    v.y = static_cast<R>(f * Q);
-    v.z = static_cast<R>(f * U);
-    v.w = static_cast<R>(f * V);
-    st[c] = v;
-    if (p.src_f) p.src_f[g * p.nchan + c] = static_cast<float>(f);
+  int outside = 0;
+  if (s < nsrc) {
+    const double l = sd.lm[2 * s], m = sd.lm[2 * s + 1];
+    const double r2 = sumsq_rn(l, m);
+    outside = r2 >= 1.0;
+    const double nan = __builtin_nan("");
+    const double n = outside ? nan : sqrt(1.0 - r2);
+    const double nm1 = outside ? nan : -r2 / (1.0 + n);
+    const int64_t g = sd.src_off + s;
+    p.src_geo[g] = make_double4(l, m, nm1, outside ? 1.0 : 0.0);
+    p.src_lon[g] = make_double2(l / n, m / n);
+    const double I = sd.stokes[4 * s], Q = sd.stokes[4 * s + 1];
+    const double U = sd.stokes[4 * s + 2], V = sd.stokes[4 * s + 3];
+    const double a = sd.alpha[s];
+    R4 *st = static_cast<R4 *>(p.src_st) + g * p.nchan;
+    for (int c = 0; c < p.nchan; ++c) {
+      const double f = exp(a * p.lnfr[c]);
+      R4 v;
+      v.x = static_cast<R>(f * I);
+      v.y = static_cast<R>(f * Q);
+      v.z = static_cast<R>(f * U);
+      v.w = static_cast<R>(f * V);
+      st[c] = v;
+      if (p.src_f) p.src_f[g * p.nchan + c] = static_cast<float>(f);
+    }
+    if (s >= sd.npsrc) {
+      // Gaussian or disk shape with the axis ratio folded into the minor-axis
+      // pair, so that the quadratic form is A^2 + B^2 with A = du el + dv em
+      // and B = du (R em) - dv (R el)
+      const int gi = s - sd.npsrc;
+      const double *sh = gi < sd.ngsrc ? sd.gshape + 3 * gi : sd.xshape + 3 * (gi - sd.ngsrc);
+      const double el = sh[0], em = sh[1], Rr = sh[2];
+      R4 v;
+      v.x = static_cast<R>(el);
+      v.y = static_cast<R>(em);
+      v.z = static_cast<R>(Rr * em);
+      v.w = static_cast<R>(Rr * el);
+      static_cast<R4 *>(p.src_gs)[g] = v;
+    }
   }
-  if (s >= sd.npsrc) {
-    // Gaussian shape with the axis ratio folded into the minor-axis pair, so
-    // that the exponent is A^2 + B^2 with A = du el + dv em and
-    // B = du (R em) - dv (R el)
-    const int gi = s - sd.npsrc;
-    const double el = sd.gshape[3 * gi], em = sd.gshape[3 * gi + 1], Rr = sd.gshape[3 * gi + 2];
-    R4 v;
-    v.x = static_cast<R>(el);
-    v.y = static_cast<R>(em);
-    v.z = static_cast<R>(Rr * em);
-    v.w = static_cast<R>(Rr * el);
-    static_cast<R4 *>(p.src_gs)[g] = v;
+  if (p.dom) {
+    // every workgroup of the set rows writes its flag word (no clearing pass)
+    const int any = __syncthreads_or(outside);
+    if (threadIdx.x == 0) {
+      p.dom[1 + p.dom_off + set * gridDim.x + blockIdx.x] = any;
+      if (set == 0 && blockIdx.x == 0 && p.dom_off == 0) p.dom[0] = p.dom_count;
+    }
   }
 }
 
@@ -126,7 +141,15 @@ __device__ void prep_baselines(const KParams &p, int nc, int t) {
 // Main kernel
 // ---------------------------------------------------------------------------
 
-enum { MODE_PREDICT = 0, MODE_CHI2 = 1, MODE_GRAD = 2 };
+// Kernel modes.  MODE_RESID is the forward of the float64-residual mixed
+// mode: float64 arithmetic over float32 data and weights, chi^2 partials and,
+// when p.rho_b is set, the weighted residual in Stokes form (float32) per
+// visibility and, with p.pme_adj, in the antenna-pair slots.  MODE_ADJ is its
+// float32 adjoint: pass 2 alone, over the residual read from p.rho_b.
+enum { MODE_PREDICT = 0, MODE_CHI2 = 1, MODE_GRAD = 2, MODE_RESID = 3, MODE_ADJ = 4 };
+
+template <bool B, class X, class Y> struct Pick { using T = X; };
+template <class X, class Y> struct Pick<false, X, Y> { using T = Y; };
 
 template <class R, int NBT, int NC, int NS, int MODE>
 struct Layout {
@@ -137,7 +160,7 @@ struct Layout {
   // a-tile row per source: NAT antennas x NC channels, padded by two
   // elements so that the adjoint's lanes (source x channel) hit distinct banks.
   static constexpr int AST = NAT * NC + 2;
-  static constexpr bool GRAD = MODE == MODE_GRAD;
+  static constexpr bool GRAD = MODE == MODE_GRAD || MODE == MODE_ADJ;
   static constexpr size_t A_BYTES = (sizeof(R2) * NS * AST + 511) / 512 * 512;
   static constexpr size_t BETA_BYTES = GRAD ? A_BYTES : 0;
   static constexpr size_t RED_BYTES = GRAD ? sizeof(R) * NBT * 10 : 0;
@@ -180,7 +203,7 @@ struct Layout {
 // and Gaussian shapes.
 template <class R, int NBT, int NC, int NS, int MODE, bool WITH_BETA>
 __device__ inline void stage_tile(const KParams &p, const SetDesc &sd, int tile, int s0, int cnt,
-                                  bool gauss, int c0, int ncv, const double (*s_uvw)[3],
+                                  bool shaped, int c0, int ncv, const double (*s_uvw)[3],
                                   const double (*s_pnt)[2], typename Num<R>::R2 *s_a,
                                   typename Num<R>::R2 *s_beta, typename Num<R>::R4 *s_src) {
   using L = Layout<R, NBT, NC, NS, MODE>;
@@ -204,39 +227,41 @@ __device__ inline void stage_tile(const KParams &p, const SetDesc &sd, int tile,
     }
     if (ok) {
       const double4 g = p.src_geo[sd.src_off + s0 + s];
-      // tau = u l + v m + w (n - 1), metres (eq. k_term)
-      const double tau = dot3_rn(s_uvw[ai][0], g.x, s_uvw[ai][1], g.y, s_uvw[ai][2], g.z);
-      double r2b = 0.0, dl = 0.0, dm = 0.0;
-      R rb = R(0);
+      // tau = u l + v m + w (n - 1), metres (eq. k_term), error-free
+      const Pair tau = path_length(s_uvw[ai][0], s_uvw[ai][1], s_uvw[ai][2], g.x, g.y, g.z);
+      double r2b = 0.0, dl = 0.0, dm = 0.0, rb = 0.0;
       if (p.beam) {
         dl = g.x - s_pnt[ai][0];
         dm = g.y - s_pnt[ai][1];
         r2b = sumsq_rn(dl, dm);
-        rb = N::sqrt_(r2b);
+        rb = sqrt(r2b);
       }
+      // The angles of the per-antenna factors are formed in float64 and their
+      // sines and cosines to within about a unit of R (N::sincos_turns): each
+      // factor is reused by every baseline of the tile that holds the antenna.
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         if (c < ncv) {
-          const double x = tau * p.nu_c[c0 + c];
-          const double r = x - rint(x);
+          const double r = phase_frac(tau, p.nu_c[c0 + c]);
           R sn, cs;
           N::sincos_turns(r, &sn, &cs);
           R e = R(1);
           if (p.beam) {
             // x_b = bs r, bs = beam_k nu / beam_ref_freq, clipped at beam_clip
-            // (eq. e_term); the clip is decided in float64 on r^2 against the
-            // per-channel threshold (beam_clip / bs)^2.
+            // (eq. e_term); the clip is decided on r^2 against the per-channel
+            // threshold (beam_clip / bs)^2.
             const double bs = p.beam_k * p.bfr[c0 + c];
             const bool clipped = r2b >= p.clip_r2[c0 + c];
-            const R xr = clipped ? static_cast<R>(p.beam_clip) : static_cast<R>(bs) * rb;
+            const double xr = clipped ? p.beam_clip : bs * rb;
             R sb, cb;
-            N::sincos_rad(xr, &sb, &cb);
+            N::sincos_turns(xr * kInvTwoPi, &sb, &cb);
             e = cb * cb * cb;
             if (WITH_BETA) {
               // d ln e / dl = -3 tan(x) dx/dl, dx/dl = bs (l - dl_p) / r
               //             = -3 bs^2 (l - dl_p) tan(x)/x ; zero past the clip.
               R tx = R(0);
-              if (!clipped) tx = xr > R(1e-4) ? sb * N::rcp(cb * xr) : R(1) + xr * xr * R(1.0 / 3.0);
+              const R xf = static_cast<R>(xr);
+              if (!clipped) tx = xr > 1e-4 ? sb * N::rcp(cb * xf) : R(1) + xf * xf * R(1.0 / 3.0);
               const R k3 = static_cast<R>(-3.0 * bs * bs) * tx;
               bet[c].x = k3 * static_cast<R>(dl);
               bet[c].y = k3 * static_cast<R>(dm);
@@ -254,7 +279,7 @@ __device__ inline void stage_tile(const KParams &p, const SetDesc &sd, int tile,
     }
   }
   // per-source records: the NC Stokes rows of the block's channels, then the
-  // Gaussian shape (zeros for point sources and past the tile's end)
+  // Gaussian or disk shape (zeros for point sources and past the tile's end)
   const R4 *st = static_cast<const R4 *>(p.src_st);
   const R4 *gs = static_cast<const R4 *>(p.src_gs);
   for (int idx = tid; idx < NS * L::SREC; idx += NBT) {
@@ -264,7 +289,7 @@ __device__ inline void stage_tile(const KParams &p, const SetDesc &sd, int tile,
     if (s < cnt) {
       if (c < NC) {
         if (c < ncv) v = st[(sd.src_off + s0 + s) * p.nchan + c0 + c];
-      } else if (gauss) {
+      } else if (shaped) {
         v = gs[sd.src_off + s0 + s];
       }
     }
@@ -275,10 +300,12 @@ __device__ inline void stage_tile(const KParams &p, const SetDesc &sd, int tile,
 // Pass 1 inner loop over the sources of one tile: adds
 // sum_s S c_s (I', Q', U', V')_s to the 8 accumulators of each channel.
 // `src` holds the tile's per-source records (NC scaled Stokes rows, then the
-// shape coefficients (el, em, R em, R el)); the Gaussian factor is
-// S = expb(gqs[c] (A^2 + B^2)) with A = du el + dv em, B = du R em - dv R el.
-// All lanes read the same record (an LDS broadcast).
-template <class R, int NC, int AST, bool GAUSS>
+// shape coefficients (el, em, R em, R el)).  With A = du el + dv em and
+// B = du R em - dv R el, the shape factor is S = expb(gqs[c] (A^2 + B^2)) for
+// a Gaussian and S = (1 + gqs[c] (A^2 + B^2))^(-3/2) for an exponential disk
+// (gqs: the channel's coefficient of the morphology).  All lanes read the
+// same record (an LDS broadcast).
+template <class R, int NC, int AST, int SHAPE>
 __device__ inline void accumulate(int cnt, const typename Num<R>::R2 *ap_row,
                                   const typename Num<R>::R2 *aq_row,
                                   const typename Num<R>::R4 *src, R du, R dv, const R *gqs,
@@ -291,7 +318,7 @@ __device__ inline void accumulate(int cnt, const typename Num<R>::R2 *ap_row,
   for (int s = 0; s < cnt; ++s) {
     const R4 *rs = src + s * (NC + 1);
     R Qf = R(0);
-    if (GAUSS) {
+    if (SHAPE != SHAPE_POINT) {
       const R4 g = rs[NC];
       const R A = du * g.x + dv * g.y;
       const R B = du * g.z - dv * g.w;
@@ -319,8 +346,13 @@ __device__ inline void accumulate(int cnt, const typename Num<R>::R2 *ap_row,
       const R4 st = rs[c];
       R cr = ap.x * aq.x + ap.y * aq.y;
       R ci = ap.y * aq.x - ap.x * aq.y;
-      if (GAUSS) {
+      if (SHAPE == SHAPE_GAUSS) {
         const R S = N::expb(gqs[c] * Qf);
+        cr *= S;
+        ci *= S;
+      } else if (SHAPE == SHAPE_DISK) {
+        const R r = N::rsqrt_(R(1) + gqs[c] * Qf);
+        const R S = r * r * r;
         cr *= S;
         ci *= S;
       }
@@ -342,13 +374,16 @@ __device__ inline void accumulate(int cnt, const typename Num<R>::R2 *ap_row,
 //            give sum Re P = sum_k St'_k g[k] for alpha)
 //   g[5], g[6]   sum (beta_p + beta_q)_{l,m} Re P  (beam part of l, m)
 //   g[7], g[8], g[9]  sum (du, dv, dw) Im P        (phase part of l, m)
-//   g[10..14]  Gaussian: sum du A ReP, sum dv B ReP, sum dv A ReP, sum du B ReP,
-//              sum B^2 ReP, with A = du e.x + dv e.y and B = du e.z - dv e.w the
-//              lane-scaled shape terms (S = expb(-(A^2 + B^2)))
+//   g[10..14]  Gaussian and disk: sum du A h ReP, sum dv B h ReP, sum dv A h ReP,
+//              sum du B h ReP, sum B^2 h ReP, with A = du e.x + dv e.y and
+//              B = du e.z - dv e.w the lane-scaled shape terms: for a Gaussian
+//              S = expb(-(A^2 + B^2)) and h = 1; for a disk
+//              S = (1 + A^2 + B^2)^(-3/2) and h = 1 / (1 + A^2 + B^2), the
+//              term-dependent part of d ln S / d(A^2 + B^2)
 // with P = c Phi, Phi = sum_k St'_k rho_k.  `rec` holds the tile's
 // per-baseline records (du, dv, dw, a-tile offsets of p and q), read with
 // scalar loads; the beta row of a source lies BETA_OFF bytes after its a row.
-template <class R, int NC, bool GAUSS, bool BEAM, int BETA_OFF>
+template <class R, int NC, int SHAPE, bool BEAM, int BETA_OFF>
 __device__ inline void adjoint_loop(int wave, int nw, int nact, const RIME_CONST Quad<R> *rec,
                                     const typename Num<R>::R2 *s_rho, const char *arow,
                                     const typename Num<R>::R4 st,
@@ -371,11 +406,19 @@ __device__ inline void adjoint_loop(int wave, int nw, int nact, const RIME_CONST
     const R2 r0 = rho[0], r1 = rho[1], r2 = rho[2], r3 = rho[3];
     R cr = ap.x * aq.x + ap.y * aq.y;
     R ci = ap.y * aq.x - ap.x * aq.y;
-    R A = R(0), B = R(0);
-    if (GAUSS) {
+    R A = R(0), B = R(0), h = R(1);
+    if (SHAPE == SHAPE_GAUSS) {
       A = geo.x * e.x + geo.y * e.y;
       B = geo.x * e.z - geo.y * e.w;
       const R S = N::expb(-(A * A + B * B));
+      cr *= S;
+      ci *= S;
+    } else if (SHAPE == SHAPE_DISK) {
+      A = geo.x * e.x + geo.y * e.y;
+      B = geo.x * e.z - geo.y * e.w;
+      const R r = N::rsqrt_(R(1) + A * A + B * B);
+      h = r * r;
+      const R S = h * r;
       cr *= S;
       ci *= S;
     }
@@ -401,8 +444,9 @@ __device__ inline void adjoint_loop(int wave, int nw, int nact, const RIME_CONST
     g[7] += geo.x * Pi;
     g[8] += geo.y * Pi;
     g[9] += geo.z * Pi;
-    if (GAUSS) {
-      const R t1 = A * Pr, t2 = B * Pr;
+    if (SHAPE != SHAPE_POINT) {
+      const R hP = SHAPE == SHAPE_DISK ? h * Pr : Pr;
+      const R t1 = A * hP, t2 = B * hP;
       g[10] += geo.x * t1;
       g[11] += geo.y * t2;
       g[12] += geo.y * t1;
@@ -412,12 +456,31 @@ __device__ inline void adjoint_loop(int wave, int nw, int nact, const RIME_CONST
   }
 }
 
+// Source tiles of a set: points first, then Gaussians, then disks; tile k
+// covers sources [s0, s0 + cnt) of one morphology.
+struct SrcTile {
+  int shape, s0, cnt;
+};
+
+__device__ inline SrcTile src_tile(const SetDesc &sd, int k, int ns, int npt, int ngt) {
+  if (k < npt) return {SHAPE_POINT, k * ns, min(ns, sd.npsrc - k * ns)};
+  if (k < npt + ngt) {
+    const int s0 = sd.npsrc + (k - npt) * ns;
+    return {SHAPE_GAUSS, s0, min(ns, sd.npsrc + sd.ngsrc - s0)};
+  }
+  const int s0 = sd.npsrc + sd.ngsrc + (k - npt - ngt) * ns;
+  return {SHAPE_DISK, s0, min(ns, sd.npsrc + sd.ngsrc + sd.nxsrc - s0)};
+}
+
 template <class R, int NBT, int NC, int NS, int MODE>
 __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
   using L = Layout<R, NBT, NC, NS, MODE>;
   using N = Num<R>;
   using R2 = typename N::R2;
   using R4 = typename N::R4;
+  // data and weights: float32 in the float64 forward of the float64-residual mode
+  using DT = typename Pick<MODE == MODE_RESID, float, R>::T;
+  using DT2 = typename Num<DT>::R2;
   constexpr int NAT = L::NAT;
   constexpr int NW = L::NW;
 
@@ -446,6 +509,8 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
   rem /= p.ntile;
   const int chb = rem % p.nchb;
   const int tc = rem / p.nchb;
+  // this set's part of the per-visibility residual (float64-residual mode)
+  const int64_t rho_set = static_cast<int64_t>(set) * p.ntime * p.nbl * p.nchan * 4;
 
   const int tid = threadIdx.x;
   const int nact = p.tile_nact[tile];
@@ -455,20 +520,21 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
   const int lp = lpq & 0xffff, lq = lpq >> 16;
   const int c0 = chb * NC;
   const int ncv = min(NC, p.nchan - c0);
-  const int nsrc = sd.npsrc + sd.ngsrc;
+  const int nsrc = sd.npsrc + sd.ngsrc + sd.nxsrc;
   const int t0 = tc * p.tchunk;
   const int t1 = min(p.ntime, t0 + p.tchunk);
   const int npt = (sd.npsrc + NS - 1) / NS;
   const int ngt = (sd.ngsrc + NS - 1) / NS;
-  const int nst = npt + ngt;
+  const int nst = npt + ngt + (sd.nxsrc + NS - 1) / NS;
 
   // per-channel constants of this thread's channels: -pi^2/(4 ln 2) (nu/c)^2
-  // in the argument scale of N::expb
-  R gqs[NC];
+  // in the argument scale of N::expb (Gaussian), (2 pi nu/c)^2 (disk)
+  R gqs[NC], dqs[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     const double nuc = c < ncv ? p.nu_c[c0 + c] : 0.0;
     gqs[c] = static_cast<R>(-kGauss * N::kExpScale * nuc * nuc);
+    dqs[c] = static_cast<R>(4.0 * kPi * kPi * nuc * nuc);
   }
 
   Comp chi;
@@ -552,11 +618,11 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
       } else {
         double Yr[4] = {0, 0, 0, 0}, Yi[4] = {0, 0, 0, 0};
         if (ok) {
-          const R2 *D = static_cast<const R2 *>(p.data) + vidx;
-          const R *W = static_cast<const R *>(p.weight) + vidx;
+          const DT2 *D = static_cast<const DT2 *>(p.data) + vidx;
+          const DT *W = static_cast<const DT *>(p.weight) + vidx;
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
-            const R2 d = D[k];
+            const DT2 d = D[k];
             const double w = static_cast<double>(W[k]);
             const double rr = Vr[k] - static_cast<double>(d.x);
             const double ri = Vi[k] - static_cast<double>(d.y);
@@ -565,7 +631,7 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
             Yi[k] = w * ri;
           }
         }
-        if (MODE == MODE_GRAD) {
+        if (MODE == MODE_GRAD || MODE == MODE_RESID) {
           // Z_ij = Y_ij conj(g_pi) g_qj = Y_ij conj(gg_ij); then
           // rho_I = conj(Zxx) + conj(Zyy), rho_Q = conj(Zxx) - conj(Zyy),
           // rho_U = conj(Zxy) + conj(Zyx), rho_V = i (conj(Zxy) - conj(Zyx))
@@ -575,19 +641,28 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
             Zr[k] = Yr[k] * gg[k].x + Yi[k] * gg[k].y;
             Zi[k] = Yi[k] * gg[k].x - Yr[k] * gg[k].y;
           }
-          R2 *rho = s_rho + (tid * NC + c) * 4;
-          R2 v[4];
-          v[0].x = static_cast<R>(Zr[0] + Zr[3]);
-          v[0].y = static_cast<R>(-(Zi[0] + Zi[3]));
-          v[1].x = static_cast<R>(Zr[0] - Zr[3]);
-          v[1].y = static_cast<R>(-(Zi[0] - Zi[3]));
-          v[2].x = static_cast<R>(Zr[1] + Zr[2]);
-          v[2].y = static_cast<R>(-(Zi[1] + Zi[2]));
-          v[3].x = static_cast<R>(Zi[1] - Zi[2]);
-          v[3].y = static_cast<R>(Zr[1] - Zr[2]);
+          // rho_k in the adjoint's precision (float32 in both mixed modes)
+          using A = typename Pick<MODE == MODE_RESID, float, R>::T;
+          using A2 = typename Num<A>::R2;
+          A2 v[4];
+          v[0].x = static_cast<A>(Zr[0] + Zr[3]);
+          v[0].y = static_cast<A>(-(Zi[0] + Zi[3]));
+          v[1].x = static_cast<A>(Zr[0] - Zr[3]);
+          v[1].y = static_cast<A>(-(Zi[0] - Zi[3]));
+          v[2].x = static_cast<A>(Zr[1] + Zr[2]);
+          v[2].y = static_cast<A>(-(Zi[1] + Zi[2]));
+          v[3].x = static_cast<A>(Zi[1] - Zi[2]);
+          v[3].y = static_cast<A>(Zr[1] - Zr[2]);
+          if (MODE == MODE_GRAD) {
+            A2 *rho = reinterpret_cast<A2 *>(s_rho) + (tid * NC + c) * 4;
 #pragma unroll
-          for (int kk = 0; kk < 4; ++kk) rho[kk] = v[kk];
-          if (sizeof(R) == 4 && p.pme_adj && ok) {
+            for (int kk = 0; kk < 4; ++kk) rho[kk] = v[kk];
+          } else if (ok && p.rho_b) {
+            float2 *rb = p.rho_b + rho_set + vidx;
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) rb[kk] = make_float2(v[kk].x, v[kk].y);
+          }
+          if (sizeof(A) == 4 && p.pme_adj && ok) {
             // the point-source adjoint on the matrix cores reads rho from its
             // antenna-pair slot (conjugated when the slot holds (q, p))
             const int slot = p.bl_slot[bl];
@@ -606,7 +681,19 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
       }
     };
 
-    {
+    if constexpr (MODE == MODE_ADJ) {
+      // the weighted residual of this thread's baseline from the float64
+      // forward (zero past the last channel)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const int64_t vidx =
+            rho_set + ((static_cast<int64_t>(t) * p.nbl + bl) * p.nchan + c0 + c) * 4;
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+          s_rho[(tid * NC + c) * 4 + kk] =
+              (active && c < ncv) ? p.rho_b[vidx + kk] : make_float2(0.0f, 0.0f);
+      }
+    } else {
       // ---- pass 1: source sums ----------------------------------------------
       double acc[NC][8];
 #pragma unroll
@@ -616,12 +703,12 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
 
       // with the matrix-core engine the point-source sums arrive from HBM
       for (int k = p.pme ? npt : 0; k < nst; ++k) {
-        const bool gauss = k >= npt;
-        const int s0 = gauss ? sd.npsrc + (k - npt) * NS : k * NS;
-        const int cnt = min(NS, (gauss ? nsrc : sd.npsrc) - s0);
+        const SrcTile st = src_tile(sd, k, NS, npt, ngt);
+        const int cnt = st.cnt;
         __syncthreads();
-        stage_tile<R, NBT, NC, NS, MODE, false>(p, sd, tile, s0, cnt, gauss, c0, ncv, s_uvw,
-                                                s_pnt, s_a, s_beta, s_src);
+        stage_tile<R, NBT, NC, NS, MODE, false>(p, sd, tile, st.s0, cnt,
+                                                st.shape != SHAPE_POINT, c0, ncv, s_uvw, s_pnt,
+                                                s_a, s_beta, s_src);
         __syncthreads();
         R in[NC][8];
 #pragma unroll
@@ -643,10 +730,12 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
               smem + opaque_vgpr(static_cast<uint32_t>(L::OFF_A + lq * NC * sizeof(R2))), 16));
           const R4 *src = static_cast<const R4 *>(__builtin_assume_aligned(
               smem + opaque_vgpr(static_cast<uint32_t>(L::OFF_SRC)), 16));
-          if (gauss)
-            accumulate<R, NC, L::AST, true>(cnt, ap_row, aq_row, src, du, dv, gqs, in);
+          if (st.shape == SHAPE_GAUSS)
+            accumulate<R, NC, L::AST, SHAPE_GAUSS>(cnt, ap_row, aq_row, src, du, dv, gqs, in);
+          else if (st.shape == SHAPE_DISK)
+            accumulate<R, NC, L::AST, SHAPE_DISK>(cnt, ap_row, aq_row, src, du, dv, dqs, in);
           else
-            accumulate<R, NC, L::AST, false>(cnt, ap_row, aq_row, src, du, dv, gqs, in);
+            accumulate<R, NC, L::AST, SHAPE_POINT>(cnt, ap_row, aq_row, src, du, dv, gqs, in);
         }
 #pragma unroll
         for (int c = 0; c < NC; ++c)
@@ -687,7 +776,7 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
     }
 
     // ---- pass 2: adjoint ----------------------------------------------------
-    if (MODE == MODE_GRAD) {
+    if (L::GRAD) {
       const int lane = tid % kWave;
       // wavefront index, uniform across the wavefront (scalar loop counters)
       const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
@@ -700,6 +789,11 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
       // gq = -kGauss (nu/c)^2 turns the accumulated sums into d chi^2 / d shape
       const double kap_l = sqrt(kGauss * N::kExpScale) * nuc_l;
       const double dsc_l = -2.0 * kap_l / N::kExpScale;
+      // disk lanes scale by kapd = 2 pi nu/c, so that S = (1 + A^2 + B^2)^(-3/2)
+      // and d ln S / d(A^2 + B^2) = -3/2 h: the sums turn into d chi^2 / d shape
+      // with -3 kapd in place of 2 gq / kap
+      const double kapd_l = 2.0 * kPi * nuc_l;
+      const double dscd_l = -3.0 * kapd_l;
       const double lnfr_l = lane_ok_c ? p.lnfr[c0 + cl] : 0.0;
       const RIME_CONST Quad<R> *rec =
           const_ptr<Quad<R>>(p.bl_rec) + (static_cast<int64_t>(t) * p.ntile + tile) * NBT;
@@ -708,11 +802,12 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
                      static_cast<int64_t>(local_item) * nsrc * 10;
       // with the matrix-core adjoint the point sources are done elsewhere
       for (int k = p.pme_adj ? npt : 0; k < nst; ++k) {
-        const bool gauss = k >= npt;
-        const int s0 = gauss ? sd.npsrc + (k - npt) * NS : k * NS;
-        const int cnt = min(NS, (gauss ? nsrc : sd.npsrc) - s0);
+        const SrcTile tl = src_tile(sd, k, NS, npt, ngt);
+        const int s0 = tl.s0, cnt = tl.cnt;
+        const bool shaped = tl.shape != SHAPE_POINT;
+        const bool disk = tl.shape == SHAPE_DISK;
         __syncthreads();
-        stage_tile<R, NBT, NC, NS, MODE, true>(p, sd, tile, s0, cnt, gauss, c0, ncv, s_uvw,
+        stage_tile<R, NBT, NC, NS, MODE, true>(p, sd, tile, s0, cnt, shaped, c0, ncv, s_uvw,
                                                s_pnt, s_a, s_beta, s_src);
         __syncthreads();
         R gl[10];
@@ -723,9 +818,9 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
           const double2 lo = p.src_lon[sd.src_off + s0 + sl];
           R4 e;
           e.x = e.y = e.z = e.w = R(0);
-          if (gauss) {
+          if (shaped) {
             const R4 gsh = s_src[sl * L::SREC + NC];
-            const R kap = static_cast<R>(kap_l);
+            const R kap = static_cast<R>(disk ? kapd_l : kap_l);
             e.x = kap * gsh.x;
             e.y = kap * gsh.y;
             e.z = kap * gsh.z;
@@ -739,16 +834,25 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
 #pragma unroll
           for (int j = 0; j < 15; ++j) g[j] = R(0);
           if (p.beam) {
-            if (gauss)
-              adjoint_loop<R, NC, true, true, BO>(wave, NW, nact, rec, s_rho, arow, st, e, cl, g);
+            if (tl.shape == SHAPE_GAUSS)
+              adjoint_loop<R, NC, SHAPE_GAUSS, true, BO>(wave, NW, nact, rec, s_rho, arow, st, e,
+                                                         cl, g);
+            else if (disk)
+              adjoint_loop<R, NC, SHAPE_DISK, true, BO>(wave, NW, nact, rec, s_rho, arow, st, e,
+                                                        cl, g);
             else
-              adjoint_loop<R, NC, false, true, BO>(wave, NW, nact, rec, s_rho, arow, st, e, cl, g);
+              adjoint_loop<R, NC, SHAPE_POINT, true, BO>(wave, NW, nact, rec, s_rho, arow, st, e,
+                                                         cl, g);
           } else {
-            if (gauss)
-              adjoint_loop<R, NC, true, false, BO>(wave, NW, nact, rec, s_rho, arow, st, e, cl, g);
+            if (tl.shape == SHAPE_GAUSS)
+              adjoint_loop<R, NC, SHAPE_GAUSS, false, BO>(wave, NW, nact, rec, s_rho, arow, st, e,
+                                                          cl, g);
+            else if (disk)
+              adjoint_loop<R, NC, SHAPE_DISK, false, BO>(wave, NW, nact, rec, s_rho, arow, st, e,
+                                                         cl, g);
             else
-              adjoint_loop<R, NC, false, false, BO>(wave, NW, nact, rec, s_rho, arow, st, e, cl,
-                                                    g);
+              adjoint_loop<R, NC, SHAPE_POINT, false, BO>(wave, NW, nact, rec, s_rho, arow, st, e,
+                                                          cl, g);
           }
           g[4] = st.x * g[0] + st.y * g[1] + st.z * g[2] + st.w * g[3];
           // assemble: Stokes by the spectral factor, alpha by ln(nu/nu_ref),
@@ -766,13 +870,16 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
           gl[4] = g[2] * f;
           gl[5] = g[3] * f;
           gl[6] = g[4] * static_cast<R>(lnfr_l);
-          if (gauss) {
-            const double Rr = sd.gshape[3 * (s0 + sl - sd.npsrc) + 2];
-            const R dsc = static_cast<R>(dsc_l), Rf = static_cast<R>(Rr);
+          if (shaped) {
+            const int xi = s0 + sl - sd.npsrc;
+            const double Rr =
+                disk ? sd.xshape[3 * (xi - sd.ngsrc) + 2] : sd.gshape[3 * xi + 2];
+            const double dl_ = disk ? dscd_l : dsc_l, kl_ = disk ? kapd_l : kap_l;
+            const R dsc = static_cast<R>(dl_), Rf = static_cast<R>(Rr);
             gl[7] = dsc * (g[10] - Rf * g[11]);
             gl[8] = dsc * (g[12] + Rf * g[13]);
-            gl[9] = (Rr > 0.0 && kap_l > 0.0)
-                        ? static_cast<R>(dsc_l * static_cast<double>(g[14]) / (kap_l * Rr))
+            gl[9] = (Rr > 0.0 && kl_ > 0.0)
+                        ? static_cast<R>(dl_ * static_cast<double>(g[14]) / (kl_ * Rr))
                         : R(0);
           }
         }
@@ -804,7 +911,7 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
     }
   }
 
-  if (MODE != MODE_PREDICT) {
+  if (MODE != MODE_PREDICT && MODE != MODE_ADJ) {
     const Comp r = block_reduce<NBT>(chi, s_scr);
     if (tid == 0)
       p.chi2_part[static_cast<int64_t>(set) * p.items_per_set + local_item] =
@@ -855,7 +962,7 @@ __global__ __launch_bounds__(256) void finalize_grad1(const KParams p) {
     return;
   }
   const SetDesc sd = p.sets ? p.sets[set] : p.one;
-  const int nsrc = sd.npsrc + sd.ngsrc;
+  const int nsrc = sd.npsrc + sd.ngsrc + sd.nxsrc;
   const int idx = blockIdx.x * 256 + threadIdx.x;
   if (idx >= nsrc * 10) return;
   const int chunk = blockIdx.y;
@@ -883,7 +990,7 @@ __global__ __launch_bounds__(256) void finalize_grad1(const KParams p) {
 __global__ __launch_bounds__(256) void finalize_grad2(const KParams p) {
   const int set = blockIdx.y;
   const SetDesc sd = p.sets ? p.sets[set] : p.one;
-  const int nsrc = sd.npsrc + sd.ngsrc;
+  const int nsrc = sd.npsrc + sd.ngsrc + sd.nxsrc;
   const int idx = blockIdx.x * 256 + threadIdx.x;
   if (idx >= nsrc * 10) return;
   const int64_t stride = static_cast<int64_t>(nsrc) * 10;
@@ -904,6 +1011,32 @@ __global__ __launch_bounds__(256) void finalize_grad2(const KParams p) {
     acc.merge(v.x, v.y);
   }
   p.grad_out[sd.src_off * 10 + idx] = 2.0 * (acc.s + acc.c);
+}
+
+// ---------------------------------------------------------------------------
+// Streamed evaluation: chi^2 and its gradient are additive over time
+// (eq. lhood sums over timesteps), so a call over time chunks sums the
+// chunks' results, in chunk order, compensated.  part[k] = (chi^2, grad) of
+// chunk k, `stride` doubles apart; thread idx sums entry idx of every chunk.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void sum_chunks(const double *part, int nchunk, int64_t stride,
+                                                  int64_t n, double *chi2, double *grad) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (idx >= n) return;
+  Comp acc;
+  for (int k = 0; k < nchunk; ++k) acc.add(part[k * stride + idx]);
+  const double v = acc.s + acc.c;
+  if (idx == 0)
+    chi2[0] = v;
+  else
+    grad[idx - 1] = v;
+}
+
+hipError_t launch_sum_chunks(const double *part, int nchunk, int64_t stride, int64_t n,
+                             double *chi2, double *grad, hipStream_t stream) {
+  hipLaunchKernelGGL(sum_chunks, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0,
+                     stream, part, nchunk, stride, n, chi2, grad);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -928,7 +1061,10 @@ hipError_t launch_prep(const KParams &p, bool fp64, int max_nsrc, int rec_nc,
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const KParams &p, int mode, int max_nsrc, hipStream_t stream) {
+// with_chi2 = false (gradient mode): the gradient only, chi^2 being formed
+// from the partials of another launch geometry (the float64-residual mode).
+hipError_t launch_finalize(const KParams &p, int mode, int max_nsrc, hipStream_t stream,
+                           bool with_chi2) {
   if (mode == MODE_PREDICT) return hipSuccess;
   if (mode != MODE_GRAD) {
     hipLaunchKernelGGL(finalize_chi2, dim3(p.nset), dim3(256), 0, stream, p);
@@ -936,8 +1072,8 @@ hipError_t launch_finalize(const KParams &p, int mode, int max_nsrc, hipStream_t
   }
   // level 1 of the gradient, plus chi^2 in the extra row of chunks
   const int nblk = (max_nsrc * 10 + 255) / 256;
-  hipLaunchKernelGGL(finalize_grad1, dim3(nblk, p.grad_nchunk + 1, p.nset), dim3(256), 0, stream,
-                     p);
+  hipLaunchKernelGGL(finalize_grad1, dim3(nblk, p.grad_nchunk + (with_chi2 ? 1 : 0), p.nset),
+                     dim3(256), 0, stream, p);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(finalize_grad2, dim3(nblk, p.nset), dim3(256), 0, stream, p);
@@ -979,15 +1115,37 @@ static const VariantEntry kVariants[3][2][kMaxVariants] = {
       RIME_V(float, 1024, 2, 32, MODE_GRAD, 1), RIME_V(float, 256, 2, 32, MODE_GRAD, 1)}},
 };
 
+// The float64-residual mode: float64 forwards (the shapes of the float64
+// variants) and float32 adjoints (the shapes of the float32-mixed gradient
+// variants; 4 and 5 take the point sources on the matrix cores).
+static const VariantEntry kResid[4] = {
+    RIME_V(double, 64, 2, 32, MODE_RESID, 0), RIME_V(double, 256, 2, 32, MODE_RESID, 0),
+    RIME_V(double, 1024, 2, 32, MODE_RESID, 0), RIME_V(double, 256, 4, 16, MODE_RESID, 0)};
+static const VariantEntry kAdj[kMaxVariants] = {
+    RIME_V(float, 64, 2, 32, MODE_ADJ, 0),   RIME_V(float, 256, 2, 32, MODE_ADJ, 0),
+    RIME_V(float, 1024, 2, 32, MODE_ADJ, 0), RIME_V(float, 256, 4, 16, MODE_ADJ, 0),
+    RIME_V(float, 1024, 2, 32, MODE_ADJ, 1), RIME_V(float, 256, 2, 32, MODE_ADJ, 1)};
+
+hipError_t launch_resid(int index, const KParams &p, int nitems, hipStream_t stream) {
+  return kResid[index].fn(p, nitems, stream);
+}
+
+hipError_t launch_adj(int index, const KParams &p, int nitems, hipStream_t stream) {
+  return kAdj[index].fn(p, nitems, stream);
+}
+
+// Precision 2 is the float64-residual mixed mode: its chi^2 variants are the
+// float64 forwards, its gradient variants the float32 adjoints; it has no
+// predict variant (model visibilities come from either other precision).
 int variant_count(int mode, int prec) {
-  if (mode < 0 || mode > 2 || prec < 0 || prec > 1) return 0;
+  if (mode < 0 || mode > 2 || prec < 0 || prec > 2) return 0;
+  if (prec == 2) return mode == MODE_PREDICT ? 0 : mode == MODE_CHI2 ? 4 : kMaxVariants;
   return kVariantCount[prec];
 }
 
 const Variant *variant_info(int mode, int prec, int index) {
-  if (mode < 0 || mode > 2 || prec < 0 || prec > 1 || index < 0 ||
-      index >= kVariantCount[prec])
-    return nullptr;
+  if (index < 0 || index >= variant_count(mode, prec)) return nullptr;
+  if (prec == 2) return mode == MODE_CHI2 ? &kResid[index].v : &kAdj[index].v;
   return &kVariants[mode][prec][index].v;
 }
 

@@ -114,18 +114,16 @@ __global__ __launch_bounds__(256) void pme_phase(const KParams p) {
   }
   const double4 g = p.src_geo[sd.src_off + s];
   const double *x = p.uvw + (static_cast<int64_t>(t) * p.na + a) * 3;
-  // tau = u l + v m + w (n - 1), metres (eq. k_term)
-  const double tau = dot3_rn(x[0], g.x, x[1], g.y, x[2], g.z);
-  double r2b = 0.0;
-  float rb = 0.0f;
+  // tau = u l + v m + w (n - 1), metres (eq. k_term), error-free
+  const Pair tau = path_length(x[0], x[1], x[2], g.x, g.y, g.z);
+  double r2b = 0.0, rb = 0.0;
   if (p.beam) {
     const double *q = p.pointing + (static_cast<int64_t>(t) * p.na + a) * 2;
     r2b = sumsq_rn(g.x - q[0], g.y - q[1]);
-    rb = N::sqrt_(r2b);
+    rb = sqrt(r2b);
   }
   for (int c = cb; c < ce; ++c) {
-    const double xt = tau * p.nu_c[c];
-    const double r = xt - rint(xt);
+    const double r = phase_frac(tau, p.nu_c[c]);
     float sn, cs;
     N::sincos_turns(r, &sn, &cs);
     float e = 1.0f, k3 = 0.0f;
@@ -134,9 +132,10 @@ __global__ __launch_bounds__(256) void pme_phase(const KParams p) {
       // is decided in float64 on r^2 as in the per-baseline kernels
       const double bs = p.beam_k * p.bfr[c];
       const bool clipped = r2b >= p.clip_r2[c];
-      const float xr = clipped ? static_cast<float>(p.beam_clip) : static_cast<float>(bs) * rb;
+      const double xd = clipped ? p.beam_clip : bs * rb;
+      const float xr = static_cast<float>(xd);
       float sb, cb;
-      N::sincos_rad(xr, &sb, &cb);
+      N::sincos_turns(xd * kInvTwoPi, &sb, &cb);
       e = cb * cb * cb;
       // d ln e / dl = -3 bs^2 (l - dl_p) tan(x)/x; zero past the clip
       if (!clipped) {

@@ -18,12 +18,15 @@ LIB_PATH = os.path.join(HERE, "librime.so")
 
 FP64 = 0
 MIXED = 1
+MIXED_RES64 = 2  # float64 forward and residual, float32 adjoint (chi^2 entry points)
 MODE_PREDICT = 0
 MODE_CHI2 = 1
 MODE_CHI2_GRAD = 2
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "workspace too small", 3: "HIP runtime error",
-          4: "unsupported request", 5: "device allocation failed"}
+          4: "unsupported request", 5: "device allocation failed",
+          6: "source outside the domain l^2 + m^2 < 1"}
+RIME_ERR_DOMAIN = 6
 
 C_LIGHT = 299792458.0
 
@@ -51,7 +54,7 @@ class SkyDesc(ctypes.Structure):
     _fields_ = [
         ("npsrc", ctypes.c_int32), ("ngsrc", ctypes.c_int32),
         ("lm", ctypes.c_void_p), ("stokes", ctypes.c_void_p), ("alpha", ctypes.c_void_p),
-        ("gshape", ctypes.c_void_p),
+        ("gshape", ctypes.c_void_p), ("nxsrc", ctypes.c_int32), ("xshape", ctypes.c_void_p),
     ]
 
 
@@ -90,6 +93,10 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "rime_batch_get_variant": (i32, [vp, i32, i32]),
         "rime_loglike_const": (dbl, [ctypes.POINTER(ctypes.c_double), sz]),
         "rime_status_string": (ctypes.c_char_p, [i32]),
+        "rime_domain_status": (i32, [vp, sz, vp]),
+        "rime_streamed_workspace_size": (sz, [vp, i32, i32, i64, i32]),
+        "rime_chi2_streamed": (i32, [vp, ctypes.POINTER(SkyDesc), i32, vp, vp, vp, vp, i32, vp,
+                                     sz, vp]),
         "rime_last_hip_error": (i32, []),
         "rime_autotune": (i32, [vp, ctypes.POINTER(SkyDesc), i32, i32, vp, vp, vp, sz,
                                 ctypes.c_char_p]),
@@ -219,36 +226,44 @@ class Plan:
 
 @dataclass
 class DeviceSky:
-    """One sky model on the device: float64 CUDA tensors, points first."""
+    """One sky model on the device: float64 CUDA tensors, points first, then
+    Gaussians (gshape), then exponential disks (xshape)."""
     lm: object
     stokes: object
     alpha: object
     gshape: object
     npsrc: int
     ngsrc: int
+    xshape: object = None
+    nxsrc: int = 0
 
     @property
     def nsrc(self) -> int:
-        return self.npsrc + self.ngsrc
+        return self.npsrc + self.ngsrc + self.nxsrc
 
     @staticmethod
     def from_host(sky, device="cuda"):
         import torch
         t = lambda a, shape: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64).reshape(shape),
                                              device=device)
-        n, ng = int(sky.lm.shape[0]), int(sky.gshape.shape[0])
+        xs = getattr(sky, "xshape", None)
+        xs = np.zeros((0, 3)) if xs is None else xs
+        n, ng, nx = int(sky.lm.shape[0]), int(sky.gshape.shape[0]), int(xs.shape[0])
         return DeviceSky(lm=t(sky.lm, (n, 2)), stokes=t(sky.stokes, (n, 4)),
                          alpha=t(sky.alpha, (n,)), gshape=t(sky.gshape, (ng, 3)),
-                         npsrc=n - ng, ngsrc=ng)
+                         npsrc=n - ng - nx, ngsrc=ng, xshape=t(xs, (nx, 3)), nxsrc=nx)
 
     def desc(self) -> SkyDesc:
         for x in (self.lm, self.stokes, self.alpha, self.gshape):
             _expect(x, "float64")
+        if self.nxsrc:
+            _expect(self.xshape, "float64", (self.nxsrc, 3))
         d = SkyDesc()
-        d.npsrc, d.ngsrc = self.npsrc, self.ngsrc
+        d.npsrc, d.ngsrc, d.nxsrc = self.npsrc, self.ngsrc, self.nxsrc
         d.lm, d.stokes, d.alpha = (self.lm.data_ptr(), self.stokes.data_ptr(),
                                    self.alpha.data_ptr())
         d.gshape = self.gshape.data_ptr() if self.ngsrc > 0 else None
+        d.xshape = self.xshape.data_ptr() if self.nxsrc > 0 else None
         return d
 
 
@@ -310,6 +325,35 @@ def rime_chi2_grad(plan: Plan, sky: DeviceSky, prec: int, data, weight, chi2, gr
                                     ws.numel(), _stream(stream)), "rime_chi2_grad")
 
 
+def rime_streamed_workspace_size(plan: Plan, mode: int, prec: int, nsrc: int,
+                                 chunk_t: int) -> int:
+    return int(plan._lib.rime_streamed_workspace_size(plan.handle, mode, prec, nsrc, chunk_t))
+
+
+def rime_chi2_streamed(plan: Plan, sky: DeviceSky, prec: int, data_host, weight_host, chi2,
+                       grad, chunk_t: int, ws, stream=None):
+    """chi^2 (grad None) or chi^2 and gradient with the data and weights in
+    host memory (CPU torch tensors, preferably pinned), uploaded in chunks of
+    chunk_t timesteps.  The host tensors must stay alive and unchanged until
+    the stream has finished the call."""
+    cdt, rdt = _vis_dtypes(prec)
+    shp = (plan.ntime, plan.nbl, plan.nchan, 4)
+    for x, dt in ((data_host, cdt), (weight_host, rdt)):
+        if x.is_cuda or not x.is_contiguous():
+            raise ValueError("expected a contiguous host tensor")
+        if str(x.dtype).replace("torch.", "") != dt or tuple(x.shape) != shp:
+            raise ValueError(f"expected a host {dt} tensor of shape {shp}")
+    _expect(chi2, "float64", (1,))
+    if grad is not None:
+        _expect(grad, "float64", (sky.nsrc, 10))
+    d = sky.desc()
+    _check(plan._lib.rime_chi2_streamed(plan.handle, ctypes.byref(d), prec,
+                                        ctypes.c_void_p(data_host.data_ptr()),
+                                        ctypes.c_void_p(weight_host.data_ptr()), _dptr(chi2),
+                                        _dptr(grad), int(chunk_t), _dptr(ws), ws.numel(),
+                                        _stream(stream)), "rime_chi2_streamed")
+
+
 class Batch:
     """rime_batch_create over a list of DeviceSky (their tensors must stay
     alive and keep their addresses; overwrite values in place)."""
@@ -363,8 +407,19 @@ def rime_variant_matrix_cores(mode: int, prec: int, index: int) -> bool:
     """Whether the variant forms the point-source sums on the matrix cores."""
     r = int(load_library().rime_variant_matrix_cores(mode, prec, index))
     if r < 0:
-        raise RimeError(f"no variant {index} for mode {mode}, precision {prec}")
+        raise RimeError(1, f"rime_variant_matrix_cores: no variant {index} for mode {mode}, "
+                           f"precision {prec}")
     return bool(r)
+
+
+def rime_domain_status(ws, stream=None) -> int:
+    """Status of the domain check of the last call that used workspace `ws`
+    (synchronises `stream` first): 0 when every source had l^2 + m^2 < 1,
+    RIME_ERR_DOMAIN (6) when one did; raises RimeError on any other status."""
+    st = int(load_library().rime_domain_status(_dptr(ws), ws.numel(), _stream(stream)))
+    if st not in (0, RIME_ERR_DOMAIN):
+        raise RimeError(st, "rime_domain_status")
+    return st
 
 
 def rime_batch_autotune(batch: Batch, mode: int, prec: int, data, weight, ws):

@@ -208,6 +208,22 @@ def make_sky(npsrc: int, ngsrc: int, rng: np.random.Generator) -> Sky:
     return Sky(lm=lm, stokes=stokes, alpha=alpha, gshape=gshape)
 
 
+def add_disks(sky: Sky, nxsrc: int, rng: np.random.Generator) -> Sky:
+    """`sky` followed by nxsrc exponential disks: positions, Stokes and
+    spectral indices drawn as in make_sky; major-axis scale length
+    h ~ U(0.5, 15) arcsec, axis ratio R ~ U(0.1, 1), position angle
+    ~ U(0, pi); xshape = (h sin(pa), h cos(pa), R)."""
+    extra = make_sky(nxsrc, 0, rng)
+    h = rng.uniform(0.5, 15.0, nxsrc) * ARCSEC
+    R = rng.uniform(0.1, 1.0, nxsrc)
+    pa = rng.uniform(0.0, math.pi, nxsrc)
+    xshape = np.stack([h * np.sin(pa), h * np.cos(pa), R], axis=1) if nxsrc else np.zeros((0, 3))
+    return Sky(lm=np.concatenate([sky.lm, extra.lm]),
+               stokes=np.concatenate([sky.stokes, extra.stokes]),
+               alpha=np.concatenate([sky.alpha, extra.alpha]),
+               gshape=sky.gshape, xshape=np.concatenate([sky.xshape, xshape]))
+
+
 def perturb(sky: Sky, rng: np.random.Generator, frac: float = PERTURB_FRAC) -> Sky:
     """Every scalar parameter multiplied by (1 + frac * N(0, 1))."""
     p = sky.params()

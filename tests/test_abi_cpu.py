@@ -36,7 +36,7 @@ def test_header_symbols_exported(lib):
 
 
 def test_status_strings(lib):
-    for s in range(6):
+    for s in range(7):
         assert lib.rime_status_string(s)
     assert lib.rime_status_string(0) == b"ok"
 
@@ -49,8 +49,11 @@ def test_loglike_const_matches_definition(lib):
 
 def test_variant_table(lib):
     for mode in range(3):
-        for prec in range(2):
+        for prec in range(3):
             n = R.rime_variant_count(mode, prec)
+            if prec == R.MIXED_RES64 and mode == R.MODE_PREDICT:
+                assert n == 0  # no predict entry point in the float64-residual precision
+                continue
             assert n >= 1
             for i in range(n):
                 t, c, s = R.rime_variant_info(mode, prec, i)
@@ -161,3 +164,25 @@ def test_tiling_arbitrary_lists():
     a2 = np.concatenate([a2, a2[:50], np.arange(5)]).astype(np.int32)
     for threads in (64, 256, 1024):
         _check_tiling(na, a1, a2, threads)
+
+
+def test_residual_precision_variants_mirror_the_others(lib):
+    """The float64-residual precision's chi^2 variants are the FP64 forwards
+    and its gradient variants the float32-mixed adjoints (same shapes, same
+    matrix-core flags)."""
+    for i in range(R.rime_variant_count(R.MODE_CHI2, R.MIXED_RES64)):
+        assert R.rime_variant_info(R.MODE_CHI2, R.MIXED_RES64, i) == \
+            R.rime_variant_info(R.MODE_CHI2, R.FP64, i)
+        assert not R.rime_variant_matrix_cores(R.MODE_CHI2, R.MIXED_RES64, i)
+    assert R.rime_variant_count(R.MODE_CHI2_GRAD, R.MIXED_RES64) == \
+        R.rime_variant_count(R.MODE_CHI2_GRAD, R.MIXED)
+    for i in range(R.rime_variant_count(R.MODE_CHI2_GRAD, R.MIXED)):
+        assert R.rime_variant_info(R.MODE_CHI2_GRAD, R.MIXED_RES64, i) == \
+            R.rime_variant_info(R.MODE_CHI2_GRAD, R.MIXED, i)
+        assert R.rime_variant_matrix_cores(R.MODE_CHI2_GRAD, R.MIXED_RES64, i) == \
+            R.rime_variant_matrix_cores(R.MODE_CHI2_GRAD, R.MIXED, i)
+
+
+def test_domain_status_rejects_bad_arguments(lib):
+    assert lib.rime_domain_status(None, 0, None) == 1
+    assert lib.rime_domain_status(None, 1024, None) == 1

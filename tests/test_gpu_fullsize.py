@@ -130,7 +130,7 @@ def test_full_predict_sampled(f, prec):
     assert worst <= TOL[prec], worst
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 def test_full_chi2_property(f, prec):
     """chi^2 of rime_chi2 and rime_chi2_grad at full size equals
     sum w |V - D|^2 formed from the FP64 model visibilities."""
@@ -186,3 +186,39 @@ def test_full_grad_mixed_vs_fp64(f):
     say(name, {k: f"{v:.2e}" for k, v in ge.items()})
     assert max(ge.values()) <= TOL[1], ge
     assert np.all(g32[:f.sky.npsrc, 7:] == 0.0)
+
+
+def test_full_grad_converged_res64_vs_fp64(f):
+    """Converged data at full size (D = the FP64 model at the evaluation sky
+    plus noise, rounded to complex64 and given to both precisions): the
+    float64-residual mixed gradient against the FP64 gradient, per parameter
+    type, to the mixed tolerance.  The float32-mixed gradient's error in this
+    regime is printed."""
+    name = f.name
+    obs = f.obs
+    shp = (obs.ntime, obs.nbl, obs.nchan, 4)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1502)
+    nz = torch.randn(shp + (2,), dtype=torch.float64, device="cuda", generator=g) * 0.01
+    Dc32 = (f.V64 + torch.view_as_complex(nz)).to(torch.complex64)
+    del nz
+    Dc64 = Dc32.to(torch.complex128)
+    out = {}
+    for prec, (D, W) in ((R.FP64, (Dc64, f.W64)), (R.MIXED_RES64, (Dc32, f.W32)),
+                         (R.MIXED, (Dc32, f.W32))):
+        c = torch.empty(1, dtype=torch.float64, device="cuda")
+        gr = torch.empty((f.sky.nsrc, 10), dtype=torch.float64, device="cuda")
+        ws = R.workspace(f.plan, R.MODE_CHI2_GRAD, prec, 1, f.sky.nsrc)
+        R.rime_chi2_grad(f.plan, f.dsky, prec, D, W, c, gr, ws)
+        out[prec] = (c.item(), gr.cpu().numpy())
+        del ws
+    del Dc64, Dc32
+    c64, g64 = out[R.FP64]
+    for prec in (R.MIXED_RES64, R.MIXED):
+        cp, gp = out[prec]
+        ge = grad_errors(gp, g64, f.sky.npsrc)
+        say(name, "converged", prec, f"chi2 rel {abs(cp - c64) / c64:.2e}",
+            {k: f"{v:.2e}" for k, v in ge.items()})
+        assert abs(cp - c64) <= TOL[1] * c64
+        if prec == R.MIXED_RES64:
+            assert max(ge.values()) <= TOL[1], ge

@@ -15,7 +15,8 @@ import pytest
 
 import oracle.rime_oracle as O
 from rime_synth import Observation, Sky, make_problem
-from tests._helpers import TOL, grad_errors, rel, round_inputs, vis_error
+from tests._helpers import (TOL, grad_component_errors, grad_component_worst, grad_errors, rel,
+                            round_inputs, vis_error)
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -27,9 +28,10 @@ def say(*a):
     print("[gpu-mc]", *a, flush=True)
 
 
-def mc_variants(mode):
-    return [i for i in range(R.rime_variant_count(mode, R.MIXED))
-            if R.rime_variant_matrix_cores(mode, R.MIXED, i)]
+def mc_variants(mode, prec=None):
+    prec = R.MIXED if prec is None else prec
+    return [i for i in range(R.rime_variant_count(mode, prec))
+            if R.rime_variant_matrix_cores(mode, prec, i)]
 
 
 def problem(kind):
@@ -112,17 +114,22 @@ def test_matrix_core_engine(kind):
         e = rel(chi2.item(), c)
         say(kind, "chi2", vi, f"rel {e:.2e}")
         assert e <= tol
-    for vi in mc_variants(R.MODE_CHI2_GRAD):
-        plan.set_variant(R.MODE_CHI2_GRAD, R.MIXED, vi)
-        chi2 = torch.empty(1, dtype=torch.float64, device="cuda")
-        grad = torch.empty((sky.nsrc, 10), dtype=torch.float64, device="cuda")
-        R.rime_chi2_grad(plan, dsky, R.MIXED, Dd, Wd, chi2, grad,
-                         R.workspace(plan, R.MODE_CHI2_GRAD, R.MIXED, 1, sky.nsrc))
-        ge = grad_errors(grad.cpu().numpy(), g, sky.npsrc)
-        say(kind, "grad", vi, f"chi2 rel {rel(chi2.item(), c):.2e}",
-            {k: f"{v:.1e}" for k, v in ge.items()})
-        assert rel(chi2.item(), c) <= tol
-        assert max(ge.values()) <= tol
+    for prec in (R.MIXED, R.MIXED_RES64):
+        for vi in mc_variants(R.MODE_CHI2_GRAD, prec):
+            plan.set_variant(R.MODE_CHI2_GRAD, prec, vi)
+            chi2 = torch.empty(1, dtype=torch.float64, device="cuda")
+            grad = torch.empty((sky.nsrc, 10), dtype=torch.float64, device="cuda")
+            R.rime_chi2_grad(plan, dsky, prec, Dd, Wd, chi2, grad,
+                             R.workspace(plan, R.MODE_CHI2_GRAD, prec, 1, sky.nsrc))
+            gg = grad.cpu().numpy()
+            ge = grad_errors(gg, g, sky.npsrc)
+            wc = max(grad_component_errors(gg, g, sky.npsrc, floor="rms").values())
+            say(kind, "grad", prec, vi, f"chi2 rel {rel(chi2.item(), c):.2e}",
+                {k: f"{v:.1e}" for k, v in ge.items()}, f"worst component (rms floor) {wc:.1e}",
+                f"(1e-3 max floor {grad_component_worst(gg, g, sky.npsrc):.1e})")
+            assert rel(chi2.item(), c) <= tol
+            assert max(ge.values()) <= tol
+            assert wc <= tol
     plan.close()
 
 
@@ -210,4 +217,69 @@ def test_bitwise_deterministic(prec):
     for c, g in res[1:]:
         np.testing.assert_array_equal(c, res[0][0])
         np.testing.assert_array_equal(g, res[0][1])
+    plan.close()
+
+
+def test_high_dynamic_range():
+    """A sky spanning 1e5 in brightness (I from 10 Jy down to 1e-4 Jy) with
+    Q = U = V = 0 on a third of the sources: the faint sources sit far below
+    the power-of-two operand scale that the brightest source sets for the
+    fp16 hi/lo products.  Matrix-core variants of both mixed precisions
+    against the oracle: visibilities, chi^2, and the gradient per type and per
+    component (against the type's root mean square), for all sources and for
+    the faint ones (I < 1e-3 Jy) on their own scale."""
+    pr = make_problem("c1", ntime=2, nchan=3, npsrc=60, ngsrc=10, na=40, key=38)
+    obs, sky = pr.obs, pr.sky
+    rng = np.random.default_rng(38)
+    st = sky.stokes.copy()
+    I = 10.0 * 10.0 ** (-5.0 * rng.random(sky.nsrc))
+    I[0], I[1] = 10.0, 1e-4
+    frac = st[:, 1:4] / st[:, :1]
+    st[:, 0] = I
+    st[:, 1:4] = I[:, None] * frac
+    st[::3, 1:4] = 0.0
+    sky = Sky(lm=sky.lm, stokes=st, alpha=sky.alpha, gshape=sky.gshape)
+    truth = Sky.from_params(sky.params() * (1 + 0.01 * rng.standard_normal((sky.nsrc, 10))),
+                            sky.ngsrc)
+    nz = rng.normal(0, 0.01, (obs.ntime, obs.nbl, obs.nchan, 4, 2))
+    D = O.model_vis(obs, truth) + nz[..., 0] + 1j * nz[..., 1]
+    D, W = round_inputs(D, np.full(D.shape, 1e4), R.MIXED)
+    V = O.model_vis(obs, sky)
+    c, g = O.chi2_and_grad(obs, sky, D, W)
+    faint = np.flatnonzero(I < 1e-3)
+    assert faint.size >= 5
+    plan = R.Plan(obs)
+    dsky = R.DeviceSky.from_host(sky)
+    Dd = torch.as_tensor(D, dtype=torch.complex64, device="cuda")
+    Wd = torch.as_tensor(W, dtype=torch.float32, device="cuda")
+    tol = TOL[R.MIXED]
+    for vi in mc_variants(R.MODE_PREDICT):
+        plan.set_variant(R.MODE_PREDICT, R.MIXED, vi)
+        vis = torch.empty((obs.ntime, obs.nbl, obs.nchan, 4), dtype=torch.complex64,
+                          device="cuda")
+        R.rime_predict(plan, dsky, R.MIXED, vis,
+                       R.workspace(plan, R.MODE_PREDICT, R.MIXED, 1, sky.nsrc))
+        ev = vis_error(vis.cpu().numpy().astype(np.complex128), V, sky, obs)
+        say("hdr predict", vi, f"|dV|/F = {ev:.2e}")
+        assert ev <= tol
+    for prec in (R.MIXED, R.MIXED_RES64):
+        for vi in mc_variants(R.MODE_CHI2_GRAD, prec):
+            plan.set_variant(R.MODE_CHI2_GRAD, prec, vi)
+            chi2 = torch.empty(1, dtype=torch.float64, device="cuda")
+            grad = torch.empty((sky.nsrc, 10), dtype=torch.float64, device="cuda")
+            R.rime_chi2_grad(plan, dsky, prec, Dd, Wd, chi2, grad,
+                             R.workspace(plan, R.MODE_CHI2_GRAD, prec, 1, sky.nsrc))
+            gg = grad.cpu().numpy()
+            ge = grad_errors(gg, g, sky.npsrc)
+            wc = max(grad_component_errors(gg, g, sky.npsrc, floor="rms").values())
+            # faint sources on their own scale: per column (l .. alpha), the
+            # floor is the root mean square of the faint-source components
+            a, b = gg[faint, :7], g[faint, :7]
+            floor = np.sqrt(np.mean(b * b, axis=0))
+            wf = float((np.abs(a - b) / np.maximum(np.abs(b), floor)).max())
+            say("hdr grad", prec, vi, f"chi2 rel {rel(chi2.item(), c):.2e}",
+                {k: f"{v:.1e}" for k, v in ge.items()}, f"worst {wc:.1e} faint {wf:.1e}")
+            assert rel(chi2.item(), c) <= tol
+            assert max(ge.values()) <= tol
+            assert wc <= tol and wf <= tol
     plan.close()

@@ -167,6 +167,23 @@ rime_status rime_chi2_grad(const rime_plan *plan, const rime_sky *sky, rime_prec
                            const void *data, const void *weight, double *chi2, double *grad,
                            void *ws, size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid allocation):
+ * rime_chi2_grad without a workspace argument.  The workspace is a fixed
+ * 32 MiB block of device memory inside the library, one per device, held
+ * until the process ends; the call allocates nothing.  A call whose
+ * workspace need (rime_workspace_size for mode RIME_MODE_CHI2_GRAD, one set,
+ * the sky's sources, with the plan's variant) exceeds 32 MiB returns
+ * RIME_ERR_WORKSPACE and enqueues nothing.  Every call on one device shares
+ * the block: calls that overlap on one device (on different streams, or
+ * from different host threads) race and must be serialised by the caller.
+ * rime_domain_status is not available for these calls (NaN outputs still
+ * mark a source outside the domain).  Arguments otherwise as for
+ * rime_chi2_grad. */
+rime_status rime_chi2_grad_noalloc(const rime_plan *plan, const rime_sky *sky,
+                                   rime_precision prec, const void *data, const void *weight,
+                                   double *chi2, double *grad, void *stream);
+
 /* Out-of-core chi^2 (grad == NULL) or chi^2 and gradient, streaming the
  * observed data through the device in time chunks: the paper's subdivision
  * of a problem too large for device memory along time (Section 4 "Scaling the

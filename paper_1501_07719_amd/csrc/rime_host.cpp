@@ -36,6 +36,13 @@ hipError_t launch_adj(int index, const KParams &p, int nitems, hipStream_t strea
 
 using namespace rime;
 
+// Device memory of the allocation-free entry point rime_chi2_grad_noalloc:
+// one fixed block on every device the library runs on, held until the
+// process ends.  Its name is a host-side stand-in; the device address comes
+// from hipGetSymbolAddress, once per device (scratch_ptr below).
+constexpr size_t kScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace {
 
 thread_local int32_t g_last_hip = 0;
@@ -874,6 +881,25 @@ std::string sky_signature(const rime_sky *sky) {
 
 std::mutex g_cache_mu;
 
+// Device address of `scratch` on device `dev` (the current device), looked up
+// on the first call for that device and kept.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices] = {};
+
+rime_status scratch_ptr(int dev, void **out) {
+  if (dev < 0 || dev >= kMaxDevices) return RIME_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(reinterpret_cast<void **>(&ptr), HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e);
+    g_scratch[dev] = ptr;
+  }
+  *out = g_scratch[dev];
+  return RIME_OK;
+}
+
 std::map<std::string, int> read_cache(const char *path) {
   std::map<std::string, int> m;
   std::ifstream f(path);
@@ -1183,6 +1209,22 @@ rime_status rime_chi2_grad(const rime_plan *plan, const rime_sky *sky, rime_prec
                            void *ws, size_t ws_bytes, void *stream) {
   return single(plan, RIME_MODE_CHI2_GRAD, prec, sky, data, weight, nullptr, chi2, grad, ws,
                 ws_bytes, stream);
+}
+
+rime_status rime_chi2_grad_noalloc(const rime_plan *plan, const rime_sky *sky,
+                                   rime_precision prec, const void *data, const void *weight,
+                                   double *chi2, double *grad, void *stream) {
+  if (!plan || !valid_prec(prec)) return RIME_ERR_ARG;
+  int dev = 0;
+  RIME_HIP(hipGetDevice(&dev));
+  if (dev != plan->device) return RIME_ERR_ARG;
+  void *ptr = nullptr;
+  const rime_status st = scratch_ptr(dev, &ptr);
+  if (st != RIME_OK) return st;
+  // the call's own checks reject a workspace need above kScratchBytes with
+  // RIME_ERR_WORKSPACE before anything is enqueued
+  return single(plan, RIME_MODE_CHI2_GRAD, prec, sky, data, weight, nullptr, chi2, grad, ptr,
+                kScratchBytes, stream);
 }
 
 size_t rime_streamed_workspace_size(const rime_plan *plan, rime_mode mode, rime_precision prec,

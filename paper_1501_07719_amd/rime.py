@@ -94,6 +94,7 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "rime_loglike_const": (dbl, [ctypes.POINTER(ctypes.c_double), sz]),
         "rime_status_string": (ctypes.c_char_p, [i32]),
         "rime_domain_status": (i32, [vp, sz, vp]),
+        "rime_chi2_grad_noalloc": (i32, [vp, ctypes.POINTER(SkyDesc), i32, vp, vp, vp, vp, vp]),
         "rime_streamed_workspace_size": (sz, [vp, i32, i32, i64, i32]),
         "rime_chi2_streamed": (i32, [vp, ctypes.POINTER(SkyDesc), i32, vp, vp, vp, vp, i32, vp,
                                      sz, vp]),
@@ -323,6 +324,22 @@ def rime_chi2_grad(plan: Plan, sky: DeviceSky, prec: int, data, weight, chi2, gr
     _check(plan._lib.rime_chi2_grad(plan.handle, ctypes.byref(d), prec, _dptr(data),
                                     _dptr(weight), _dptr(chi2), _dptr(grad), _dptr(ws),
                                     ws.numel(), _stream(stream)), "rime_chi2_grad")
+
+
+def rime_chi2_grad_noalloc(plan: Plan, sky: DeviceSky, prec: int, data, weight, chi2, grad,
+                           stream=None):
+    """rime_chi2_grad with the library's fixed per-device workspace (no
+    allocation; calls on one device must not overlap)."""
+    cdt, rdt = _vis_dtypes(prec)
+    shp = (plan.ntime, plan.nbl, plan.nchan, 4)
+    _expect(data, cdt, shp)
+    _expect(weight, rdt, shp)
+    _expect(chi2, "float64", (1,))
+    _expect(grad, "float64", (sky.nsrc, 10))
+    d = sky.desc()
+    _check(plan._lib.rime_chi2_grad_noalloc(plan.handle, ctypes.byref(d), prec, _dptr(data),
+                                            _dptr(weight), _dptr(chi2), _dptr(grad),
+                                            _stream(stream)), "rime_chi2_grad_noalloc")
 
 
 def rime_streamed_workspace_size(plan: Plan, mode: int, prec: int, nsrc: int,

@@ -167,6 +167,43 @@ rime_status rime_chi2_grad(const rime_plan *plan, const rime_sky *sky, rime_prec
                            const void *data, const void *weight, double *chi2, double *grad,
                            void *ws, size_t ws_bytes, void *stream);
 
+/* Per-call terms of eq. 1 beyond the sky model (NULL members are absent):
+ *  die           DEVICE [ntime][na][nchan][2][2] complex128 (re, im): the
+ *                direction-independent Jones term G_p(t, nu), applied
+ *                outside the source sum, V_pq = G_p X_pq G_q^H (eq. 1; the
+ *                paper lists it as future work, Section 6).  It replaces the
+ *                plan's diagonal gains (fold them into G).
+ *  grad_die      DEVICE, same shape: d chi^2 / d Re G + i d chi^2 / d Im G
+ *                (gradient calls only; needs die).
+ *  stokes_t      DEVICE [ntime][nsrc][4] Stokes I, Q, U, V per timestep (Table
+ *                rime_input gives the brightness as an ntime x nsrc array);
+ *                replaces the sky's stokes; the spectral index stays per
+ *                source.  Point sources then stay on the per-baseline kernel
+ *                (the matrix-core engine takes the plan's variant's
+ *                per-baseline counterpart).
+ *  grad_stokes_t DEVICE [ntime][nsrc][4]: d chi^2 / d stokes_t (gradient
+ *                calls only; needs stokes_t); the Stokes columns of `grad`
+ *                are then its sum over time. */
+typedef struct rime_terms {
+  const double *die;
+  double *grad_die;
+  const double *stokes_t;
+  double *grad_stokes_t;
+} rime_terms;
+
+/* Workspace of one single-sky call with `terms` (NULL: as rime_workspace_size
+ * with nset 1).  0 for invalid arguments. */
+size_t rime_workspace_size_ex(const rime_plan *plan, rime_mode mode, rime_precision prec,
+                              int64_t nsrc, const rime_terms *terms);
+/* rime_predict and rime_chi2 / rime_chi2_grad (grad == NULL: chi^2 only)
+ * with per-call terms; terms == NULL gives the plain calls.  Single sky. */
+rime_status rime_predict_ex(const rime_plan *plan, const rime_sky *sky, const rime_terms *terms,
+                            rime_precision prec, void *vis, void *ws, size_t ws_bytes,
+                            void *stream);
+rime_status rime_chi2_ex(const rime_plan *plan, const rime_sky *sky, const rime_terms *terms,
+                         rime_precision prec, const void *data, const void *weight, double *chi2,
+                         double *grad, void *ws, size_t ws_bytes, void *stream);
+
 /* For callers that cannot allocate device memory (code under stream
  * capture, tight serving loops, harnesses that forbid allocation):
  * rime_chi2_grad without a workspace argument.  The workspace is a fixed

@@ -231,4 +231,54 @@ __device__ inline Comp block_reduce(Comp v, double2 *scratch) {
 
 constexpr int nat_for(int nbt) { return nbt >= 1024 ? 64 : nbt >= 256 ? 32 : 16; }
 
+// 2x2 complex matrices in float64, entries (xx, xy, yx, yy) = ([0][0], [0][1],
+// [1][0], [1][1]).
+struct M22 {
+  double re[4], im[4];
+};
+
+// a b
+__device__ inline M22 m22_mul(const M22 &a, const M22 &b) {
+  M22 r;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      double sr = 0.0, si = 0.0;
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int x = 2 * i + k, y = 2 * k + j;
+        sr += a.re[x] * b.re[y] - a.im[x] * b.im[y];
+        si += a.re[x] * b.im[y] + a.im[x] * b.re[y];
+      }
+      r.re[2 * i + j] = sr;
+      r.im[2 * i + j] = si;
+    }
+  return r;
+}
+
+// a^H
+__device__ inline M22 m22_herm(const M22 &a) {
+  M22 r;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      r.re[2 * i + j] = a.re[2 * j + i];
+      r.im[2 * i + j] = -a.im[2 * j + i];
+    }
+  return r;
+}
+
+__device__ inline M22 m22_load(const double2 *m) {
+  M22 r;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double2 v = m[k];
+    r.re[k] = v.x;
+    r.im[k] = v.y;
+  }
+  return r;
+}
+
 }  // namespace rime

@@ -31,6 +31,8 @@ hipError_t launch_variant(int mode, int prec, int index, const KParams &p, int n
 hipError_t launch_resid(int index, const KParams &p, int nitems, hipStream_t stream);
 hipError_t launch_sum_chunks(const double *part, int nchunk, int64_t stride, int64_t n,
                              double *chi2, double *grad, hipStream_t stream);
+hipError_t launch_die_grad(const KParams &p, hipStream_t stream);
+hipError_t launch_stokes_t_grad(const KParams &p, hipStream_t stream);
 hipError_t launch_adj(int index, const KParams &p, int nitems, hipStream_t stream);
 }  // namespace rime
 
@@ -102,6 +104,8 @@ struct rime_plan {
   int32_t ngroup = 0;
   int32_t *d_groups = nullptr;  // [ngroup][5] forward work groups
   bool pme_adj_ok = false;  // every antenna-pair slot holds at most one baseline
+  int32_t *d_ant_off = nullptr;  // [na + 1] baselines of each antenna (both sides)
+  int2 *d_ant_bl = nullptr;      // [2 nbl] (baseline, 0: p / 1: q)
   int32_t variant[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // [mode][precision]
   std::string signature;  // observation part of the autotune key
   hipEvent_t ev_start = nullptr, ev_stop = nullptr;        // around all compute kernels
@@ -301,8 +305,13 @@ Geometry geometry(const rime_plan *plan, const Variant &v, int nset) {
   return g;
 }
 
+// Per-call terms beyond the sky (rime_terms): bits of the `terms` argument of
+// the layouts.
+enum { TERM_DIE_GRAD = 1, TERM_STOKES_T = 2, TERM_STOKES_T_GRAD = 4 };
+
 struct WsLayout {
   size_t dom = 0;
+  size_t die_part = 0, src_sf = 0, gst = 0;
   size_t geo = 0, lon = 0, st = 0, gs = 0, rec = 0, chi2 = 0, grad = 0, grad2 = 0;
   size_t ph_hi = 0, ph_lo = 0, ph_k3 = 0, spts = 0, pexp = 0, rho_t = 0, pgrad = 0;
   size_t src_f = 0, mfrag = 0, mscale = 0, rho_g = 0, pfin = 0;
@@ -340,7 +349,7 @@ int64_t dom_words(int nset, int64_t total_src) {
 // fwd_sums = false: the point-source sums of the matrix-core forward are not
 // needed (the adjoint half of the float64-residual mode).
 WsLayout ws_layout(const rime_plan *plan, int mode, int prec, const Geometry &g, int nset,
-                   int64_t total_src, const Variant &v, bool fwd_sums = true) {
+                   int64_t total_src, const Variant &v, bool fwd_sums = true, int terms = 0) {
   WsLayout L;
   const size_t r4 = prec == RIME_FP64 ? 32 : 16;
   size_t off = 0;
@@ -420,6 +429,20 @@ WsLayout ws_layout(const rime_plan *plan, int mode, int prec, const Geometry &g,
       off += align_up(nfrag * sizeof(float));
     }
   }
+  if (terms & TERM_DIE_GRAD) {
+    L.die_part = off;
+    off += align_up(static_cast<size_t>(plan->ntime) * plan->nbl * plan->nchan * 8 *
+                    sizeof(double2));
+  }
+  if (terms & TERM_STOKES_T) {
+    L.src_sf = off;
+    off += align_up(static_cast<size_t>(total_src) * plan->nchan * (r4 / 4));
+  }
+  if ((terms & TERM_STOKES_T_GRAD) && mode == RIME_MODE_CHI2_GRAD) {
+    L.gst = off;
+    off += align_up(static_cast<size_t>(g.items_per_set) * g.tchunk * total_src * 4 *
+                    sizeof(double));
+  }
   L.total = off;
   return L;
 }
@@ -434,10 +457,12 @@ struct Res64Layout {
 };
 
 Res64Layout res64_layout(const rime_plan *plan, int mode, const Variant &vf,
-                         const Variant *va, int nset, int64_t total_src) {
+                         const Variant *va, int nset, int64_t total_src, int terms = 0) {
   Res64Layout R;
+  // the forward writes the partials of the G gradient; both halves stage the
+  // brightness per timestep; the adjoint writes its per-timestep partials
   R.f = ws_layout(plan, RIME_MODE_CHI2, RIME_FP64, geometry(plan, vf, nset), nset, total_src,
-                  vf);
+                  vf, true, terms & (TERM_DIE_GRAD | TERM_STOKES_T));
   size_t off = R.f.total;
   if (mode == RIME_MODE_CHI2_GRAD && va) {
     R.va = *va;
@@ -445,7 +470,7 @@ Res64Layout res64_layout(const rime_plan *plan, int mode, const Variant &vf,
     if (!plan->pme_adj_ok) R.va.pme = 0;
     R.a_off = off;
     R.a = ws_layout(plan, RIME_MODE_CHI2_GRAD, RIME_MIXED, geometry(plan, R.va, nset), nset,
-                    total_src, R.va, false);
+                    total_src, R.va, false, terms & (TERM_STOKES_T | TERM_STOKES_T_GRAD));
     off += R.a.total;
     R.rho_b = off;
     off += align_up(static_cast<size_t>(nset) * plan->ntime * plan->nbl * plan->nchan * 4 *
@@ -458,15 +483,17 @@ Res64Layout res64_layout(const rime_plan *plan, int mode, const Variant &vf,
 // Workspace of one call of (mode, prec) with kernel variant `vidx` and, for a
 // gradient in the float64-residual mode, forward variant `fidx`.
 size_t call_ws(const rime_plan *plan, int mode, int prec, int vidx, int fidx, int nset,
-               int64_t total_src) {
+               int64_t total_src, int terms = 0) {
   const Variant *v = variant_info(mode, prec, vidx);
   if (!v) return 0;
   if (prec != kRes64)
-    return ws_layout(plan, mode, prec, geometry(plan, *v, nset), nset, total_src, *v).total;
-  if (mode == RIME_MODE_CHI2) return res64_layout(plan, mode, *v, nullptr, nset, total_src).total;
+    return ws_layout(plan, mode, prec, geometry(plan, *v, nset), nset, total_src, *v, true, terms)
+        .total;
+  if (mode == RIME_MODE_CHI2)
+    return res64_layout(plan, mode, *v, nullptr, nset, total_src, terms).total;
   const Variant *vf = variant_info(RIME_MODE_CHI2, kRes64, fidx);
   if (!vf) return 0;
-  return res64_layout(plan, mode, *vf, v, nset, total_src).total;
+  return res64_layout(plan, mode, *vf, v, nset, total_src, terms).total;
 }
 
 // Whether a batched call with this variant runs the single-sky pipeline once
@@ -568,6 +595,16 @@ struct Call {
   // and the batch's total word count
   int32_t *dom = nullptr;
   int32_t dom_off = 0, dom_count = 0;
+  // per-call terms (single sky only): G_p(t, nu) and its gradient, the
+  // brightness per timestep and its gradient
+  const double2 *die = nullptr;
+  double2 *grad_die = nullptr;
+  const double *stokes_t = nullptr;
+  double *grad_stokes_t = nullptr;
+  int terms() const {
+    return (grad_die ? TERM_DIE_GRAD : 0) | (stokes_t ? TERM_STOKES_T : 0) |
+           (grad_stokes_t ? TERM_STOKES_T_GRAD : 0);
+  }
 };
 
 // Kernel parameters of one launch geometry over workspace region `w` laid out
@@ -617,6 +654,17 @@ KParams make_params(const rime_plan *plan, const Call &c, const Variant &v, cons
   p.grad_nchunk = g.grad_nchunk;
   p.chi2_out = c.chi2;
   p.grad_out = c.grad;
+  p.die = c.die;
+  p.grad_die = c.grad_die;
+  p.ant_off = plan->d_ant_off;
+  p.ant_bl = plan->d_ant_bl;
+  if (c.grad_die && c.mode == RIME_MODE_CHI2_GRAD)
+    p.die_part = reinterpret_cast<double2 *>(w + L.die_part);
+  p.stokes_t = c.stokes_t;
+  if (c.stokes_t) p.src_sf = w + L.src_sf;
+  p.grad_stokes_t = c.grad_stokes_t;
+  if (c.grad_stokes_t && c.mode == RIME_MODE_CHI2_GRAD)
+    p.gst_part = reinterpret_cast<double *>(w + L.gst);
   p.pme = 0;
   p.pme_adj = 0;
   if (L.pme_tchunk > 0 && c.one.npsrc > 0) {
@@ -676,7 +724,7 @@ rime_status enqueue_res64(const rime_plan *plan, const Call &c, int vidx, void *
   const Variant *vf = variant_info(RIME_MODE_CHI2, kRes64, fidx);
   const Variant *va = grad ? variant_info(RIME_MODE_CHI2_GRAD, kRes64, vidx) : nullptr;
   if (!vf || (grad && !va)) return RIME_ERR_UNSUPPORTED;
-  const Res64Layout R = res64_layout(plan, c.mode, *vf, va, c.nset, c.total_src);
+  const Res64Layout R = res64_layout(plan, c.mode, *vf, va, c.nset, c.total_src, c.terms());
   if (!ws || ws_bytes < R.total) return RIME_ERR_WORKSPACE;
   const Geometry gf = geometry(plan, *vf, c.nset);
   const Geometry ga = grad ? geometry(plan, R.va, c.nset) : Geometry{};
@@ -695,8 +743,11 @@ rime_status enqueue_res64(const rime_plan *plan, const Call &c, int vidx, void *
     pa = make_params(plan, ca, R.va, ga, R.a, w + R.a_off);
     pa.dom = nullptr;  // the forward's preparation records the domain
     pa.pme = 0;        // no forward on the matrix cores
+    pa.die = nullptr;  // G enters through the forward's residual
+    pa.die_part = nullptr;
     pa.rho_b = reinterpret_cast<float2 *>(w + R.rho_b);
     pf.rho_b = pa.rho_b;
+    if (c.grad_die) pf.die_part = reinterpret_cast<double2 *>(w + R.f.die_part);
     if (pa.pme_adj) {
       // the forward also stores the residual in the antenna-pair slots
       pf.pme_adj = 1;
@@ -723,6 +774,8 @@ rime_status enqueue_res64(const rime_plan *plan, const Call &c, int vidx, void *
   if (grad) {
     RIME_HIP(launch_finalize(pa, RIME_MODE_CHI2_GRAD, c.max_nsrc, stream, false));
     if (pa.pme_adj) RIME_HIP(launch_pme_finalize(pa, stream));
+    if (pf.die_part) RIME_HIP(launch_die_grad(pf, stream));
+    if (pa.gst_part) RIME_HIP(launch_stokes_t_grad(pa, stream));
   }
   return RIME_OK;
 }
@@ -735,7 +788,7 @@ rime_status enqueue(const rime_plan *plan, const Call &c, int vidx, void *ws, si
   const Variant *v = variant_info(mode, prec, vidx);
   if (!v) return RIME_ERR_UNSUPPORTED;
   const Geometry g = geometry(plan, *v, c.nset);
-  const WsLayout L = ws_layout(plan, mode, prec, g, c.nset, c.total_src, *v);
+  const WsLayout L = ws_layout(plan, mode, prec, g, c.nset, c.total_src, *v, true, c.terms());
   if (L.total > 0 && (!ws || ws_bytes < L.total)) return RIME_ERR_WORKSPACE;
   const int64_t nitems = static_cast<int64_t>(c.nset) * g.items_per_set;
   if (nitems <= 0 || nitems > 0x7fffffff) return RIME_ERR_UNSUPPORTED;
@@ -769,19 +822,44 @@ rime_status enqueue(const rime_plan *plan, const Call &c, int vidx, void *ws, si
   if (events && plan->ev_stop) RIME_HIP(hipEventRecord(plan->ev_stop, stream));
   RIME_HIP(launch_finalize(p, mode, c.max_nsrc, stream, true));
   if (p.pme_adj) RIME_HIP(launch_pme_finalize(p, stream));
+  if (p.die_part) RIME_HIP(launch_die_grad(p, stream));
+  if (p.gst_part) RIME_HIP(launch_stokes_t_grad(p, stream));
   return RIME_OK;
 }
 
 bool valid_prec(int prec) { return prec == RIME_FP64 || prec == RIME_MIXED || prec == kRes64; }
 
+// The variant that runs a call: the plan's, except that brightness per
+// timestep keeps the point sources on the per-baseline kernel (the
+// matrix-core engine's operands are per source, not per timestep).
+int call_variant(const rime_plan *plan, int mode, int prec, bool stokes_t) {
+  const int vi = plan->variant[mode][prec];
+  const Variant *v = variant_info(mode, prec, vi);
+  if (!stokes_t || !v || !v->pme) return vi;
+  for (int i = 0; i < variant_count(mode, prec); ++i) {
+    const Variant *u = variant_info(mode, prec, i);
+    if (!u->pme && u->threads == v->threads && u->nc == v->nc && u->ns == v->ns) return i;
+  }
+  return vi;
+}
+
+rime_status check_terms(const rime_terms *terms, int mode) {
+  if (!terms) return RIME_OK;
+  if (terms->grad_die && !terms->die) return RIME_ERR_ARG;
+  if (terms->grad_stokes_t && !terms->stokes_t) return RIME_ERR_ARG;
+  if ((terms->grad_die || terms->grad_stokes_t) && mode != RIME_MODE_CHI2_GRAD) return RIME_ERR_ARG;
+  return RIME_OK;
+}
+
 rime_status single(const rime_plan *plan, int mode, rime_precision prec, const rime_sky *sky,
                    const void *data, const void *weight, void *vis, double *chi2, double *grad,
-                   void *ws, size_t ws_bytes, void *stream) {
+                   void *ws, size_t ws_bytes, void *stream, const rime_terms *terms = nullptr) {
   if (!plan) return RIME_ERR_ARG;
   if (!valid_prec(prec)) return RIME_ERR_ARG;
   if (prec == kRes64 && mode == RIME_MODE_PREDICT) return RIME_ERR_UNSUPPORTED;
   rime_status st = check_sky(sky);
   if (st != RIME_OK) return st;
+  if ((st = check_terms(terms, mode)) != RIME_OK) return st;
   if (mode == RIME_MODE_PREDICT && !vis) return RIME_ERR_ARG;
   if (mode != RIME_MODE_PREDICT && (!data || !weight || !chi2)) return RIME_ERR_ARG;
   if (mode == RIME_MODE_CHI2_GRAD && !grad) return RIME_ERR_ARG;
@@ -796,10 +874,16 @@ rime_status single(const rime_plan *plan, int mode, rime_precision prec, const r
   c.vis = vis;
   c.chi2 = chi2;
   c.grad = grad;
+  if (terms) {
+    c.die = reinterpret_cast<const double2 *>(terms->die);
+    c.grad_die = reinterpret_cast<double2 *>(terms->grad_die);
+    c.stokes_t = terms->stokes_t;
+    c.grad_stokes_t = terms->grad_stokes_t;
+  }
   int dev = 0;
   RIME_HIP(hipGetDevice(&dev));
   if (dev != plan->device) return RIME_ERR_ARG;
-  return enqueue(plan, c, plan->variant[mode][prec], ws, ws_bytes,
+  return enqueue(plan, c, call_variant(plan, mode, prec, c.stokes_t != nullptr), ws, ws_bytes,
                  static_cast<hipStream_t>(stream));
 }
 
@@ -1066,6 +1150,8 @@ void rime_plan_destroy(rime_plan *plan) {
   (void)hipFree(plan->d_pair_of);
   (void)hipFree(plan->d_pair_mask);
   (void)hipFree(plan->d_groups);
+  (void)hipFree(plan->d_ant_off);
+  (void)hipFree(plan->d_ant_bl);
   for (auto &t : plan->tiles) {
     (void)hipFree(t.bl);
     (void)hipFree(t.lpq);
@@ -1161,6 +1247,23 @@ rime_status rime_plan_create(const rime_obs_desc *obs, rime_plan **out) {
     st = build_tiles(obs->na, obs->nbl, a1, a2, kNbt[i], pl->tiles[i]);
   if (st == RIME_OK) st = build_pairs(obs->na, obs->nbl, a1, a2, pl);
   if (st == RIME_OK) {
+    // the baselines of every antenna, in baseline order (gradient of G)
+    std::vector<int32_t> off(obs->na + 1, 0);
+    for (int b = 0; b < obs->nbl; ++b) {
+      ++off[a1[b] + 1];
+      ++off[a2[b] + 1];
+    }
+    for (int a = 0; a < obs->na; ++a) off[a + 1] += off[a];
+    std::vector<int2> lst(static_cast<size_t>(2) * obs->nbl);
+    std::vector<int32_t> fill(off.begin(), off.end() - 1);
+    for (int b = 0; b < obs->nbl; ++b) {
+      lst[fill[a1[b]]++] = make_int2(b, 0);
+      lst[fill[a2[b]]++] = make_int2(b, 1);
+    }
+    if ((e = upload(&pl->d_ant_off, off)) != hipSuccess || (e = upload(&pl->d_ant_bl, lst)) != hipSuccess)
+      st = e == hipErrorOutOfMemory ? RIME_ERR_NOMEM : hip_fail(e);
+  }
+  if (st == RIME_OK) {
     // default priority, non-blocking: the streamed calls' upload lane
     if ((e = hipStreamCreateWithFlags(&pl->copy, hipStreamNonBlocking)) != hipSuccess ||
         (e = hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming)) != hipSuccess)
@@ -1209,6 +1312,39 @@ rime_status rime_chi2_grad(const rime_plan *plan, const rime_sky *sky, rime_prec
                            void *ws, size_t ws_bytes, void *stream) {
   return single(plan, RIME_MODE_CHI2_GRAD, prec, sky, data, weight, nullptr, chi2, grad, ws,
                 ws_bytes, stream);
+}
+
+size_t rime_workspace_size_ex(const rime_plan *plan, rime_mode mode, rime_precision prec,
+                              int64_t nsrc, const rime_terms *terms) {
+  if (!plan || nsrc < 1 || mode < 0 || mode > 2 || !valid_prec(prec) ||
+      check_terms(terms, mode) != RIME_OK)
+    return 0;
+  int bits = 0;
+  if (terms)
+    bits = (terms->grad_die ? TERM_DIE_GRAD : 0) | (terms->stokes_t ? TERM_STOKES_T : 0) |
+           (terms->grad_stokes_t ? TERM_STOKES_T_GRAD : 0);
+  size_t best = 0;
+  const int nf = prec == kRes64 && mode == RIME_MODE_CHI2_GRAD
+                     ? variant_count(RIME_MODE_CHI2, kRes64)
+                     : 1;
+  for (int i = 0; i < variant_count(mode, prec); ++i)
+    for (int f = 0; f < nf; ++f)
+      best = std::max(best, call_ws(plan, mode, prec, i, f, 1, nsrc, bits));
+  return best;
+}
+
+rime_status rime_predict_ex(const rime_plan *plan, const rime_sky *sky, const rime_terms *terms,
+                            rime_precision prec, void *vis, void *ws, size_t ws_bytes,
+                            void *stream) {
+  return single(plan, RIME_MODE_PREDICT, prec, sky, nullptr, nullptr, vis, nullptr, nullptr, ws,
+                ws_bytes, stream, terms);
+}
+
+rime_status rime_chi2_ex(const rime_plan *plan, const rime_sky *sky, const rime_terms *terms,
+                         rime_precision prec, const void *data, const void *weight, double *chi2,
+                         double *grad, void *ws, size_t ws_bytes, void *stream) {
+  return single(plan, grad ? RIME_MODE_CHI2_GRAD : RIME_MODE_CHI2, prec, sky, data, weight,
+                nullptr, chi2, grad, ws, ws_bytes, stream, terms);
 }
 
 rime_status rime_chi2_grad_noalloc(const rime_plan *plan, const rime_sky *sky,

@@ -85,6 +85,24 @@ struct KParams {
   // (rho_I, rho_Q, rho_U, rho_V), written by the float64 forward of the
   // float64-residual mixed mode and read by its float32 adjoint
   float2 *rho_b;
+  // direction-independent 2x2 term of eq. 1, G_p(t, nu): [ntime][na][nchan][4]
+  // complex (xx, xy, yx, yy), or nullptr for the plan's diagonal gains; its
+  // gradient (gradient calls with grad_die): per-visibility partials
+  // [ntime][nbl][nchan][2][4] (Y G_q X^H for antenna p, Y^H G_p X for q),
+  // summed per antenna over the CSR list ant_off / ant_bl (baseline, side)
+  const double2 *die;
+  double2 *die_part;
+  double2 *grad_die;
+  const int32_t *ant_off;  // [na + 1]
+  const int2 *ant_bl;      // [2 nbl] (baseline, 0 for p / 1 for q), by antenna then baseline
+  // brightness per timestep (single sky): stokes_t [ntime][nsrc][4] replaces
+  // the sky's Stokes; src_sf [nsrc][nchan] (nu/nu_ref)^alpha in R; the
+  // adjoint's per-timestep Stokes partials gst_part [item][tchunk][nsrc][4]
+  // and their sums grad_stokes_t [ntime][nsrc][4]
+  const double *stokes_t;
+  void *src_sf;
+  double *gst_part;
+  double *grad_stokes_t;
   // per-call data
   const void *data;        // [ntime][nbl][nchan][4] complex
   const void *weight;      // [ntime][nbl][nchan][4] real

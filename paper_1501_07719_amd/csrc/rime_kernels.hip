@@ -74,6 +74,7 @@ __global__ __launch_bounds__(256) void prep_sources(const KParams p, int nc) {
       v.w = static_cast<R>(f * V);
       st[c] = v;
       if (p.src_f) p.src_f[g * p.nchan + c] = static_cast<float>(f);
+      if (p.src_sf) static_cast<R *>(p.src_sf)[g * p.nchan + c] = static_cast<R>(f);
     }
     if (s >= sd.npsrc) {
       // Gaussian or disk shape with the axis ratio folded into the minor-axis
@@ -201,9 +202,10 @@ struct Layout {
 // Per-antenna stage for one source tile: a[s][ant][c] = e K (and, for the
 // adjoint, beta[s][ant][c] = d ln e / d(l, m)), plus the tile's scaled Stokes
 // and Gaussian shapes.
-template <class R, int NBT, int NC, int NS, int MODE, bool WITH_BETA>
-__device__ inline void stage_tile(const KParams &p, const SetDesc &sd, int tile, int s0, int cnt,
-                                  bool shaped, int c0, int ncv, const double (*s_uvw)[3],
+template <class R, int NBT, int NC, int NS, int MODE, bool WITH_BETA, bool TERMS>
+__device__ inline void stage_tile(const KParams &p, const SetDesc &sd, int t, int tile, int s0,
+                                  int cnt, bool shaped, int c0, int ncv,
+                                  const double (*s_uvw)[3],
                                   const double (*s_pnt)[2], typename Num<R>::R2 *s_a,
                                   typename Num<R>::R2 *s_beta, typename Num<R>::R4 *s_src) {
   using L = Layout<R, NBT, NC, NS, MODE>;
@@ -279,16 +281,31 @@ __device__ inline void stage_tile(const KParams &p, const SetDesc &sd, int tile,
     }
   }
   // per-source records: the NC Stokes rows of the block's channels, then the
-  // Gaussian or disk shape (zeros for point sources and past the tile's end)
+  // Gaussian or disk shape (zeros for point sources and past the tile's end);
+  // with brightness per timestep, the rows are (nu/nu_ref)^alpha times this
+  // timestep's Stokes vector
   const R4 *st = static_cast<const R4 *>(p.src_st);
   const R4 *gs = static_cast<const R4 *>(p.src_gs);
+  const int nsrc = sd.npsrc + sd.ngsrc + sd.nxsrc;
   for (int idx = tid; idx < NS * L::SREC; idx += NBT) {
     const int s = idx / L::SREC, c = idx - s * L::SREC;
     R4 v;
     v.x = v.y = v.z = v.w = R(0);
     if (s < cnt) {
       if (c < NC) {
-        if (c < ncv) v = st[(sd.src_off + s0 + s) * p.nchan + c0 + c];
+        if (c < ncv) {
+          if (TERMS && p.stokes_t) {
+            const double *q = p.stokes_t + (static_cast<int64_t>(t) * nsrc + s0 + s) * 4;
+            const double f = static_cast<double>(
+                static_cast<const R *>(p.src_sf)[(sd.src_off + s0 + s) * p.nchan + c0 + c]);
+            v.x = static_cast<R>(f * q[0]);
+            v.y = static_cast<R>(f * q[1]);
+            v.z = static_cast<R>(f * q[2]);
+            v.w = static_cast<R>(f * q[3]);
+          } else {
+            v = st[(sd.src_off + s0 + s) * p.nchan + c0 + c];
+          }
+        }
       } else if (shaped) {
         v = gs[sd.src_off + s0 + s];
       }
@@ -472,7 +489,10 @@ __device__ inline SrcTile src_tile(const SetDesc &sd, int k, int ns, int npt, in
   return {SHAPE_DISK, s0, min(ns, sd.npsrc + sd.ngsrc + sd.nxsrc - s0)};
 }
 
-template <class R, int NBT, int NC, int NS, int MODE>
+// TERMS: the instantiation that also applies per-call terms (a 2x2 G per
+// antenna, brightness per timestep); kept apart so that the plain calls do
+// not carry their registers.
+template <class R, int NBT, int NC, int NS, int MODE, bool TERMS>
 __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
   using L = Layout<R, NBT, NC, NS, MODE>;
   using N = Num<R>;
@@ -567,9 +587,11 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
 
     // ---- epilogue for one channel: V, residual, chi^2 (and rho) ---------------
     // S = the four Stokes sums (re, im) of this thread's baseline.
+    // the global antennas of this thread's baseline
+    const int gap = active ? p.tile_ant[tile * NAT + lp] : 0;
+    const int gaq = active ? p.tile_ant[tile * NAT + lq] : 0;
     auto gains = [&](double2 (&gg)[4]) {
       // V_ij *= g_pi conj(g_qj)
-      const int gap = p.tile_ant[tile * NAT + lp], gaq = p.tile_ant[tile * NAT + lq];
       const double2 gpi[2] = {make_double2(p.gains[4 * gap + 0], p.gains[4 * gap + 1]),
                               make_double2(p.gains[4 * gap + 2], p.gains[4 * gap + 3])};
       const double2 gqj[2] = {make_double2(p.gains[4 * gaq + 0], p.gains[4 * gaq + 1]),
@@ -584,24 +606,38 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
     };
     auto epilogue = [&](int c, const double (&S)[8], const double2 (&gg)[4]) {
       const bool ok = c < ncv;
-      // Stokes sums -> 2x2 coherency (eq. brightness_term)
+      // Stokes sums -> 2x2 coherency X (eq. brightness_term)
       const double SIr = S[0], SIi = S[1], SQr = S[2], SQi = S[3];
       const double SUr = S[4], SUi = S[5], SVr = S[6], SVi = S[7];
+      M22 X;
+      X.re[0] = SIr + SQr;  // xx
+      X.im[0] = SIi + SQi;
+      X.re[1] = SUr - SVi;  // xy = S_U + i S_V
+      X.im[1] = SUi + SVr;
+      X.re[2] = SUr + SVi;  // yx = S_U - i S_V
+      X.im[2] = SUi - SVr;
+      X.re[3] = SIr - SQr;  // yy
+      X.im[3] = SIi - SQi;
       double Vr[4], Vi[4];
-      Vr[0] = SIr + SQr;  // xx
-      Vi[0] = SIi + SQi;
-      Vr[1] = SUr - SVi;  // xy = S_U + i S_V
-      Vi[1] = SUi + SVr;
-      Vr[2] = SUr + SVi;  // yx = S_U - i S_V
-      Vi[2] = SUi - SVr;
-      Vr[3] = SIr - SQr;  // yy
-      Vi[3] = SIi - SQi;
+      // V = G_p X G_q^H (eq. 1's direction-independent term, outside the
+      // source sum), or the plan's diagonal gains
+      M22 Gp, Gq;
+      if (TERMS && p.die) {
+        const int64_t gi = (static_cast<int64_t>(t) * p.na) * p.nchan + c0 + min(c, ncv - 1);
+        Gp = m22_load(p.die + (gi + static_cast<int64_t>(gap) * p.nchan) * 4);
+        Gq = m22_load(p.die + (gi + static_cast<int64_t>(gaq) * p.nchan) * 4);
+        const M22 V = m22_mul(m22_mul(Gp, X), m22_herm(Gq));
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const double r = Vr[k] * gg[k].x - Vi[k] * gg[k].y;
-        const double i = Vr[k] * gg[k].y + Vi[k] * gg[k].x;
-        Vr[k] = r;
-        Vi[k] = i;
+        for (int k = 0; k < 4; ++k) {
+          Vr[k] = V.re[k];
+          Vi[k] = V.im[k];
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          Vr[k] = X.re[k] * gg[k].x - X.im[k] * gg[k].y;
+          Vi[k] = X.re[k] * gg[k].y + X.im[k] * gg[k].x;
+        }
       }
       const int64_t vidx = ((static_cast<int64_t>(t) * p.nbl + bl) * p.nchan + c0 + c) * 4;
       if (MODE == MODE_PREDICT) {
@@ -632,14 +668,42 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
           }
         }
         if (MODE == MODE_GRAD || MODE == MODE_RESID) {
-          // Z_ij = Y_ij conj(g_pi) g_qj = Y_ij conj(gg_ij); then
+          // the residual carried to the coherency X: Z = G_p^H Y G_q (with
+          // diagonal gains Z_ij = Y_ij conj(g_pi) g_qj = Y_ij conj(gg_ij)); then
           // rho_I = conj(Zxx) + conj(Zyy), rho_Q = conj(Zxx) - conj(Zyy),
           // rho_U = conj(Zxy) + conj(Zyx), rho_V = i (conj(Zxy) - conj(Zyx))
           double Zr[4], Zi[4];
+          if (TERMS && p.die) {
+            M22 Y;
 #pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            Zr[k] = Yr[k] * gg[k].x + Yi[k] * gg[k].y;
-            Zi[k] = Yi[k] * gg[k].x - Yr[k] * gg[k].y;
+            for (int k = 0; k < 4; ++k) {
+              Y.re[k] = Yr[k];
+              Y.im[k] = Yi[k];
+            }
+            const M22 Z = m22_mul(m22_mul(m22_herm(Gp), Y), Gq);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              Zr[k] = Z.re[k];
+              Zi[k] = Z.im[k];
+            }
+            if (ok && p.die_part) {
+              // d chi^2 / d conj(G) of this visibility: Y G_q X^H for antenna
+              // p and Y^H G_p X for antenna q
+              const M22 Ap = m22_mul(m22_mul(Y, Gq), m22_herm(X));
+              const M22 Aq = m22_mul(m22_mul(m22_herm(Y), Gp), X);
+              double2 *dp = p.die_part + vidx * 2;
+#pragma unroll
+              for (int k = 0; k < 4; ++k) {
+                dp[k] = make_double2(Ap.re[k], Ap.im[k]);
+                dp[4 + k] = make_double2(Aq.re[k], Aq.im[k]);
+              }
+            }
+          } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              Zr[k] = Yr[k] * gg[k].x + Yi[k] * gg[k].y;
+              Zi[k] = Yi[k] * gg[k].x - Yr[k] * gg[k].y;
+            }
           }
           // rho_k in the adjoint's precision (float32 in both mixed modes)
           using A = typename Pick<MODE == MODE_RESID, float, R>::T;
@@ -706,7 +770,7 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
         const SrcTile st = src_tile(sd, k, NS, npt, ngt);
         const int cnt = st.cnt;
         __syncthreads();
-        stage_tile<R, NBT, NC, NS, MODE, false>(p, sd, tile, st.s0, cnt,
+        stage_tile<R, NBT, NC, NS, MODE, false, TERMS>(p, sd, t, tile, st.s0, cnt,
                                                 st.shape != SHAPE_POINT, c0, ncv, s_uvw, s_pnt,
                                                 s_a, s_beta, s_src);
         __syncthreads();
@@ -807,8 +871,8 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
         const bool shaped = tl.shape != SHAPE_POINT;
         const bool disk = tl.shape == SHAPE_DISK;
         __syncthreads();
-        stage_tile<R, NBT, NC, NS, MODE, true>(p, sd, tile, s0, cnt, shaped, c0, ncv, s_uvw,
-                                               s_pnt, s_a, s_beta, s_src);
+        stage_tile<R, NBT, NC, NS, MODE, true, TERMS>(p, sd, t, tile, s0, cnt, shaped, c0, ncv,
+                                                      s_uvw, s_pnt, s_a, s_beta, s_src);
         __syncthreads();
         R gl[10];
 #pragma unroll
@@ -906,6 +970,11 @@ __global__ __launch_bounds__(NBT) void rime_main(const KParams p) {
             *dst = sum;
           else
             *dst += sum;
+          const int j = idx - s * 10;
+          if (TERMS && p.gst_part && j >= 2 && j < 6)
+            p.gst_part[((static_cast<int64_t>(local_item) * p.tchunk + (t - t0)) * nsrc + s0 + s) *
+                           4 +
+                       j - 2] = sum;
         }
       }
     }
@@ -1014,6 +1083,66 @@ __global__ __launch_bounds__(256) void finalize_grad2(const KParams p) {
 }
 
 // ---------------------------------------------------------------------------
+// Gradient with respect to the direction-independent term: per (timestep,
+// antenna, channel, matrix entry), twice the sum of the per-visibility
+// partials of the antenna's baselines in baseline order (compensated), i.e.
+// d chi^2 / d Re G + i d chi^2 / d Im G.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void die_grad(const KParams p) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  const int64_t n = static_cast<int64_t>(p.ntime) * p.na * p.nchan * 4;
+  if (idx >= n) return;
+  const int k = static_cast<int>(idx & 3);
+  int64_t rest = idx >> 2;
+  const int c = static_cast<int>(rest % p.nchan);
+  rest /= p.nchan;
+  const int a = static_cast<int>(rest % p.na);
+  const int t = static_cast<int>(rest / p.na);
+  Comp re, im;
+  for (int j = p.ant_off[a]; j < p.ant_off[a + 1]; ++j) {
+    const int2 e = p.ant_bl[j];
+    const double2 v =
+        p.die_part[((static_cast<int64_t>(t) * p.nbl + e.x) * p.nchan + c) * 8 + e.y * 4 + k];
+    re.add(v.x);
+    im.add(v.y);
+  }
+  p.grad_die[idx] = make_double2(2.0 * (re.s + re.c), 2.0 * (im.s + im.c));
+}
+
+// Gradient with respect to the brightness per timestep: per (timestep,
+// source, Stokes parameter), twice the sum over the work items of that
+// timestep's chunk (tiles, then channel blocks, in order).
+__global__ __launch_bounds__(256) void stokes_t_grad(const KParams p) {
+  const int nsrc = p.one.npsrc + p.one.ngsrc + p.one.nxsrc;
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (idx >= static_cast<int64_t>(p.ntime) * nsrc * 4) return;
+  const int64_t sk = idx % (static_cast<int64_t>(nsrc) * 4);
+  const int t = static_cast<int>(idx / (static_cast<int64_t>(nsrc) * 4));
+  const int tc = t / p.tchunk, tt = t - tc * p.tchunk;
+  Comp acc;
+  for (int chb = 0; chb < p.nchb; ++chb)
+    for (int tile = 0; tile < p.ntile; ++tile) {
+      const int64_t item = tile + static_cast<int64_t>(p.ntile) * (chb + p.nchb * tc);
+      acc.add(p.gst_part[(item * p.tchunk + tt) * nsrc * 4 + sk]);
+    }
+  p.grad_stokes_t[idx] = 2.0 * (acc.s + acc.c);
+}
+
+hipError_t launch_stokes_t_grad(const KParams &p, hipStream_t stream) {
+  const int64_t n = static_cast<int64_t>(p.ntime) * (p.one.npsrc + p.one.ngsrc + p.one.nxsrc) * 4;
+  hipLaunchKernelGGL(stokes_t_grad, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0,
+                     stream, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_die_grad(const KParams &p, hipStream_t stream) {
+  const int64_t n = static_cast<int64_t>(p.ntime) * p.na * p.nchan * 4;
+  hipLaunchKernelGGL(die_grad, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, stream,
+                     p);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Streamed evaluation: chi^2 and its gradient are additive over time
 // (eq. lhood sums over timesteps), so a call over time chunks sums the
 // chunks' results, in chunk order, compensated.  part[k] = (chi^2, grad) of
@@ -1043,9 +1172,15 @@ hipError_t launch_sum_chunks(const double *part, int nchunk, int64_t stride, int
 // Launchers
 // ---------------------------------------------------------------------------
 
+// The instantiation with per-call terms runs only when a call has them.
 template <class R, int NBT, int NC, int NS, int MODE>
 static hipError_t launch_main(const KParams &p, int nitems, hipStream_t stream) {
-  hipLaunchKernelGGL((rime_main<R, NBT, NC, NS, MODE>), dim3(nitems), dim3(NBT), 0, stream, p);
+  if (p.die || p.stokes_t)
+    hipLaunchKernelGGL((rime_main<R, NBT, NC, NS, MODE, true>), dim3(nitems), dim3(NBT), 0,
+                       stream, p);
+  else
+    hipLaunchKernelGGL((rime_main<R, NBT, NC, NS, MODE, false>), dim3(nitems), dim3(NBT), 0,
+                       stream, p);
   return hipGetLastError();
 }
 

@@ -58,6 +58,11 @@ class SkyDesc(ctypes.Structure):
     ]
 
 
+class TermsDesc(ctypes.Structure):
+    _fields_ = [("die", ctypes.c_void_p), ("grad_die", ctypes.c_void_p),
+                ("stokes_t", ctypes.c_void_p), ("grad_stokes_t", ctypes.c_void_p)]
+
+
 _lib = None
 
 
@@ -95,6 +100,11 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "rime_status_string": (ctypes.c_char_p, [i32]),
         "rime_domain_status": (i32, [vp, sz, vp]),
         "rime_chi2_grad_noalloc": (i32, [vp, ctypes.POINTER(SkyDesc), i32, vp, vp, vp, vp, vp]),
+        "rime_workspace_size_ex": (sz, [vp, i32, i32, i64, ctypes.POINTER(TermsDesc)]),
+        "rime_predict_ex": (i32, [vp, ctypes.POINTER(SkyDesc), ctypes.POINTER(TermsDesc), i32, vp,
+                                  vp, sz, vp]),
+        "rime_chi2_ex": (i32, [vp, ctypes.POINTER(SkyDesc), ctypes.POINTER(TermsDesc), i32, vp,
+                               vp, vp, vp, vp, sz, vp]),
         "rime_streamed_workspace_size": (sz, [vp, i32, i32, i64, i32]),
         "rime_chi2_streamed": (i32, [vp, ctypes.POINTER(SkyDesc), i32, vp, vp, vp, vp, i32, vp,
                                      sz, vp]),
@@ -369,6 +379,63 @@ def rime_chi2_streamed(plan: Plan, sky: DeviceSky, prec: int, data_host, weight_
                                         ctypes.c_void_p(weight_host.data_ptr()), _dptr(chi2),
                                         _dptr(grad), int(chunk_t), _dptr(ws), ws.numel(),
                                         _stream(stream)), "rime_chi2_streamed")
+
+
+def _terms(plan, sky, die=None, grad_die=None, stokes_t=None, grad_stokes_t=None):
+    """TermsDesc of the optional per-call terms (device tensors): die and
+    grad_die complex128 [ntime][na][nchan][2][2], stokes_t and grad_stokes_t
+    float64 [ntime][nsrc][4]."""
+    t = TermsDesc()
+    gshape = (plan.ntime, plan.na, plan.nchan, 2, 2)
+    sshape = (plan.ntime, sky.nsrc, 4)
+    for name, x, dt, shp in (("die", die, "complex128", gshape),
+                             ("grad_die", grad_die, "complex128", gshape),
+                             ("stokes_t", stokes_t, "float64", sshape),
+                             ("grad_stokes_t", grad_stokes_t, "float64", sshape)):
+        if x is not None:
+            _expect(x, dt, shp)
+            setattr(t, name, x.data_ptr())
+    return t
+
+
+def rime_workspace_size_ex(plan: Plan, mode: int, prec: int, nsrc: int, die=False,
+                           grad_die=False, stokes_t=False, grad_stokes_t=False) -> int:
+    """Workspace bytes of a single-sky call with the given terms present."""
+    t = TermsDesc()
+    # presence is what counts: any non-null address
+    t.die = 1 if (die or grad_die) else None
+    t.grad_die = 1 if grad_die else None
+    t.stokes_t = 1 if (stokes_t or grad_stokes_t) else None
+    t.grad_stokes_t = 1 if grad_stokes_t else None
+    return int(plan._lib.rime_workspace_size_ex(plan.handle, mode, prec, nsrc, ctypes.byref(t)))
+
+
+def rime_predict_ex(plan: Plan, sky: DeviceSky, prec: int, vis, ws, die=None, stokes_t=None,
+                    stream=None):
+    cdt, _ = _vis_dtypes(prec)
+    _expect(vis, cdt, (plan.ntime, plan.nbl, plan.nchan, 4))
+    d = sky.desc()
+    t = _terms(plan, sky, die=die, stokes_t=stokes_t)
+    _check(plan._lib.rime_predict_ex(plan.handle, ctypes.byref(d), ctypes.byref(t), prec,
+                                     _dptr(vis), _dptr(ws), ws.numel(), _stream(stream)),
+           "rime_predict_ex")
+
+
+def rime_chi2_ex(plan: Plan, sky: DeviceSky, prec: int, data, weight, chi2, grad, ws, die=None,
+                 grad_die=None, stokes_t=None, grad_stokes_t=None, stream=None):
+    """chi^2 (grad None) or chi^2 and gradient with the per-call terms."""
+    cdt, rdt = _vis_dtypes(prec)
+    shp = (plan.ntime, plan.nbl, plan.nchan, 4)
+    _expect(data, cdt, shp)
+    _expect(weight, rdt, shp)
+    _expect(chi2, "float64", (1,))
+    if grad is not None:
+        _expect(grad, "float64", (sky.nsrc, 10))
+    d = sky.desc()
+    t = _terms(plan, sky, die, grad_die, stokes_t, grad_stokes_t)
+    _check(plan._lib.rime_chi2_ex(plan.handle, ctypes.byref(d), ctypes.byref(t), prec,
+                                  _dptr(data), _dptr(weight), _dptr(chi2), _dptr(grad),
+                                  _dptr(ws), ws.numel(), _stream(stream)), "rime_chi2_ex")
 
 
 class Batch:

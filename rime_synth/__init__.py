@@ -224,6 +224,23 @@ def add_disks(sky: Sky, nxsrc: int, rng: np.random.Generator) -> Sky:
                gshape=sky.gshape, xshape=np.concatenate([sky.xshape, xshape]))
 
 
+def random_die(ntime: int, na: int, nchan: int, rng: np.random.Generator,
+               scale: float = 0.1) -> np.ndarray:
+    """A direction-independent 2x2 complex term per (timestep, antenna,
+    channel), [ntime][na][nchan][2][2]: the identity plus complex Gaussian
+    entries of standard deviation `scale` in real and imaginary parts."""
+    shp = (ntime, na, nchan, 2, 2)
+    return np.eye(2)[None, None, None] + scale * (rng.standard_normal(shp)
+                                                   + 1j * rng.standard_normal(shp))
+
+
+def stokes_per_time(sky: Sky, ntime: int, rng: np.random.Generator,
+                    frac: float = 0.1) -> np.ndarray:
+    """Brightness per timestep, [ntime][nsrc][4]: the sky's Stokes vector
+    times (1 + frac N(0, 1)) drawn per timestep, source and parameter."""
+    return sky.stokes[None] * (1.0 + frac * rng.standard_normal((ntime, sky.nsrc, 4)))
+
+
 def perturb(sky: Sky, rng: np.random.Generator, frac: float = PERTURB_FRAC) -> Sky:
     """Every scalar parameter multiplied by (1 + frac * N(0, 1))."""
     p = sky.params()

@@ -47,9 +47,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Published MI355X peaks (dense): FP32 vector 157.3 TFLOP/s, FP64 vector 78.6,
-# fp16 matrix 2.5 PFLOP/s.
-PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6, "f16_mfma": 2500.0}
+# MI355X peaks (dense).  Published: FP32 vector 157.3 TFLOP/s (with packed
+# dual FP32 instructions), FP64 vector 78.6, fp16 matrix 2.5 PFLOP/s.  This
+# build compiles without packed FP32 (v_pk_fma_f32 is disabled for all device
+# code), so its float32 vector ceiling is the one derived from the unit
+# counts and clock: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz =
+# 78.6 TFLOP/s.
+PEAK_TFLOPS = {"f32": 78.6, "f32_packed": 157.3, "f64": 78.6, "f16_mfma": 2500.0}
 
 # Algorithmic flops per source x visibility term (4 correlations), minimal
 # formulation: forward point 22, forward Gaussian 25 (+1 exp); adjoint point
@@ -75,8 +79,11 @@ def parse():
     ap.add_argument("--variant", type=int, default=None,
                     help="pin the float32-mixed kernel variant (library index) instead of "
                          "autotuning it")
-    ap.add_argument("--modes", default="grad_mixed,grad_res64,grad_fp64,chi2_mixed,chi2_fp64",
-                    help="comma list of timed evaluations (the first must be grad_mixed)")
+    ap.add_argument("--modes", default="grad_mixed,grad_res64,grad_fp64,chi2_mixed,chi2_fp64,"
+                                       "grad_terms,grad_disk,grad_streamed",
+                    help="comma list of timed evaluations (the first must be grad_mixed); "
+                         "grad_terms, grad_disk and grad_streamed time the per-call terms, the "
+                         "exponential-disk morphology and the out-of-core path")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="MiB copied device-to-device once before timing (a kernel of known "
                          "traffic for calibrating HBM counters)")
@@ -113,6 +120,8 @@ def cpu_baseline(sample_fn, seconds_target: float = 15.0):
 
     import oracle.rime_oracle as O
 
+    # the GPU machine gives one GPU a share of 16 host cores, whatever
+    # os.cpu_count() reports there
     ncores = min(os.cpu_count() or 1, 16)
     torch.set_num_threads(ncores)
     nc = 8
@@ -126,9 +135,20 @@ def cpu_baseline(sample_fn, seconds_target: float = 15.0):
         nc = min(full, int(nc * seconds_target / max(dt, 1e-3)) + 1)
     terms = obs.ntime * obs.nbl * obs.nchan * sky.nsrc
     return {"value": terms / dt, "unit": "terms/s", "cores": torch.get_num_threads(),
-            "kind": "oracle",
+            "host_cpus": os.cpu_count(), "cpu_model": cpu_model(), "kind": "oracle",
             "sample": f"{desc} restricted to 1 timestep x {nc} channels (all {obs.nbl} "
                       f"baselines, {sky.nsrc} sources): chi2 + autograd gradient, {dt:.1f} s"}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def problem_sample(name):
@@ -192,6 +212,8 @@ def roofline(flops, kernel_ms, variant, traffic):
     achieved = flops / (kernel_ms * 1e-3) / 1e12
     return {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS["f32"],
             "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS["f32"], "traffic": traffic,
+            "peak_packed": PEAK_TFLOPS["f32_packed"],
+            "frac_packed": achieved / PEAK_TFLOPS["f32_packed"],
             "kernel": "rime_main<float, %d, %d, %d, chi2+grad>" % tuple(variant),
             "kernel_ms": kernel_ms, "flops_per_launch": flops}
 
@@ -210,12 +232,18 @@ def rooflines(g, tp, tg, obs, sky, traffic):
     if not g["matrix_cores"]:
         return {"roofline": main}
     mc_ms = g["kernel_ms"] - g["main_ms"]
-    fl = mfma_flops(obs, sky.npsrc)
+    # the method's own work on the point sources (the algorithmic flops of
+    # the point terms), and what the matrix cores execute for it (three fp16
+    # products per hi/lo pair, full 32 x 32 tiles)
+    fl = alg_flops(tp, 0)
     ach = fl / (mc_ms * 1e-3) / 1e12
+    fl_exec = mfma_flops(obs, sky.npsrc)
     mc = {"bound": "mfma", "achieved": ach, "peak": PEAK_TFLOPS["f16_mfma"], "unit": "TFLOP/s",
           "frac": ach / PEAK_TFLOPS["f16_mfma"], "traffic": None,
           "kernel": "pme_phase + pme_forward + pme_mfrag + pme_adjoint (point sources)",
-          "kernel_ms": mc_ms, "flops_per_launch": fl}
+          "kernel_ms": mc_ms, "flops_per_launch": fl,
+          "executed_mfma_flops_per_launch": fl_exec,
+          "executed_tflops": fl_exec / (mc_ms * 1e-3) / 1e12}
     main["kernel"] += " (Gaussian sources)"
     if mc_ms > g["main_ms"]:
         return {"roofline": mc, "roofline_other": main}
@@ -389,6 +417,8 @@ def bench_single(args):
             "chi2_fp64": (R.MODE_CHI2, R.FP64, fp_steps, 1),
             "grad_res64": (R.MODE_CHI2_GRAD, R.MIXED_RES64, args.steps, 1)}
     for m in modes:
+        if m not in spec:
+            continue  # the timings of bench_extras
         log("timing", m)
         out[m] = run(*spec[m])
         log(m, out[m])
@@ -422,6 +452,7 @@ def bench_single(args):
         if "grad_fp64" in out:
             rec["res64"]["speedup_vs_fp64"] = (out["grad_fp64"]["ms_per_step"] /
                                                r64["ms_per_step"])
+    rec.update(bench_extras(args, R, plan, obs, sky, D32, W32, modes, g["ms_per_step"]))
     if "chi2_mixed" in out and "chi2_fp64" in out:
         rec["chi2_only"] = {
             "mixed_terms_per_s": out["chi2_mixed"]["terms_per_s"],
@@ -433,6 +464,76 @@ def bench_single(args):
         log("cpu baseline")
         rec["cpu_baseline"] = cpu_baseline(problem_sample(name))
     return rec
+
+
+def bench_extras(args, R, plan, obs, sky, D32, W32, modes, base_ms):
+    """Float32-mixed chi^2 + gradient of the same workload with the rows
+    beyond the static sky: per-call terms (a 2x2 G per timestep, antenna and
+    channel, and Stokes per timestep, both with their gradients), the
+    Gaussians replaced by exponential disks, and the out-of-core path with
+    the data in pinned host memory (PCIe-inclusive; never the headline)."""
+    import torch
+
+    from rime_synth import Sky, random_die, rngs, stokes_per_time
+    out = {}
+    terms = obs.ntime * obs.nbl * obs.nchan * sky.nsrc
+    dsky = R.DeviceSky.from_host(sky)
+    chi2 = torch.empty(1, dtype=torch.float64, device="cuda")
+    grad = torch.empty((sky.nsrc, 10), dtype=torch.float64, device="cuda")
+
+    def record(ms, **kw):
+        r = {"ms_per_step": ms, "terms_per_s": terms / (ms * 1e-3),
+             "vs_static_sky": ms / base_ms}
+        r.update(kw)
+        return r
+
+    if "grad_terms" in modes:
+        log("timing grad_terms")
+        rng = rngs(1501)[0]
+        die = torch.as_tensor(random_die(obs.ntime, obs.na, obs.nchan, rng), device="cuda")
+        st = torch.as_tensor(stokes_per_time(sky, obs.ntime, rng), device="cuda")
+        gdie, gst = torch.empty_like(die), torch.empty_like(st)
+        ws = torch.empty(R.rime_workspace_size_ex(plan, R.MODE_CHI2_GRAD, R.MIXED, sky.nsrc,
+                                                  die=True, grad_die=True, stokes_t=True,
+                                                  grad_stokes_t=True),
+                         dtype=torch.uint8, device="cuda")
+        ms = timed(lambda: R.rime_chi2_ex(plan, dsky, R.MIXED, D32, W32, chi2, grad, ws,
+                                          die=die, grad_die=gdie, stokes_t=st,
+                                          grad_stokes_t=gst), args.steps, 1)[0]
+        out["terms"] = record(ms, what="2x2 G per (timestep, antenna, channel) and Stokes per "
+                                       "(timestep, source), with d chi2/dG and d chi2/dStokes_t; "
+                                       "point sources on the per-baseline kernel")
+        log("grad_terms", out["terms"])
+        del ws, die, st, gdie, gst
+    if "grad_disk" in modes:
+        log("timing grad_disk")
+        disky = R.DeviceSky.from_host(Sky(lm=sky.lm, stokes=sky.stokes, alpha=sky.alpha,
+                                          xshape=sky.gshape))
+        ws = R.workspace(plan, R.MODE_CHI2_GRAD, R.MIXED, 1, sky.nsrc)
+        ms = timed(lambda: R.rime_chi2_grad(plan, disky, R.MIXED, D32, W32, chi2, grad, ws),
+                   args.steps, 1)[0]
+        out["disk"] = record(ms, what=f"the {sky.ngsrc} Gaussians replaced by exponential disks")
+        log("grad_disk", out["disk"])
+        del ws
+    if "grad_streamed" in modes:
+        log("timing grad_streamed")
+        chunk_t = max(1, obs.ntime // 10)
+        Dh, Wh = D32.cpu().pin_memory(), W32.cpu().pin_memory()
+        ws = torch.empty(R.rime_streamed_workspace_size(plan, R.MODE_CHI2_GRAD, R.MIXED,
+                                                        sky.nsrc, chunk_t),
+                         dtype=torch.uint8, device="cuda")
+        ms = timed(lambda: R.rime_chi2_streamed(plan, dsky, R.MIXED, Dh, Wh, chi2, grad,
+                                                chunk_t, ws), args.steps, 1)[0]
+        nbytes = Dh.numel() * Dh.element_size() + Wh.numel() * Wh.element_size()
+        out["streamed"] = record(ms, chunk_t=chunk_t, host_bytes=nbytes,
+                                 upload_GBps=nbytes / (ms * 1e-3) / 1e9,
+                                 what="data and weights in pinned host memory, uploaded in "
+                                      f"chunks of {chunk_t} timesteps overlapping the compute "
+                                      "(PCIe-inclusive)")
+        log("grad_streamed", out["streamed"])
+        del ws, Dh, Wh
+    torch.cuda.empty_cache()
+    return out
 
 
 # --------------------------------------------------------------------------- #
@@ -702,7 +803,7 @@ def write_traffic(pairs, out_path, workload="c2"):
     import re
     import statistics
 
-    pat = re.compile(r"rime_main<float, (\d+), (\d+), (\d+), 2>")
+    pat = re.compile(r"rime_main<float, (\d+), (\d+), (\d+), 2, false>")
 
     def read(path):
         rows = list(csv.DictReader(open(path)))
@@ -727,7 +828,7 @@ def write_traffic(pairs, out_path, workload="c2"):
             raise SystemExit("the two passes ran different variants")
         fscale, wscale = 1048576.0 / fc, 1048576.0 / wc
         fb, wb = fk * 1024 * fscale, wk * 1024 * wscale
-        entries.append({"kernel": "rime_main<float, %d, %d, %d, 2>" % tuple(var[:3]),
+        entries.append({"kernel": "rime_main<float, %d, %d, %d, 2, false>" % tuple(var[:3]),
                         "variant": var, "workload": workload, "fetch_kib_raw": fk,
                         "write_kib_raw": wk, "fetch_scale": fscale, "write_scale": wscale,
                         "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,

@@ -23,7 +23,8 @@ def write_counters(path, counter, copy_kib, kernel_kib, threads=1024, matrix_cor
     matrix-core kernel."""
     rows = [("__amd_rocclr_copyBuffer", 131072, copy_kib)]
     for v in kernel_kib:
-        rows.append((f"void rime::rime_main<float, {threads}, 2, 32, 2>(rime::KParams)", 6400, v))
+        rows.append((f"void rime::rime_main<float, {threads}, 2, 32, 2, false>(rime::KParams)",
+                     6400, v))
     if matrix_cores:
         rows.append(("rime::pme_forward(rime::KParams)", 25600, 123.0))
     with open(path, "w", newline="") as f:

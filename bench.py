@@ -342,6 +342,11 @@ def calib_copy(mib):
         del a, b
 
 
+MIXED_PRECISION = "float32 per term; FP64 phase argument, chi2 and gradient sums"
+MIXED_PRECISION_MC = (MIXED_PRECISION + "; point-source products on the matrix cores from "
+                      "fp16 hi + lo operands (hi*hi + hi*lo + lo*hi, about 22 bits)")
+
+
 def base_record(args, metric, value, ms, dtype, workload, extra_cfg):
     cfg = {"workload": workload}
     cfg.update(extra_cfg)
@@ -432,7 +437,8 @@ def bench_single(args):
         f"{args.config}: RIME chi2+grad, {obs.na} antennas ({obs.nbl} baselines), "
         f"{obs.ntime} timesteps, {obs.nchan} channels, {sky.npsrc} point + {sky.ngsrc} "
         f"Gaussian sources, beam",
-        {"terms_per_eval": terms, "precision": "mixed (FP64 phase and sums)"})
+        {"terms_per_eval": terms,
+         "precision": MIXED_PRECISION_MC if g["matrix_cores"] else MIXED_PRECISION})
     rec["evals_per_s"] = g["evals_per_s"]
     rec["step_ms"] = g["step_ms"]
     rec["variant"] = {"per_baseline": list(g["variant"]), "matrix_cores": g["matrix_cores"]}
@@ -620,10 +626,11 @@ def bench_batch(args):
         f"c3: {nset} batched proposals of {nsrc.min()}..{nsrc.max()} sources "
         f"(sum {nsrc.sum()}, 30 % Gaussian) over {obs.na} antennas ({obs.nbl} baselines), "
         f"{obs.ntime} timesteps, {obs.nchan} channels, beam; one hipGraph launch",
-        {"terms_per_eval": terms, "sets": nset, "precision": "mixed (FP64 phase and sums)"})
+        {"terms_per_eval": terms, "sets": nset})
     rec["evals_per_s"] = nset * 1e3 / ms
     rec["step_ms"] = step_stats(tuned_steps)
     mc = R.rime_variant_matrix_cores(R.MODE_CHI2_GRAD, R.MIXED, v_tuned)
+    rec["config"]["precision"] = MIXED_PRECISION_MC if mc else MIXED_PRECISION
     rec["roofline"] = roofline(alg_flops(tp, tg), kms, variant, None)
     if mc:
         # the matrix-core variant runs the per-set pipeline (per-baseline kernel
@@ -780,7 +787,7 @@ def bench_points(args):
         f"c4p: point subset of c4, {obs_free.na} antennas ({obs_free.nbl} baselines), "
         f"{obs_free.ntime} timesteps, {obs_free.nchan} channels, {pts.nsrc} point sources, "
         "beam-free; matrix-core variant against the per-baseline variants",
-        {"terms_per_eval": terms, "precision": "mixed (FP64 phase and sums)"})
+        {"terms_per_eval": terms, "precision": MIXED_PRECISION_MC})
     flops = mfma_flops(obs_free, pts.nsrc)
     achieved = flops / (best * 1e-3) / 1e12
     rec["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS["f16_mfma"],

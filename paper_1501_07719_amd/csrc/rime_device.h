@@ -1,6 +1,7 @@
 // Device-side numeric helpers shared by the kernels of librime.so: the
-// precision traits of the two arithmetic paths (float64, and float32 with the
-// gfx950 hardware transcendentals), the error-free phase argument, and float64
+// precision traits of the two arithmetic paths (float64, and float32 with an
+// accurate sine/cosine of turns and the gfx950 hardware exp2, reciprocal and
+// reciprocal square root), the error-free phase argument, and float64
 // compensated (two-sum) accumulation with wavefront and workgroup reductions.
 #pragma once
 

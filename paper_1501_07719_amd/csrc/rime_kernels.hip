@@ -17,8 +17,9 @@
 // accumulates d chi^2 / d theta_s without ever storing V.
 //
 // Precision: R = double (plain FP64) or R = float (mixed).  In the mixed path
-// the phase argument is formed in float64 and reduced to [-1/2, 1/2] turns
-// before the float32 hardware sine/cosine; the beam clip decision is taken in
+// the phase argument is formed error-free in float64 and reduced to
+// [-1/2, 1/2] turns before a float32 sine/cosine accurate to about one unit;
+// the beam clip decision is taken in
 // float64; the per-visibility source sums run in float32 within a source tile
 // and are folded into float64 after each tile; chi^2 and gradient sums are
 // float64.

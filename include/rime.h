@@ -107,7 +107,7 @@ typedef struct rime_obs_desc {
                              /* NULL for unity gains                              */
   double beam_k;             /* 65.0                                              */
   double beam_ref_freq;      /* 1.4e9 Hz                                          */
-  double beam_clip;          /* 1.0881 rad                                        */
+  double beam_clip;          /* 1.0881 rad; 0 < beam_clip <= 1.5 (RIME_ERR_ARG)   */
 } rime_obs_desc;
 
 /* One sky model (one sampler proposal).  Point sources first, then

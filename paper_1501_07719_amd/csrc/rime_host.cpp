@@ -1171,7 +1171,8 @@ rime_status rime_plan_create(const rime_obs_desc *obs, rime_plan **out) {
   if (!(obs->ref_freq > 0)) return RIME_ERR_ARG;
   if ((obs->ant1 == nullptr) != (obs->ant2 == nullptr)) return RIME_ERR_ARG;
   if (obs->beam != 0 && obs->beam != 1) return RIME_ERR_ARG;
-  if (obs->beam == 1 && !(obs->beam_ref_freq > 0 && obs->beam_k >= 0 && obs->beam_clip > 0))
+  if (obs->beam == 1 && !(obs->beam_ref_freq > 0 && obs->beam_k >= 0 && obs->beam_clip > 0 &&
+                          obs->beam_clip <= 1.5))
     return RIME_ERR_ARG;
   if (static_cast<int64_t>(obs->ntime) * obs->nbl * obs->nchan > (int64_t(1) << 40))
     return RIME_ERR_ARG;

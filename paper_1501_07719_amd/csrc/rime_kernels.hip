@@ -230,8 +230,10 @@ __device__ inline void stage_tile(const KParams &p, const SetDesc &sd, int t, in
     }
     if (ok) {
       const double4 g = p.src_geo[sd.src_off + s0 + s];
-      // tau = u l + v m + w (n - 1), metres (eq. k_term), error-free
-      const Pair tau = path_length(s_uvw[ai][0], s_uvw[ai][1], s_uvw[ai][2], g.x, g.y, g.z);
+      // tau = u l + v m + w (n - 1), metres (eq. k_term): error-free in
+      // float64, a plain float64 evaluation for the float32 path
+      const PhaseArg<sizeof(R) == 8> tau(s_uvw[ai][0], s_uvw[ai][1], s_uvw[ai][2], g.x, g.y,
+                                         g.z);
       double r2b = 0.0, dl = 0.0, dm = 0.0, rb = 0.0;
       if (p.beam) {
         dl = g.x - s_pnt[ai][0];
@@ -245,7 +247,7 @@ __device__ inline void stage_tile(const KParams &p, const SetDesc &sd, int t, in
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         if (c < ncv) {
-          const double r = phase_frac(tau, p.nu_c[c0 + c]);
+          const double r = tau.turns(p.nu_c[c0 + c]);
           R sn, cs;
           N::sincos_turns(r, &sn, &cs);
           R e = R(1);
@@ -253,18 +255,24 @@ __device__ inline void stage_tile(const KParams &p, const SetDesc &sd, int t, in
             // x_b = bs r, bs = beam_k nu / beam_ref_freq, clipped at beam_clip
             // (eq. e_term); the clip is decided on r^2 against the per-channel
             // threshold (beam_clip / bs)^2.
+            // d ln e / dl = -3 tan(x) dx/dl, dx/dl = bs (l - dl_p) / r
+            //             = -3 bs^2 (l - dl_p) tan(x)/x ; zero past the clip.
             const double bs = p.beam_k * p.bfr[c0 + c];
             const bool clipped = r2b >= p.clip_r2[c0 + c];
             const double xr = clipped ? p.beam_clip : bs * rb;
-            R sb, cb;
-            N::sincos_turns(xr * kInvTwoPi, &sb, &cb);
-            e = cb * cb * cb;
+            R tx = R(0);
+            if constexpr (sizeof(R) == 8) {
+              R sb, cb;
+              N::sincos_turns(xr * kInvTwoPi, &sb, &cb);
+              e = cb * cb * cb;
+              if (WITH_BETA && !clipped)
+                tx = xr > 1e-4 ? sb * N::rcp(cb * xr) : R(1) + xr * xr * R(1.0 / 3.0);
+            } else {
+              float txf = 0.0f;
+              beam_f32(static_cast<float>(xr), WITH_BETA, &e, &txf);
+              if (!clipped) tx = txf;
+            }
             if (WITH_BETA) {
-              // d ln e / dl = -3 tan(x) dx/dl, dx/dl = bs (l - dl_p) / r
-              //             = -3 bs^2 (l - dl_p) tan(x)/x ; zero past the clip.
-              R tx = R(0);
-              const R xf = static_cast<R>(xr);
-              if (!clipped) tx = xr > 1e-4 ? sb * N::rcp(cb * xf) : R(1) + xf * xf * R(1.0 / 3.0);
               const R k3 = static_cast<R>(-3.0 * bs * bs) * tx;
               bet[c].x = k3 * static_cast<R>(dl);
               bet[c].y = k3 * static_cast<R>(dm);

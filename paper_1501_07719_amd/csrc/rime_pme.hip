@@ -9,9 +9,9 @@
 // evaluates that product, and the corresponding part of the adjoint, on the
 // matrix cores:
 //   pme_phase    a_ps for every (t, nu, s, p), split into fp16 hi + lo parts
-//                (22 significant bits; the phase argument is reduced in
-//                float64 exactly as in the per-baseline kernels), and the
-//                beam's d ln e / d(l, m) factor;
+//                (22 significant bits; the phase argument is formed and
+//                reduced in float64 as in the float32 per-baseline kernels),
+//                and the beam's d ln e / d(l, m) factor;
 //   pme_scale    per (channel, Stokes parameter) power-of-two scale of the
 //                source-side operand;
 //   pme_forward  one Q block of 32 antennas against up to two P blocks per
@@ -114,8 +114,9 @@ __global__ __launch_bounds__(256) void pme_phase(const KParams p) {
   }
   const double4 g = p.src_geo[sd.src_off + s];
   const double *x = p.uvw + (static_cast<int64_t>(t) * p.na + a) * 3;
-  // tau = u l + v m + w (n - 1), metres (eq. k_term), error-free
-  const Pair tau = path_length(x[0], x[1], x[2], g.x, g.y, g.z);
+  // tau = u l + v m + w (n - 1), metres (eq. k_term), in float64 to well
+  // below the resolution of the float32 sine and cosine
+  const PhaseArg<false> tau(x[0], x[1], x[2], g.x, g.y, g.z);
   double r2b = 0.0, rb = 0.0;
   if (p.beam) {
     const double *q = p.pointing + (static_cast<int64_t>(t) * p.na + a) * 2;
@@ -123,7 +124,7 @@ __global__ __launch_bounds__(256) void pme_phase(const KParams p) {
     rb = sqrt(r2b);
   }
   for (int c = cb; c < ce; ++c) {
-    const double r = phase_frac(tau, p.nu_c[c]);
+    const double r = tau.turns(p.nu_c[c]);
     float sn, cs;
     N::sincos_turns(r, &sn, &cs);
     float e = 1.0f, k3 = 0.0f;
@@ -133,15 +134,10 @@ __global__ __launch_bounds__(256) void pme_phase(const KParams p) {
       const double bs = p.beam_k * p.bfr[c];
       const bool clipped = r2b >= p.clip_r2[c];
       const double xd = clipped ? p.beam_clip : bs * rb;
-      const float xr = static_cast<float>(xd);
-      float sb, cb;
-      N::sincos_turns(xd * kInvTwoPi, &sb, &cb);
-      e = cb * cb * cb;
+      float tx = 0.0f;
+      beam_f32(static_cast<float>(xd), k3p != nullptr, &e, &tx);
       // d ln e / dl = -3 bs^2 (l - dl_p) tan(x)/x; zero past the clip
-      if (!clipped) {
-        const float tx = xr > 1e-4f ? sb * N::rcp(cb * xr) : 1.0f + xr * xr / 3.0f;
-        k3 = static_cast<float>(-3.0 * bs * bs) * tx;
-      }
+      if (!clipped) k3 = static_cast<float>(-3.0 * bs * bs) * tx;
     }
     _Float16 rh, rl, ih, il;
     split_h(e * cs, rh, rl);

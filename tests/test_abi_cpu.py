@@ -102,6 +102,10 @@ def test_plan_create_rejects_bad_arguments(lib):
     d = mk()
     d.beam = 2
     assert lib.rime_plan_create(ctypes.byref(d), ctypes.byref(h)) == 1
+    for clip in (0.0, 1.6):  # beam_clip must lie in (0, 1.5]
+        d = mk()
+        d.beam, d.beam_k, d.beam_ref_freq, d.beam_clip = 1, 65.0, 1.4e9, clip
+        assert lib.rime_plan_create(ctypes.byref(d), ctypes.byref(h)) == 1
     f2 = np.array([1e9, -1.0, 1.2e9])
     d = mk()
     d.freq = f2.ctypes.data_as(ctypes.POINTER(ctypes.c_double))

@@ -218,7 +218,7 @@ def roofline(flops, kernel_ms, variant, traffic):
             "kernel_ms": kernel_ms, "flops_per_launch": flops}
 
 
-def rooflines(g, tp, tg, obs, sky, traffic):
+def rooflines(g, tp, tg, obs, sky, traffic, npoint=None):
     """Roofline objects of one chi^2 + gradient call.  Without the matrix
     cores the per-baseline kernel does all the work: VALU-bound, algorithmic
     flops of all terms over its time.  With them it does the Gaussian sources
@@ -237,7 +237,7 @@ def rooflines(g, tp, tg, obs, sky, traffic):
     # products per hi/lo pair, full 32 x 32 tiles)
     fl = alg_flops(tp, 0)
     ach = fl / (mc_ms * 1e-3) / 1e12
-    fl_exec = mfma_flops(obs, sky.npsrc)
+    fl_exec = mfma_flops(obs, sky.npsrc if npoint is None else npoint)
     mc = {"bound": "mfma", "achieved": ach, "peak": PEAK_TFLOPS["f16_mfma"], "unit": "TFLOP/s",
           "frac": ach / PEAK_TFLOPS["f16_mfma"], "traffic": None,
           "kernel": "pme_phase + pme_forward + pme_mfrag + pme_adjoint (point sources)",
@@ -310,7 +310,8 @@ def mfma_flops(obs, npsrc):
     the adjoint 4 x 6 x 4 per (P block, q block); 32x32x16 = 32768 flops."""
     nblk = (obs.na + 31) // 32
     pairs = {(min(a // 32, b // 32), max(a // 32, b // 32)) for a, b in zip(obs.ant1, obs.ant2)}
-    nch = (npsrc + 31) // 32
+    # npsrc: one count, or the counts of the sets of a batch (one pipeline each)
+    nch = sum((int(n) + 31) // 32 for n in np.atleast_1d(npsrc))
     per_slice = 96 * nch * (len(pairs) + nblk * nblk)
     return per_slice * obs.ntime * obs.nchan * 32768
 
@@ -621,7 +622,25 @@ def bench_batch(args):
             R.rime_chi2_grad(plan, skies[i], R.MIXED, D32, W32, chi2[i:i + 1], grads[i], wsl)
     res["loop_tuned"] = timed(loop, args.steps, 1)[0]
     log("per-set loop", res["loop_tuned"])
-    del wsl
+    # kernel times per set from the same loop, with HIP events around all
+    # compute kernels of each call and around its per-baseline kernel: the
+    # per-set pipelines of the batched call run these same kernels
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(nset)]
+    for e4 in ev:
+        for e in e4:
+            e.record()
+    torch.cuda.synchronize()
+    for i in range(nset):
+        plan.set_timing_events(ev[i][0], ev[i][1])
+        plan.set_main_events(ev[i][2], ev[i][3])
+        R.rime_chi2_grad(plan, skies[i], R.MIXED, D32, W32, chi2[i:i + 1], grads[i], wsl)
+    plan.set_timing_events(None, None)
+    plan.set_main_events(None, None)
+    torch.cuda.synchronize()
+    set_kernel_ms = sum(e4[0].elapsed_time(e4[1]) for e4 in ev)
+    set_main_ms = sum(e4[2].elapsed_time(e4[3]) for e4 in ev)
+    log("per-set kernels", set_kernel_ms, "per-baseline kernels", set_main_ms)
+    del wsl, ev
     if not args.no_fp64:
         call, ws = batched(R.FP64, True)
         res["graph_fp64"] = timed(call, max(1, args.steps // 2), 1)[0]
@@ -640,13 +659,17 @@ def bench_batch(args):
     rec["step_ms"] = step_stats(tuned_steps)
     mc = R.rime_variant_matrix_cores(R.MODE_CHI2_GRAD, R.MIXED, v_tuned)
     rec["config"]["precision"] = MIXED_PRECISION_MC if mc else MIXED_PRECISION
-    rec["roofline"] = roofline(alg_flops(tp, tg), kms, variant, None)
     if mc:
-        # the matrix-core variant runs the per-set pipeline (per-baseline kernel
-        # for the Gaussian sources, matrix cores for the points): the figure is
-        # the algorithmic rate of the whole batched call
-        rec["roofline"]["kernel"] = ("all kernels of the batched call (per-set pipeline, "
-                                     "point sources on the matrix cores)")
+        # the matrix-core variant runs the per-set pipeline: the per-baseline
+        # kernel for the Gaussian sources, the matrix cores for the points;
+        # their times are the sums over the sets' calls in the per-set loop
+        g = {"matrix_cores": True, "main_ms": set_main_ms, "kernel_ms": set_kernel_ms,
+             "variant": variant}
+        rec.update(rooflines(g, tp, tg, obs, None, None, npoint=npsrc))
+        for k in ("roofline", "roofline_other"):
+            rec[k]["kernel"] += ", summed over the 256 sets (per-set calls)"
+    else:
+        rec["roofline"] = roofline(alg_flops(tp, tg), kms, variant, None)
     rec["batched"] = {
         "graph_tuned_ms": ms, "graph_default_ms": res["graph_default"],
         "stream_tuned_ms": res["stream_tuned"], "per_set_loop_ms": res["loop_tuned"],

@@ -335,12 +335,17 @@ def upload_data(R, plan, truth, noise, weight):
 def calib_copy(mib):
     import torch
     if mib:
-        # a plain device copy of known size: mib MiB read + written
+        # a plain device copy of known size: mib MiB read + written; then a
+        # sum over the same mib MiB (read only), a second access mix for the
+        # FETCH_SIZE factor
         a = torch.ones(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
         b.copy_(a)
         torch.cuda.synchronize()
-        del a, b
+        del b
+        a.sum()
+        torch.cuda.synchronize()
+        del a
 
 
 MIXED_PRECISION = "float32 per term; FP64 phase argument, chi2 and gradient sums"
@@ -846,7 +851,7 @@ def write_traffic(pairs, out_path, workload="c2"):
 
     def read(path):
         rows = list(csv.DictReader(open(path)))
-        kern, copy, names = [], [], set()
+        kern, copy, red, names = [], [], [], set()
         mc = any("pme_" in r["Kernel_Name"] for r in rows)
         for r in rows:
             m = pat.search(r["Kernel_Name"])
@@ -855,23 +860,30 @@ def write_traffic(pairs, out_path, workload="c2"):
                 names.add(m.groups())
             elif "copyBuffer" in r["Kernel_Name"] and int(r["Grid_Size"]) == 131072:
                 copy.append(float(r["Counter_Value"]))
+            elif "reduce_kernel" in r["Kernel_Name"]:
+                red.append(float(r["Counter_Value"]))
         if len(names) != 1 or not copy:
             raise SystemExit(f"{path}: expected one chi2+grad kernel variant and the 1 GiB copy")
-        return statistics.mean(kern), copy[0], [int(x) for x in names.pop()] + [int(mc)]
+        return (statistics.mean(kern), copy[0], max(red) if red else None,
+                [int(x) for x in names.pop()] + [int(mc)])
 
     entries = []
     for fetch_csv, write_csv in pairs:
-        fk, fc, var = read(fetch_csv)
-        wk, wc, var_w = read(write_csv)
+        fk, fc, fr, var = read(fetch_csv)
+        wk, wc, _, var_w = read(write_csv)
         if var != var_w:
             raise SystemExit("the two passes ran different variants")
         fscale, wscale = 1048576.0 / fc, 1048576.0 / wc
         fb, wb = fk * 1024 * fscale, wk * 1024 * wscale
-        entries.append({"kernel": "rime_main<float, %d, %d, %d, 2, false>" % tuple(var[:3]),
-                        "variant": var, "workload": workload, "fetch_kib_raw": fk,
-                        "write_kib_raw": wk, "fetch_scale": fscale, "write_scale": wscale,
-                        "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
-                        "grad_mixed_bytes_per_launch": fb + wb})
+        e = {"kernel": "rime_main<float, %d, %d, %d, 2, false>" % tuple(var[:3]),
+             "variant": var, "workload": workload, "fetch_kib_raw": fk,
+             "write_kib_raw": wk, "fetch_scale": fscale, "write_scale": wscale,
+             "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
+             "grad_mixed_bytes_per_launch": fb + wb}
+        if fr:
+            # the read-only sum of the same 1 GiB: its factor beside the copy's
+            e["fetch_scale_read_only"] = 1048576.0 / fr
+        entries.append(e)
     digest = kernel_source_digest()
     try:
         with open(out_path) as f:

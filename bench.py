@@ -825,13 +825,18 @@ def bench_points(args):
         f"{obs_free.ntime} timesteps, {obs_free.nchan} channels, {pts.nsrc} point sources, "
         "beam-free; matrix-core variant against the per-baseline variants",
         {"terms_per_eval": terms, "precision": MIXED_PRECISION_MC})
-    flops = mfma_flops(obs_free, pts.nsrc)
+    # the method's flops on the point terms, and beside them what the matrix
+    # cores execute for them (as in the c2 line's roofline_other)
+    flops = alg_flops(terms, 0)
+    fl_exec = mfma_flops(obs_free, pts.nsrc)
     achieved = flops / (best * 1e-3) / 1e12
     rec["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS["f16_mfma"],
                        "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS["f16_mfma"],
                        "traffic": None,
                        "kernel": "all kernels of the call (point sources on the matrix cores)",
-                       "kernel_ms": best, "flops_per_launch": flops}
+                       "kernel_ms": best, "flops_per_launch": flops,
+                       "executed_mfma_flops_per_launch": fl_exec,
+                       "executed_tflops": fl_exec / (best * 1e-3) / 1e12}
     rec["comparison"] = cmp
     return rec
 

@@ -945,15 +945,16 @@ int default_variant(const rime_plan *plan, int mode, int prec) {
   // 2 -> 256 threads x 4 channels);
   // float32-mixed 4 / 5 -> 1024 / 256 threads with the point sources on the
   // matrix cores (measured faster from 64 antennas up); the 1024-thread one
-  // only for the gradient of mid-sized arrays (2016 baselines: 22.7 vs 23.0 ms;
-  // 19306 baselines: 218.5 vs 212.7 ms); small arrays take 1 in both
+  // for the gradient from 1024 baselines up (2016 baselines: whole call
+  // 22.7 ms against 23.0 ms; 19306 baselines: per-baseline kernel 123.7 ms
+  // against 150.6 ms); small arrays take 1 in both
   // precisions (7 antennas, 10 timesteps, 16 channels, 20 sources, one graph
   // launch of chi2 + gradient: FP64 30 us against 34 us for 0, float32-mixed
   // 26 us against 28 us for 0 and 75 us for 5).  The float64-residual mode
   // takes the float64 forward 1 and the float32-mixed gradient's adjoint.
   if (prec == RIME_FP64 || plan->nbl <= 96) return 1;
   if (prec == kRes64 && mode != RIME_MODE_CHI2_GRAD) return 1;
-  if (mode == RIME_MODE_CHI2_GRAD && plan->nbl >= 1024 && plan->nbl < 8192) return 4;
+  if (mode == RIME_MODE_CHI2_GRAD && plan->nbl >= 1024) return 4;
   return 5;
 }
 

@@ -178,9 +178,7 @@ rime_status rime_chi2_grad(const rime_plan *plan, const rime_sky *sky, rime_prec
  *  stokes_t      DEVICE [ntime][nsrc][4] Stokes I, Q, U, V per timestep (Table
  *                rime_input gives the brightness as an ntime x nsrc array);
  *                replaces the sky's stokes; the spectral index stays per
- *                source.  Point sources then stay on the per-baseline kernel
- *                (the matrix-core engine takes the plan's variant's
- *                per-baseline counterpart).
+ *                source.
  *  grad_stokes_t DEVICE [ntime][nsrc][4]: d chi^2 / d stokes_t (gradient
  *                calls only; needs stokes_t); the Stokes columns of `grad`
  *                are then its sum over time. */

@@ -829,20 +829,6 @@ rime_status enqueue(const rime_plan *plan, const Call &c, int vidx, void *ws, si
 
 bool valid_prec(int prec) { return prec == RIME_FP64 || prec == RIME_MIXED || prec == kRes64; }
 
-// The variant that runs a call: the plan's, except that brightness per
-// timestep keeps the point sources on the per-baseline kernel (the
-// matrix-core engine's operands are per source, not per timestep).
-int call_variant(const rime_plan *plan, int mode, int prec, bool stokes_t) {
-  const int vi = plan->variant[mode][prec];
-  const Variant *v = variant_info(mode, prec, vi);
-  if (!stokes_t || !v || !v->pme) return vi;
-  for (int i = 0; i < variant_count(mode, prec); ++i) {
-    const Variant *u = variant_info(mode, prec, i);
-    if (!u->pme && u->threads == v->threads && u->nc == v->nc && u->ns == v->ns) return i;
-  }
-  return vi;
-}
-
 rime_status check_terms(const rime_terms *terms, int mode) {
   if (!terms) return RIME_OK;
   if (terms->grad_die && !terms->die) return RIME_ERR_ARG;
@@ -883,7 +869,7 @@ rime_status single(const rime_plan *plan, int mode, rime_precision prec, const r
   int dev = 0;
   RIME_HIP(hipGetDevice(&dev));
   if (dev != plan->device) return RIME_ERR_ARG;
-  return enqueue(plan, c, call_variant(plan, mode, prec, c.stokes_t != nullptr), ws, ws_bytes,
+  return enqueue(plan, c, plan->variant[mode][prec], ws, ws_bytes,
                  static_cast<hipStream_t>(stream));
 }
 

@@ -1134,12 +1134,23 @@ __global__ __launch_bounds__(256) void stokes_t_grad(const KParams p) {
   const int64_t sk = idx % (static_cast<int64_t>(nsrc) * 4);
   const int t = static_cast<int>(idx / (static_cast<int64_t>(nsrc) * 4));
   const int tc = t / p.tchunk, tt = t - tc * p.tchunk;
+  const int s = static_cast<int>(sk / 4), k = static_cast<int>(sk % 4);
   Comp acc;
-  for (int chb = 0; chb < p.nchb; ++chb)
-    for (int tile = 0; tile < p.ntile; ++tile) {
-      const int64_t item = tile + static_cast<int64_t>(p.ntile) * (chb + p.nchb * tc);
-      acc.add(p.gst_part[(item * p.tchunk + tt) * nsrc * 4 + sk]);
-    }
+  if (p.pme_adj && s < p.one.npsrc) {
+    // point sources with the matrix-core adjoint: its per-item partials of
+    // timestep t, columns 2..5 (the Stokes sums times the spectral factor)
+    const int sr = s / kPmeSR, sl = s - sr * kPmeSR;
+    const int64_t nit = static_cast<int64_t>(p.pme_ncg) * p.nblk * p.pme_nqr;
+    const float *src =
+        p.pgrad + (static_cast<int64_t>(sr) * p.ntime + t) * nit * (kPmeSR * 7) + sl * 7 + 2 + k;
+    for (int64_t i = 0; i < nit; ++i) acc.add(static_cast<double>(src[i * (kPmeSR * 7)]));
+  } else {
+    for (int chb = 0; chb < p.nchb; ++chb)
+      for (int tile = 0; tile < p.ntile; ++tile) {
+        const int64_t item = tile + static_cast<int64_t>(p.ntile) * (chb + p.nchb * tc);
+        acc.add(p.gst_part[(item * p.tchunk + tt) * nsrc * 4 + sk]);
+      }
+  }
   p.grad_stokes_t[idx] = 2.0 * (acc.s + acc.c);
 }
 

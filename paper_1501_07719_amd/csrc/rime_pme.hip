@@ -148,22 +148,42 @@ __global__ __launch_bounds__(256) void pme_phase(const KParams p) {
   }
 }
 
+// St'_k (k = I, Q, U, V) of source s of the set at channel c and timestep t:
+// the spectrally scaled Stokes vector, or, with brightness per timestep (ST),
+// the spectral factor times that timestep's Stokes vector (rounded as in the
+// per-baseline kernels).  The kernels that call it per chunk take ST as a
+// template parameter, so that the plain calls do not carry its registers.
+template <bool ST>
+__device__ inline float4 pme_stokes(const KParams &p, int s, int c, int t) {
+  const int64_t gs = p.one.src_off + s;
+  if (ST) {
+    const int nsrc = p.one.npsrc + p.one.ngsrc + p.one.nxsrc;
+    const double *q = p.stokes_t + (static_cast<int64_t>(t) * nsrc + s) * 4;
+    const double f = static_cast<double>(static_cast<const float *>(p.src_sf)[gs * p.nchan + c]);
+    return make_float4(static_cast<float>(f * q[0]), static_cast<float>(f * q[1]),
+                       static_cast<float>(f * q[2]), static_cast<float>(f * q[3]));
+  }
+  return static_cast<const float4 *>(p.src_st)[gs * p.nchan + c];
+}
+
 // ---------------------------------------------------------------------------
-// Forward scale: exponent e of max_s |St'_k,s(nu)|, one workgroup per channel.
+// Forward scale: exponent e of max_s |St'_k,s(nu)| (over the timesteps too with
+// brightness per timestep), one workgroup per channel.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void pme_scale(const KParams p) {
   __shared__ float s_m[4][256 / kWave];
   const int c = blockIdx.x;
   const SetDesc sd = p.one;
-  const float4 *st = static_cast<const float4 *>(p.src_st);
+  const int nt = p.stokes_t ? p.ntime : 1;
   float m[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-  for (int s = threadIdx.x; s < sd.npsrc; s += 256) {
-    const float4 v = st[(sd.src_off + s) * p.nchan + c];
-    m[0] = fmaxf(m[0], fabsf(v.x));
-    m[1] = fmaxf(m[1], fabsf(v.y));
-    m[2] = fmaxf(m[2], fabsf(v.z));
-    m[3] = fmaxf(m[3], fabsf(v.w));
-  }
+  for (int t = 0; t < nt; ++t)
+    for (int s = threadIdx.x; s < sd.npsrc; s += 256) {
+      const float4 v = p.stokes_t ? pme_stokes<true>(p, s, c, t) : pme_stokes<false>(p, s, c, t);
+      m[0] = fmaxf(m[0], fabsf(v.x));
+      m[1] = fmaxf(m[1], fabsf(v.y));
+      m[2] = fmaxf(m[2], fabsf(v.z));
+      m[3] = fmaxf(m[3], fabsf(v.w));
+    }
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
 #pragma unroll
@@ -191,9 +211,11 @@ struct FwdRegs {
   float4 st;
 };
 
-// Global operands of one chunk for thread (source tid / 8, antennas 4 (tid % 8) ..).
+// Global operands of one chunk for thread (source tid / 8, antennas 4 (tid % 8) ..)
+// at channel c and timestep t.
+template <bool ST>
 __device__ inline FwdRegs fwd_load(const KParams &p, const uint32_t *hi0, const uint32_t *lo0,
-                                   int c, int s0, int cnt, int Q, int Pa, int Pb) {
+                                   int c, int t, int s0, int cnt, int Q, int Pa, int Pb) {
   const int tid = threadIdx.x;
   const int s = tid >> 3, ag = (tid & 7) * 4;
   FwdRegs r;
@@ -218,11 +240,12 @@ __device__ inline FwdRegs fwd_load(const KParams &p, const uint32_t *hi0, const 
       r.pbh = *reinterpret_cast<const uint4 *>(hi0 + row + Pb * kPmeBlk + ag);
       r.pbl = *reinterpret_cast<const uint4 *>(lo0 + row + Pb * kPmeBlk + ag);
     }
-    r.st = static_cast<const float4 *>(p.src_st)[(p.one.src_off + s0 + s) * p.nchan + c];
+    r.st = pme_stokes<ST>(p, s0 + s, c, t);
   }
   return r;
 }
 
+template <bool ST>
 __global__ __launch_bounds__(256, 2) void pme_forward(const KParams p) {
   const int nitems = p.pme_nt * p.nchan * p.ngroup;
   const int item = xcd_item(nitems);
@@ -265,8 +288,8 @@ __global__ __launch_bounds__(256, 2) void pme_forward(const KParams p) {
 
   const int nchunk = (sd.npsrc + kPmeCh - 1) / kPmeCh;
   for (int ch = 0; ch < nchunk; ++ch) {
-    const FwdRegs cur =
-        fwd_load(p, hi0, lo0, c, ch * kPmeCh, min(kPmeCh, sd.npsrc - ch * kPmeCh), Q, Pa, Pb);
+    const FwdRegs cur = fwd_load<ST>(p, hi0, lo0, c, p.pme_t0 + tt, ch * kPmeCh,
+                                 min(kPmeCh, sd.npsrc - ch * kPmeCh), Q, Pa, Pb);
     __syncthreads();  // the previous chunk's fragments are consumed
     {
       const int s = tid >> 3, ag = (tid & 7) * 4;
@@ -489,6 +512,7 @@ __global__ __launch_bounds__(256) void pme_mfrag(const KParams p) {
   }
 }
 
+template <bool ST>
 __global__ __launch_bounds__(256, 2) void pme_adjoint(const KParams p) {
   const int nP = p.nblk, nQR = p.pme_nqr, nCG = p.pme_ncg, nT = p.pme_nt;
   const int nitems = p.pme_nsr * nT * nCG * nP * nQR;
@@ -575,7 +599,6 @@ __global__ __launch_bounds__(256, 2) void pme_adjoint(const KParams p) {
     const uint32_t *lo0 = p.ph_lo + (static_cast<int64_t>(tt) * p.nchan + c) * plane;
     const float *k30 =
         p.beam ? p.ph_k3 + (static_cast<int64_t>(tt) * p.nchan + c) * plane : nullptr;
-    const float4 *stk = static_cast<const float4 *>(p.src_st);
     const float tpnc = static_cast<float>(2.0 * kPi * p.nu_c[c]);
     const float lnfr = static_cast<float>(p.lnfr[c]);
 
@@ -616,7 +639,7 @@ __global__ __launch_bounds__(256, 2) void pme_adjoint(const KParams p) {
           float f = 0.0f;
           if (s < cnt) {
             const int64_t gs = sd.src_off + s0 + s;
-            sv = stk[gs * p.nchan + c];
+            sv = pme_stokes<ST>(p, s0 + s, c, t);
             lo = p.src_lon[gs];
             f = p.src_f[gs * p.nchan + c];
           }
@@ -816,7 +839,12 @@ hipError_t launch_pme(const KParams &p, hipStream_t stream) {
   if (e != hipSuccess) return e;
   const int64_t nitems = static_cast<int64_t>(p.pme_nt) * p.nchan * p.ngroup;
   const int64_t grid = 8 * ((nitems + 7) / 8);
-  hipLaunchKernelGGL(pme_forward, dim3(static_cast<unsigned>(grid)), dim3(256), 0, stream, p);
+  if (p.stokes_t)
+    hipLaunchKernelGGL(pme_forward<true>, dim3(static_cast<unsigned>(grid)), dim3(256), 0, stream,
+                       p);
+  else
+    hipLaunchKernelGGL(pme_forward<false>, dim3(static_cast<unsigned>(grid)), dim3(256), 0,
+                       stream, p);
   return hipGetLastError();
 }
 
@@ -830,7 +858,12 @@ hipError_t launch_pme_adjoint(const KParams &p, bool phase, hipStream_t stream) 
   const int64_t nitems =
       static_cast<int64_t>(p.pme_nsr) * p.pme_nt * p.pme_ncg * p.nblk * p.pme_nqr;
   const int64_t grid = 8 * ((nitems + 7) / 8);
-  hipLaunchKernelGGL(pme_adjoint, dim3(static_cast<unsigned>(grid)), dim3(256), 0, stream, p);
+  if (p.stokes_t)
+    hipLaunchKernelGGL(pme_adjoint<true>, dim3(static_cast<unsigned>(grid)), dim3(256), 0, stream,
+                       p);
+  else
+    hipLaunchKernelGGL(pme_adjoint<false>, dim3(static_cast<unsigned>(grid)), dim3(256), 0,
+                       stream, p);
   return hipGetLastError();
 }
 

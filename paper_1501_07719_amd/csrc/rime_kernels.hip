@@ -501,13 +501,14 @@ __device__ inline SrcTile src_tile(const SetDesc &sd, int k, int ns, int npt, in
 // TERMS: the instantiation that also applies per-call terms (a 2x2 G per
 // antenna, brightness per timestep); kept apart so that the plain calls do
 // not carry their registers.
-// The float64 256-thread kernels with two channels per thread ask for three
-// workgroups per CU (168 VGPRs, a few dozen spilled outside the source loops):
-// their forward modes fit that in LDS and were VALU-idle a quarter of the
+// The float64 256-thread forward kernels with two channels per thread ask
+// for three workgroups per CU (168 VGPRs, a few dozen spilled outside the
+// source loops): they fit that in LDS and were VALU-idle a quarter of the
 // time at two (c2: float64-residual forward 29.5 -> 27.5 ms, FP64 chi^2
 // 28.5 -> 27.6 ms).  The gradient mode's LDS allows two workgroups anyway.
 template <class R, int NBT, int NC, int NS, int MODE, bool TERMS>
-__global__ __launch_bounds__(NBT, (NBT == 256 && NC == 2 && sizeof(R) == 8) ? 3 : 1)
+__global__ __launch_bounds__(NBT, (NBT == 256 && NC == 2 && sizeof(R) == 8 &&
+                                   MODE != MODE_GRAD) ? 3 : 1)
 void rime_main(const KParams p) {
   using L = Layout<R, NBT, NC, NS, MODE>;
   using N = Num<R>;

@@ -111,7 +111,12 @@ typedef struct rime_obs_desc {
 } rime_obs_desc;
 
 /* One sky model (one sampler proposal).  Point sources first, then
- * Gaussians, then exponential disks.  All arrays are DEVICE float64 arrays. */
+ * Gaussians, then exponential disks.  All arrays are DEVICE float64 arrays.
+ * Single-sky calls (rime_predict, rime_chi2, rime_chi2_grad, their _ex and
+ * _noalloc forms, rime_chi2_streamed) accept a sky without sources: all
+ * counts 0, the arrays may be NULL; the source sum of eq. 1 is then empty,
+ * V = 0, chi^2 = sum w |D|^2, and `grad` (no rows) may be NULL.  Batches and
+ * rime_autotune need at least one source per sky (RIME_ERR_ARG). */
 typedef struct rime_sky {
   int32_t npsrc;             /* point sources, >= 0                               */
   int32_t ngsrc;             /* Gaussian sources, >= 0                            */
@@ -142,7 +147,9 @@ rime_status rime_plan_create(const rime_obs_desc *obs, rime_plan **out);
 void rime_plan_destroy(rime_plan *plan);
 
 /* Bytes of device workspace that one call of `mode` needs for `nset` sets with
- * `total_src` sources in all (nset = 1 for the single-sky calls). */
+ * `total_src` sources in all (nset = 1 for the single-sky calls, where
+ * total_src may be 0; otherwise total_src >= nset).  0 for invalid
+ * arguments. */
 size_t rime_workspace_size(const rime_plan *plan, rime_mode mode, rime_precision prec,
                            int32_t nset, int64_t total_src);
 
@@ -193,8 +200,11 @@ typedef struct rime_terms {
  * with nset 1).  0 for invalid arguments. */
 size_t rime_workspace_size_ex(const rime_plan *plan, rime_mode mode, rime_precision prec,
                               int64_t nsrc, const rime_terms *terms);
-/* rime_predict and rime_chi2 / rime_chi2_grad (grad == NULL: chi^2 only)
- * with per-call terms; terms == NULL gives the plain calls.  Single sky. */
+/* rime_predict and rime_chi2 / rime_chi2_grad with per-call terms; terms ==
+ * NULL gives the plain calls.  Single sky.  rime_chi2_ex computes chi^2 only
+ * when grad is NULL and the terms ask for no gradient (grad_die and
+ * grad_stokes_t NULL); otherwise chi^2 and gradients (grad may then be NULL
+ * only for a sky without sources). */
 rime_status rime_predict_ex(const rime_plan *plan, const rime_sky *sky, const rime_terms *terms,
                             rime_precision prec, void *vis, void *ws, size_t ws_bytes,
                             void *stream);

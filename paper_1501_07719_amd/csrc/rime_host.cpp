@@ -343,7 +343,7 @@ bool pme_active(const Variant &v, int prec, int nset) {
 // Words of the domain-flag header at the start of every workspace: a count,
 // then one flag per (set, preparation workgroup of 256 sources).
 int64_t dom_words(int nset, int64_t total_src) {
-  return 1 + static_cast<int64_t>(nset) * ((total_src + 255) / 256);
+  return 1 + static_cast<int64_t>(nset) * std::max<int64_t>(1, (total_src + 255) / 256);
 }
 
 // fwd_sums = false: the point-source sums of the matrix-core forward are not
@@ -380,7 +380,8 @@ WsLayout ws_layout(const rime_plan *plan, int mode, int prec, const Geometry &g,
   if (mode == RIME_MODE_CHI2_GRAD && prec == RIME_FP64 && v.nc == 2 && v.threads >= 256)
     off += align_up(static_cast<size_t>(nset) * g.items_per_set * v.threads * v.nc * 4 *
                     sizeof(double2));
-  if (pme_active(v, prec, nset)) {
+  // (a sky without sources leaves the engine off)
+  if (pme_active(v, prec, nset) && total_src > 0) {
     const bool adj = mode == RIME_MODE_CHI2_GRAD && plan->pme_adj_ok;
     const bool k3 = adj && plan->beam;
     // per timestep: phase planes (total_src bounds the point count) and, for
@@ -535,10 +536,13 @@ int64_t sky_nsrc(const rime_sky *sky) {
   return static_cast<int64_t>(sky->npsrc) + sky->ngsrc + sky->nxsrc;
 }
 
-rime_status check_sky(const rime_sky *sky) {
+// allow_empty: a sky without sources (single-sky calls: V = 0), whose arrays
+// may then be NULL.
+rime_status check_sky(const rime_sky *sky, bool allow_empty = false) {
   if (!sky) return RIME_ERR_ARG;
   if (sky->npsrc < 0 || sky->ngsrc < 0 || sky->nxsrc < 0) return RIME_ERR_ARG;
-  if (sky_nsrc(sky) < 1 || sky_nsrc(sky) > (1 << 24)) return RIME_ERR_ARG;
+  if (sky_nsrc(sky) > (1 << 24)) return RIME_ERR_ARG;
+  if (sky_nsrc(sky) == 0) return allow_empty ? RIME_OK : RIME_ERR_ARG;
   if (!sky->lm || !sky->stokes || !sky->alpha) return RIME_ERR_ARG;
   if (sky->ngsrc > 0 && !sky->gshape) return RIME_ERR_ARG;
   if (sky->nxsrc > 0 && !sky->xshape) return RIME_ERR_ARG;
@@ -641,7 +645,7 @@ KParams make_params(const rime_plan *plan, const Call &c, const Variant &v, cons
   } else {
     p.dom = reinterpret_cast<int32_t *>(w + L.dom);
     p.dom_off = 0;
-    p.dom_count = c.nset * ((c.max_nsrc + 255) / 256);
+    p.dom_count = c.nset * std::max(1, (c.max_nsrc + 255) / 256);
   }
   p.data = c.data;
   p.weight = c.weight;
@@ -843,12 +847,13 @@ rime_status single(const rime_plan *plan, int mode, rime_precision prec, const r
   if (!plan) return RIME_ERR_ARG;
   if (!valid_prec(prec)) return RIME_ERR_ARG;
   if (prec == kRes64 && mode == RIME_MODE_PREDICT) return RIME_ERR_UNSUPPORTED;
-  rime_status st = check_sky(sky);
+  rime_status st = check_sky(sky, true);
   if (st != RIME_OK) return st;
   if ((st = check_terms(terms, mode)) != RIME_OK) return st;
   if (mode == RIME_MODE_PREDICT && !vis) return RIME_ERR_ARG;
   if (mode != RIME_MODE_PREDICT && (!data || !weight || !chi2)) return RIME_ERR_ARG;
-  if (mode == RIME_MODE_CHI2_GRAD && !grad) return RIME_ERR_ARG;
+  // an empty sky has no gradient rows
+  if (mode == RIME_MODE_CHI2_GRAD && !grad && sky_nsrc(sky) > 0) return RIME_ERR_ARG;
   Call c;
   c.mode = mode;
   c.prec = prec;
@@ -1277,7 +1282,9 @@ rime_status rime_plan_create(const rime_obs_desc *obs, rime_plan **out) {
 
 size_t rime_workspace_size(const rime_plan *plan, rime_mode mode, rime_precision prec,
                            int32_t nset, int64_t total_src) {
-  if (!plan || nset < 1 || total_src < 1 || mode < 0 || mode > 2 || !valid_prec(prec))
+  // total_src 0: one empty sky
+  if (!plan || nset < 1 || total_src < (nset == 1 ? 0 : nset) || mode < 0 || mode > 2 ||
+      !valid_prec(prec))
     return 0;
   return ws_max(plan, mode, prec, nset, total_src);
 }
@@ -1304,7 +1311,7 @@ rime_status rime_chi2_grad(const rime_plan *plan, const rime_sky *sky, rime_prec
 
 size_t rime_workspace_size_ex(const rime_plan *plan, rime_mode mode, rime_precision prec,
                               int64_t nsrc, const rime_terms *terms) {
-  if (!plan || nsrc < 1 || mode < 0 || mode > 2 || !valid_prec(prec) ||
+  if (!plan || nsrc < 0 || mode < 0 || mode > 2 || !valid_prec(prec) ||
       check_terms(terms, mode) != RIME_OK)
     return 0;
   int bits = 0;
@@ -1331,7 +1338,10 @@ rime_status rime_predict_ex(const rime_plan *plan, const rime_sky *sky, const ri
 rime_status rime_chi2_ex(const rime_plan *plan, const rime_sky *sky, const rime_terms *terms,
                          rime_precision prec, const void *data, const void *weight, double *chi2,
                          double *grad, void *ws, size_t ws_bytes, void *stream) {
-  return single(plan, grad ? RIME_MODE_CHI2_GRAD : RIME_MODE_CHI2, prec, sky, data, weight,
+  // a gradient call when `grad` is given or a term's gradient is asked for
+  // (an empty sky has no `grad` rows)
+  const bool g = grad || (terms && (terms->grad_die || terms->grad_stokes_t));
+  return single(plan, g ? RIME_MODE_CHI2_GRAD : RIME_MODE_CHI2, prec, sky, data, weight,
                 nullptr, chi2, grad, ws, ws_bytes, stream, terms);
 }
 
@@ -1353,7 +1363,7 @@ rime_status rime_chi2_grad_noalloc(const rime_plan *plan, const rime_sky *sky,
 
 size_t rime_streamed_workspace_size(const rime_plan *plan, rime_mode mode, rime_precision prec,
                                     int64_t nsrc, int32_t chunk_t) {
-  if (!plan || nsrc < 1 || chunk_t < 1 || (mode != RIME_MODE_CHI2 && mode != RIME_MODE_CHI2_GRAD) ||
+  if (!plan || nsrc < 0 || chunk_t < 1 || (mode != RIME_MODE_CHI2 && mode != RIME_MODE_CHI2_GRAD) ||
       !valid_prec(prec))
     return 0;
   return stream_layout(plan, mode, prec, nsrc, chunk_t).total;
@@ -1365,7 +1375,7 @@ rime_status rime_chi2_streamed(const rime_plan *plan, const rime_sky *sky, rime_
                                void *stream) {
   if (!plan || !data_host || !weight_host || !chi2 || chunk_t < 1 || !valid_prec(prec))
     return RIME_ERR_ARG;
-  rime_status st = check_sky(sky);
+  rime_status st = check_sky(sky, true);
   if (st != RIME_OK) return st;
   const int mode = grad ? RIME_MODE_CHI2_GRAD : RIME_MODE_CHI2;
   const int64_t nsrc = sky_nsrc(sky);
@@ -1388,7 +1398,7 @@ rime_status rime_chi2_streamed(const rime_plan *plan, const rime_sky *sky, rime_
   base.total_src = nsrc;
   // every chunk writes the same domain flags into the call's header
   base.dom = reinterpret_cast<int32_t *>(w + S.hdr);
-  base.dom_count = static_cast<int32_t>((nsrc + 255) / 256);
+  base.dom_count = static_cast<int32_t>(std::max<int64_t>(1, (nsrc + 255) / 256));
   // uploads start after earlier work on the caller's stream, which may still
   // be using this workspace
   RIME_HIP(hipEventRecord(plan->ev_fork, s));

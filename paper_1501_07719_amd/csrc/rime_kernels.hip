@@ -1157,6 +1157,7 @@ __global__ __launch_bounds__(256) void stokes_t_grad(const KParams p) {
 
 hipError_t launch_stokes_t_grad(const KParams &p, hipStream_t stream) {
   const int64_t n = static_cast<int64_t>(p.ntime) * (p.one.npsrc + p.one.ngsrc + p.one.nxsrc) * 4;
+  if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(stokes_t_grad, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0,
                      stream, p);
   return hipGetLastError();
@@ -1214,8 +1215,10 @@ static hipError_t launch_main(const KParams &p, int nitems, hipStream_t stream) 
 hipError_t launch_prep(const KParams &p, bool fp64, int max_nsrc, int rec_nc,
                        hipStream_t stream) {
   // rec_nc > 0: also the per-baseline records of every timestep (one grid row
-  // per timestep after the per-set rows)
-  dim3 grid((max_nsrc + 255) / 256, p.nset + (rec_nc > 0 ? p.ntime : 0));
+  // per timestep after the per-set rows); one workgroup per set row at least,
+  // which writes the set's domain flag also for a sky without sources
+  const int nblk = max_nsrc > 0 ? (max_nsrc + 255) / 256 : 1;
+  dim3 grid(nblk, p.nset + (rec_nc > 0 ? p.ntime : 0));
   if (fp64)
     hipLaunchKernelGGL(prep_sources<double>, grid, dim3(256), 0, stream, p, rec_nc);
   else
@@ -1228,6 +1231,11 @@ hipError_t launch_prep(const KParams &p, bool fp64, int max_nsrc, int rec_nc,
 hipError_t launch_finalize(const KParams &p, int mode, int max_nsrc, hipStream_t stream,
                            bool with_chi2) {
   if (mode == MODE_PREDICT) return hipSuccess;
+  if (mode == MODE_GRAD && max_nsrc == 0) {
+    // a sky without sources has no gradient rows
+    if (!with_chi2) return hipSuccess;
+    mode = MODE_CHI2;
+  }
   if (mode != MODE_GRAD) {
     hipLaunchKernelGGL(finalize_chi2, dim3(p.nset), dim3(256), 0, stream, p);
     return hipGetLastError();

@@ -12,6 +12,8 @@ benchmark configurations, shrunk in time, channels and sources so that the
 oracle finishes in seconds while still spanning several baseline tiles,
 channel blocks and source tiles with ragged tails.
 """
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -469,12 +471,24 @@ def test_errors_are_reported():
     with pytest.raises(R.RimeError) as e:
         R.rime_predict(plan, dsky, R.FP64, vis, small)
     assert e.value.status == 2
+    # a negative source count (an empty sky is valid: test_gpu_empty_sky.py)
     bad = R.DeviceSky(lm=dsky.lm, stokes=dsky.stokes, alpha=dsky.alpha, gshape=dsky.gshape,
-                      npsrc=0, ngsrc=0)
+                      npsrc=-1, ngsrc=0)
     ws = R.workspace(plan, R.MODE_PREDICT, R.FP64, 1, pr.sky.nsrc)
     with pytest.raises(R.RimeError) as e:
         R.rime_predict(plan, bad, R.FP64, vis, ws)
     assert e.value.status == 1
+    # a gradient call needs its gradient rows when the sky has sources
+    W = torch.ones((pr.obs.ntime, pr.obs.nbl, pr.obs.nchan, 4), dtype=torch.float64,
+                   device="cuda")
+    chi2 = torch.empty(1, dtype=torch.float64, device="cuda")
+    wsg = R.workspace(plan, R.MODE_CHI2_GRAD, R.FP64, 1, pr.sky.nsrc)
+    d = dsky.desc()
+    st = plan._lib.rime_chi2_grad(plan.handle, ctypes.byref(d), R.FP64,
+                                  ctypes.c_void_p(vis.data_ptr()), ctypes.c_void_p(W.data_ptr()),
+                                  ctypes.c_void_p(chi2.data_ptr()), None,
+                                  ctypes.c_void_p(wsg.data_ptr()), wsg.numel(), None)
+    assert st == 1
     plan.close()
 
 

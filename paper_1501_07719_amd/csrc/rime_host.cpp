@@ -102,6 +102,7 @@ struct rime_plan {
   int32_t *d_pair_of = nullptr;
   uint32_t *d_pair_mask = nullptr;
   int32_t ngroup = 0;
+  int32_t pme_pairs = 0;        // forward groups pair two P blocks
   int32_t *d_groups = nullptr;  // [ngroup][5] forward work groups
   bool pme_adj_ok = false;  // every antenna-pair slot holds at most one baseline
   int32_t *d_ant_off = nullptr;  // [na + 1] baselines of each antenna (both sides)
@@ -678,6 +679,7 @@ KParams make_params(const rime_plan *plan, const Call &c, const Variant &v, cons
     p.pair_blk = plan->d_pair_blk;
     p.bl_slot = plan->d_bl_slot;
     p.ngroup = plan->ngroup;
+    p.pme_pairs = plan->pme_pairs;
     p.groups = plan->d_groups;
     p.ph_hi = reinterpret_cast<uint32_t *>(w + L.ph_hi);
     p.ph_lo = reinterpret_cast<uint32_t *>(w + L.ph_lo);
@@ -1043,14 +1045,19 @@ rime_status build_pairs(int na, int nbl, const std::vector<int32_t> &a1,
     if ((w >> j) & 1u) pl->pme_adj_ok = false;
     w |= 1u << j;
   }
-  // forward work groups: every Q block with the P blocks of its pairs, two at a time
+  // forward work groups: every Q block with the P blocks of its pairs, two at
+  // a time on arrays of more than three blocks, else one at a time (where
+  // half of the pairs would be a lone block, the single-block kernel's higher
+  // occupancy wins)
+  pl->pme_pairs = nblk > 3 ? 1 : 0;
   std::vector<int32_t> groups;
   for (int Q = 0; Q < nblk; ++Q) {
     std::vector<int> ps;
     for (int P = 0; P <= Q; ++P)
       if (pair_id[static_cast<size_t>(P) * nblk + Q] >= 0) ps.push_back(P);
-    for (size_t x = 0; x < ps.size(); x += 2) {
-      const int Pa = ps[x], Pb = x + 1 < ps.size() ? ps[x + 1] : -1;
+    const size_t step = pl->pme_pairs ? 2 : 1;
+    for (size_t x = 0; x < ps.size(); x += step) {
+      const int Pa = ps[x], Pb = step == 2 && x + 1 < ps.size() ? ps[x + 1] : -1;
       groups.push_back(Q);
       groups.push_back(Pa);
       groups.push_back(Pb);

@@ -127,8 +127,9 @@ struct KParams {
   uint32_t *ph_hi;         // phase planes [pme_nt][nchan][npsrc][nap] half2 (re, im):
   uint32_t *ph_lo;         //   a = hi + lo, a = e exp(-2 pi i tau nu / c)
   float *ph_k3;            // [pme_nt][nchan][npsrc][nap] d ln e / d(l, m) = k3 (l - dl, m - dm)
-  int32_t ngroup;          // forward work groups: a Q block with up to two P blocks
+  int32_t ngroup;          // forward work groups: a Q block with one or two P blocks
   const int32_t *groups;   // [ngroup][5] (Q, Pa, Pb or -1, pair of (Pa, Q), pair of (Pb, Q))
+  int32_t pme_pairs;       // 1: groups pair two P blocks of a Q block; 0: one each
   int32_t *pme_exp;        // [nchan][4] exponent of max_s |St'_k| (forward scale 2^-e)
   int32_t pme_t0, pme_nt;  // timesteps held by the phase planes
   int32_t phase_nc;        // channels per workgroup of the phase planes (set at launch)

@@ -14,7 +14,7 @@
 //                and the beam's d ln e / d(l, m) factor;
 //   pme_scale    per (channel, Stokes parameter) power-of-two scale of the
 //                source-side operand;
-//   pme_forward  one Q block of 32 antennas against up to two P blocks per
+//   pme_forward  one Q block of 32 antennas against one or two P blocks per
 //                workgroup, one Stokes parameter per wavefront: the real form
 //                of the product over (s, re/im) with v_mfma_f32_32x32x16_f16,
 //                each fp16 product taken as hi*hi + hi*lo + lo*hi, summed in
@@ -60,8 +60,26 @@ __device__ inline void split_h(float x, _Float16 &h, _Float16 &l) {
   l = static_cast<_Float16>(x - static_cast<float>(h));
 }
 
-// (re, im) -> (im, -re) on the four pairs of a fragment: the row of the
-// imaginary part of a conj(b) in the real form of the complex product.
+// (x0, x1) = h + l as two fp16 pairs.  The hi pair is materialised once, so
+// that the lo pair is taken against the very values the products use
+// (otherwise the compiler may form the packed hi pair and the hi value the lo
+// part is taken against with different conversions, which differ by an ulp
+// when the product is rounded once rather than twice).
+__device__ inline void split_h2(float x0, float x1, uint32_t &h, uint32_t &l) {
+  typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+  const half2v hv = {static_cast<_Float16>(x0), static_cast<_Float16>(x1)};
+  h = opaque_vgpr(__builtin_bit_cast(uint32_t, hv));
+  const half2v lv = {static_cast<_Float16>(x0 - lo_h(h)), static_cast<_Float16>(x1 - hi_h(h))};
+  l = __builtin_bit_cast(uint32_t, lv);
+}
+
+// fp16 pair (re, im) -> (-im, re): with b in the B operand of the real form
+// of a complex product, the column of the imaginary part of a conj(b)
+__device__ inline uint32_t rot_h2(uint32_t w) { return ((w >> 16) | (w << 16)) ^ 0x8000u; }
+
+// (re, im) -> (im, -re) on the four pairs of a fragment: with a in the A
+// operand, the row of the imaginary part of a conj(b) (the adjoint's residual
+// fragments, rotated once per channel: they do not change over the sources)
 __device__ inline half8 rot8(half8 v) {
   half8 r;
 #pragma unroll
@@ -201,19 +219,31 @@ __global__ __launch_bounds__(256) void pme_scale(const KParams p) {
 }
 
 // ---------------------------------------------------------------------------
-// Forward: workgroup = (timestep, channel, group of one Q block and up to two
-// P blocks); wavefront k accumulates S_k for both (P, Q) tiles.  The Q side
-// carries St'_k 2^-e(nu, k) and is split after the product; the P side is the
-// plain a (and its rotation for the imaginary part).
+// Forward: workgroup = (timestep, channel, group of one Q block and NT P
+// blocks); wavefront k accumulates S_k of the group's tiles (P, Q).  The P
+// side is the plain a as fp16 hi/lo fragments from LDS.  The Q side carries
+// St'_k 2^-e(nu, k): each wavefront forms it for its own k from a float32 copy
+// of the Q block's a in LDS and splits it in registers, together with its
+// rotation (re, im) -> (-im, re), which gives the imaginary part of the
+// product; the tiles of a group share the two.  NT = 2 halves that work per
+// tile but holds the float64 sums of two tiles (two workgroups per CU);
+// NT = 1 runs three workgroups per CU, so that one's products overlap
+// another's operand work.  The plan pairs the tiles of a Q block when the
+// array has more than three antenna blocks: with fewer, half of the groups
+// would hold one tile (64 antennas, 100 timesteps, 64 channels: 2.40 ms with
+// NT = 1 against 2.70 ms; 197 antennas, 20 timesteps, 256 channels: 24.3 ms
+// against 23.1 ms).
 // ---------------------------------------------------------------------------
 struct FwdRegs {
   uint4 pah, pal, pbh, pbl, qh, ql;
   float4 st;
 };
 
+constexpr int kPmeQRow = 2 * kPmeCh + 4;  // floats per LDS row of the Q block: (s, re/im) + 16 B pad
+
 // Global operands of one chunk for thread (source tid / 8, antennas 4 (tid % 8) ..)
 // at channel c and timestep t.
-template <bool ST>
+template <bool ST, int NT>
 __device__ inline FwdRegs fwd_load(const KParams &p, const uint32_t *hi0, const uint32_t *lo0,
                                    int c, int t, int s0, int cnt, int Q, int Pa, int Pb) {
   const int tid = threadIdx.x;
@@ -233,20 +263,22 @@ __device__ inline FwdRegs fwd_load(const KParams &p, const uint32_t *hi0, const 
       r.pah = *reinterpret_cast<const uint4 *>(hi0 + row + Pa * kPmeBlk + ag);
       r.pal = *reinterpret_cast<const uint4 *>(lo0 + row + Pa * kPmeBlk + ag);
     }
-    if (Pb == Q) {
-      r.pbh = r.qh;
-      r.pbl = r.ql;
-    } else if (Pb >= 0) {
-      r.pbh = *reinterpret_cast<const uint4 *>(hi0 + row + Pb * kPmeBlk + ag);
-      r.pbl = *reinterpret_cast<const uint4 *>(lo0 + row + Pb * kPmeBlk + ag);
+    if (NT == 2) {
+      if (Pb == Q) {
+        r.pbh = r.qh;
+        r.pbl = r.ql;
+      } else if (Pb >= 0) {
+        r.pbh = *reinterpret_cast<const uint4 *>(hi0 + row + Pb * kPmeBlk + ag);
+        r.pbl = *reinterpret_cast<const uint4 *>(lo0 + row + Pb * kPmeBlk + ag);
+      }
     }
     r.st = pme_stokes<ST>(p, s0 + s, c, t);
   }
   return r;
 }
 
-template <bool ST>
-__global__ __launch_bounds__(256, 2) void pme_forward(const KParams p) {
+template <bool ST, int NT>
+__global__ __launch_bounds__(256, NT == 1 ? 3 : 2) void pme_forward(const KParams p) {
   const int nitems = p.pme_nt * p.nchan * p.ngroup;
   const int item = xcd_item(nitems);
   if (item >= nitems) return;
@@ -255,15 +287,16 @@ __global__ __launch_bounds__(256, 2) void pme_forward(const KParams p) {
   const int c = rest % p.nchan;
   const int tt = rest / p.nchan;
 
-  // [P block a/b][antenna][(s, re/im)]
-  __shared__ __attribute__((aligned(16))) _Float16 s_ah[2][kPmeBlk][kPmeRow];
-  __shared__ __attribute__((aligned(16))) _Float16 s_al[2][kPmeBlk][kPmeRow];
-  __shared__ __attribute__((aligned(16))) _Float16 s_bh[4][kPmeBlk][kPmeRow];
-  __shared__ __attribute__((aligned(16))) _Float16 s_bl[4][kPmeBlk][kPmeRow];
+  // [P block a/b][antenna][(s, re/im)] as fp16 hi/lo; the Q block's a in
+  // float32; the scaled Stokes parameters [k][s]
+  __shared__ __attribute__((aligned(16))) _Float16 s_ah[NT][kPmeBlk][kPmeRow];
+  __shared__ __attribute__((aligned(16))) _Float16 s_al[NT][kPmeBlk][kPmeRow];
+  __shared__ __attribute__((aligned(16))) float s_qf[kPmeBlk][kPmeQRow];
+  __shared__ __attribute__((aligned(16))) float s_f[4][kPmeCh];
 
   const SetDesc sd = p.one;
   const int *gr = p.groups + grp * 5;
-  const int Q = gr[0], Pa = gr[1], Pb = gr[2], ida = gr[3], idb = gr[4];
+  const int Q = gr[0], Pa = gr[1], Pb = NT == 2 ? gr[2] : -1, ida = gr[3], idb = gr[4];
   const int tid = threadIdx.x;
   const int wave = tid / kWave, lane = tid % kWave;
   const int k = wave;  // Stokes parameter of this wavefront
@@ -278,19 +311,21 @@ __global__ __launch_bounds__(256, 2) void pme_forward(const KParams p) {
   for (int kk = 0; kk < 4; ++kk) fsc[kk] = ldexpf(1.0f, -p.pme_exp[c * 4 + kk]);
   const double unscale = ldexp(1.0, p.pme_exp[c * 4 + k]);
 
-  floatx16 aR0, aI0, aR1, aI1;
-  double dR0[16], dI0[16], dR1[16], dI1[16];
+  floatx16 aR[NT], aI[NT];
+  double dR[NT][16], dI[NT][16];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    aR0[r] = aI0[r] = aR1[r] = aI1[r] = 0.0f;
-    dR0[r] = dI0[r] = dR1[r] = dI1[r] = 0.0;
-  }
+  for (int x = 0; x < NT; ++x)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      aR[x][r] = aI[x][r] = 0.0f;
+      dR[x][r] = dI[x][r] = 0.0;
+    }
 
   const int nchunk = (sd.npsrc + kPmeCh - 1) / kPmeCh;
   for (int ch = 0; ch < nchunk; ++ch) {
-    const FwdRegs cur = fwd_load<ST>(p, hi0, lo0, c, p.pme_t0 + tt, ch * kPmeCh,
-                                 min(kPmeCh, sd.npsrc - ch * kPmeCh), Q, Pa, Pb);
-    __syncthreads();  // the previous chunk's fragments are consumed
+    const FwdRegs cur = fwd_load<ST, NT>(p, hi0, lo0, c, p.pme_t0 + tt, ch * kPmeCh,
+                                         min(kPmeCh, sd.npsrc - ch * kPmeCh), Q, Pa, Pb);
+    __syncthreads();  // the previous chunk's operands are consumed
     {
       const int s = tid >> 3, ag = (tid & 7) * 4;
       const uint32_t w0[4] = {cur.pah.x, cur.pah.y, cur.pah.z, cur.pah.w};
@@ -299,29 +334,23 @@ __global__ __launch_bounds__(256, 2) void pme_forward(const KParams p) {
       const uint32_t w3[4] = {cur.pbl.x, cur.pbl.y, cur.pbl.z, cur.pbl.w};
       const uint32_t wq[4] = {cur.qh.x, cur.qh.y, cur.qh.z, cur.qh.w};
       const uint32_t wl[4] = {cur.ql.x, cur.ql.y, cur.ql.z, cur.ql.w};
-      float f[4];
-      f[0] = cur.st.x * fsc[0];
-      f[1] = cur.st.y * fsc[1];
-      f[2] = cur.st.z * fsc[2];
-      f[3] = cur.st.w * fsc[3];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         *reinterpret_cast<uint32_t *>(&s_ah[0][ag + j][2 * s]) = w0[j];
         *reinterpret_cast<uint32_t *>(&s_al[0][ag + j][2 * s]) = w1[j];
-        if (Pb >= 0) {
-          *reinterpret_cast<uint32_t *>(&s_ah[1][ag + j][2 * s]) = w2[j];
-          *reinterpret_cast<uint32_t *>(&s_al[1][ag + j][2 * s]) = w3[j];
+        if (NT == 2 && Pb >= 0) {
+          *reinterpret_cast<uint32_t *>(&s_ah[NT - 1][ag + j][2 * s]) = w2[j];
+          *reinterpret_cast<uint32_t *>(&s_al[NT - 1][ag + j][2 * s]) = w3[j];
         }
-        const float ar = lo_h(wq[j]) + lo_h(wl[j]);
-        const float ai = hi_h(wq[j]) + hi_h(wl[j]);
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-          _Float16 rh, rl, ih, il;
-          split_h(ar * f[kk], rh, rl);
-          split_h(ai * f[kk], ih, il);
-          *reinterpret_cast<uint32_t *>(&s_bh[kk][ag + j][2 * s]) = pack_h2(rh, ih);
-          *reinterpret_cast<uint32_t *>(&s_bl[kk][ag + j][2 * s]) = pack_h2(rl, il);
-        }
+        // a = hi + lo exactly in float32
+        *reinterpret_cast<float2 *>(&s_qf[ag + j][2 * s]) =
+            make_float2(lo_h(wq[j]) + lo_h(wl[j]), hi_h(wq[j]) + hi_h(wl[j]));
+      }
+      if ((tid & 7) == 0) {
+        s_f[0][s] = cur.st.x * fsc[0];
+        s_f[1][s] = cur.st.y * fsc[1];
+        s_f[2][s] = cur.st.z * fsc[2];
+        s_f[3][s] = cur.st.w * fsc[3];
       }
     }
     __syncthreads();
@@ -329,60 +358,60 @@ __global__ __launch_bounds__(256, 2) void pme_forward(const KParams p) {
     for (int step = 0; step < kPmeCh / 8; ++step) {
       // K index (s, re/im) with s = 8 step + 4 g + e / 2 for element e
       const int col = 16 * step + 8 * g;
-      const half8 bh = *reinterpret_cast<const half8 *>(&s_bh[k][row][col]);
-      const half8 bl = *reinterpret_cast<const half8 *>(&s_bl[k][row][col]);
+      half8 bh, bl, rbh, rbl;
       {
-        const half8 ah = *reinterpret_cast<const half8 *>(&s_ah[0][row][col]);
-        const half8 al = *reinterpret_cast<const half8 *>(&s_al[0][row][col]);
-        const half8 rh = rot8(ah), rl = rot8(al);
-        aR0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bh, aR0, 0, 0, 0);
-        aI0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(rh, bh, aI0, 0, 0, 0);
-        aR0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bl, aR0, 0, 0, 0);
-        aI0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(rh, bl, aI0, 0, 0, 0);
-        aR0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, bh, aR0, 0, 0, 0);
-        aI0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(rl, bh, aI0, 0, 0, 0);
+        const float4 q0 = *reinterpret_cast<const float4 *>(&s_qf[row][col]);
+        const float4 q1 = *reinterpret_cast<const float4 *>(&s_qf[row][col + 4]);
+        const float4 f = *reinterpret_cast<const float4 *>(&s_f[k][8 * step + 4 * g]);
+        uint32_t hw[4], lw[4];
+        split_h2(q0.x * f.x, q0.y * f.x, hw[0], lw[0]);
+        split_h2(q0.z * f.y, q0.w * f.y, hw[1], lw[1]);
+        split_h2(q1.x * f.z, q1.y * f.z, hw[2], lw[2]);
+        split_h2(q1.z * f.w, q1.w * f.w, hw[3], lw[3]);
+        bh = __builtin_bit_cast(half8, make_uint4(hw[0], hw[1], hw[2], hw[3]));
+        bl = __builtin_bit_cast(half8, make_uint4(lw[0], lw[1], lw[2], lw[3]));
+        rbh = __builtin_bit_cast(half8,
+                                 make_uint4(rot_h2(hw[0]), rot_h2(hw[1]), rot_h2(hw[2]), rot_h2(hw[3])));
+        rbl = __builtin_bit_cast(half8,
+                                 make_uint4(rot_h2(lw[0]), rot_h2(lw[1]), rot_h2(lw[2]), rot_h2(lw[3])));
       }
-      if (Pb >= 0) {
-        const half8 ah = *reinterpret_cast<const half8 *>(&s_ah[1][row][col]);
-        const half8 al = *reinterpret_cast<const half8 *>(&s_al[1][row][col]);
-        const half8 rh = rot8(ah), rl = rot8(al);
-        aR1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bh, aR1, 0, 0, 0);
-        aI1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(rh, bh, aI1, 0, 0, 0);
-        aR1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bl, aR1, 0, 0, 0);
-        aI1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(rh, bl, aI1, 0, 0, 0);
-        aR1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, bh, aR1, 0, 0, 0);
-        aI1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(rl, bh, aI1, 0, 0, 0);
+#pragma unroll
+      for (int x = 0; x < NT; ++x) {
+        if (x == 1 && Pb < 0) break;
+        const half8 ah = *reinterpret_cast<const half8 *>(&s_ah[x][row][col]);
+        const half8 al = *reinterpret_cast<const half8 *>(&s_al[x][row][col]);
+        aR[x] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bh, aR[x], 0, 0, 0);
+        aI[x] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, rbh, aI[x], 0, 0, 0);
+        aR[x] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bl, aR[x], 0, 0, 0);
+        aI[x] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, rbl, aI[x], 0, 0, 0);
+        aR[x] = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, bh, aR[x], 0, 0, 0);
+        aI[x] = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, rbh, aI[x], 0, 0, 0);
       }
     }
     if ((ch + 1) % kPmeFold == 0 || ch + 1 == nchunk) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        dR0[r] += static_cast<double>(aR0[r]) * unscale;
-        dI0[r] += static_cast<double>(aI0[r]) * unscale;
-        dR1[r] += static_cast<double>(aR1[r]) * unscale;
-        dI1[r] += static_cast<double>(aI1[r]) * unscale;
-        aR0[r] = aI0[r] = aR1[r] = aI1[r] = 0.0f;
-      }
+      for (int x = 0; x < NT; ++x)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          dR[x][r] += static_cast<double>(aR[x][r]) * unscale;
+          dI[x][r] += static_cast<double>(aI[x][r]) * unscale;
+          aR[x][r] = aI[x][r] = 0.0f;
+        }
     }
   }
 
   // Stokes sums S_k[i][j] of antennas (32 P + i, 32 Q + j)
   const int64_t slice = (static_cast<int64_t>(p.pme_t0) + tt) * p.nchan + c;
   const int j = lane & 31;
-  {
-    double2 *out = p.spts + ((slice * p.npair + ida) * 4 + k) * (kPmeBlk * kPmeBlk);
+#pragma unroll
+  for (int x = 0; x < NT; ++x) {
+    if (x == 1 && Pb < 0) break;
+    double2 *out =
+        p.spts + ((slice * p.npair + (x == 0 ? ida : idb)) * 4 + k) * (kPmeBlk * kPmeBlk);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int i = (r & 3) + 8 * (r >> 2) + 4 * g;
-      out[i * kPmeBlk + j] = make_double2(dR0[r], dI0[r]);
-    }
-  }
-  if (Pb >= 0) {
-    double2 *out = p.spts + ((slice * p.npair + idb) * 4 + k) * (kPmeBlk * kPmeBlk);
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int i = (r & 3) + 8 * (r >> 2) + 4 * g;
-      out[i * kPmeBlk + j] = make_double2(dR1[r], dI1[r]);
+      out[i * kPmeBlk + j] = make_double2(dR[x][r], dI[x][r]);
     }
   }
 }
@@ -839,12 +868,18 @@ hipError_t launch_pme(const KParams &p, hipStream_t stream) {
   if (e != hipSuccess) return e;
   const int64_t nitems = static_cast<int64_t>(p.pme_nt) * p.nchan * p.ngroup;
   const int64_t grid = 8 * ((nitems + 7) / 8);
-  if (p.stokes_t)
-    hipLaunchKernelGGL(pme_forward<true>, dim3(static_cast<unsigned>(grid)), dim3(256), 0, stream,
-                       p);
-  else
-    hipLaunchKernelGGL(pme_forward<false>, dim3(static_cast<unsigned>(grid)), dim3(256), 0,
-                       stream, p);
+  const dim3 gd(static_cast<unsigned>(grid)), bd(256);
+  if (p.pme_pairs) {
+    if (p.stokes_t)
+      hipLaunchKernelGGL((pme_forward<true, 2>), gd, bd, 0, stream, p);
+    else
+      hipLaunchKernelGGL((pme_forward<false, 2>), gd, bd, 0, stream, p);
+  } else {
+    if (p.stokes_t)
+      hipLaunchKernelGGL((pme_forward<true, 1>), gd, bd, 0, stream, p);
+    else
+      hipLaunchKernelGGL((pme_forward<false, 1>), gd, bd, 0, stream, p);
+  }
   return hipGetLastError();
 }
 

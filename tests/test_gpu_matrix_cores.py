@@ -3,10 +3,11 @@ form the point-source sums as the antenna x antenna product per timestep and
 channel) against the CPU oracle, through the C ABI: visibilities, chi^2 and
 gradient to the mixed tolerance (1e-5 of F_nu, 1e-5 relative).
 
-The observations span several 32-antenna blocks with a ragged last block,
-baselines in arbitrary order with swapped antenna pairs across blocks (the
-engine then takes the conjugate of the stored pair), a duplicate baseline and
-an autocorrelation, with and without the beam. Two cases end the channel
+The observations span several 32-antenna blocks with a ragged last block (up to
+three blocks, where the forward runs one tile per workgroup, and five and
+seven, where it pairs two), baselines in arbitrary order with swapped antenna
+pairs across blocks (the engine then takes the conjugate of the stored pair),
+a duplicate baseline and an autocorrelation, with and without the beam. Two cases end the channel
 blocks of the phase planes with a partial block: 16 + 3 channels for small
 planes, and 4 + 3 for planes of 1 MiB and more.
 """
@@ -50,6 +51,19 @@ def problem(kind):
         a1 = np.concatenate([a1, a1[:1], [35]]).astype(np.int32)
         a2 = np.concatenate([a2, a2[:1], [35]]).astype(np.int32)
         obs = Observation(**{**obs.__dict__, "ant1": a1, "ant2": a2})
+    elif kind == "five_blocks_swapped":
+        # 150 antennas: five blocks (the last ragged), so that the forward
+        # pairs the P blocks of each Q block, with a lone block left over
+        # where a Q block has an odd number of pairs; 300 of the baselines,
+        # shuffled, half of them swapped
+        pr = make_problem("c1", ntime=2, nchan=3, npsrc=40, ngsrc=6, na=150, key=37)
+        obs, sky = pr.obs, pr.sky
+        keep = rng.choice(obs.nbl, 300, replace=False)
+        a1, a2 = obs.ant1[keep].copy(), obs.ant2[keep].copy()
+        sw = rng.random(a1.size) < 0.5
+        a1[sw], a2[sw] = a2[sw], a1[sw].copy()
+        obs = Observation(**{**obs.__dict__, "ant1": a1.astype(np.int32),
+                             "ant2": a2.astype(np.int32)})
     elif kind == "points_no_beam":
         pr = make_problem("c4", ntime=1, nchan=3, npsrc=50, ngsrc=0, na=45, key=33)
         obs = Observation(**{**pr.obs.__dict__, "beam": False, "pointing": None,
@@ -82,8 +96,8 @@ def problem(kind):
     return obs, sky, D, W
 
 
-KINDS = ["three_blocks", "shuffled_swapped", "points_no_beam", "gauss_only",
-         "ragged_channel_blocks", "wide_planes"]
+KINDS = ["three_blocks", "shuffled_swapped", "five_blocks_swapped", "points_no_beam",
+         "gauss_only", "ragged_channel_blocks", "wide_planes"]
 
 
 @pytest.mark.parametrize("kind", KINDS)

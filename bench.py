@@ -514,7 +514,7 @@ def bench_extras(args, R, plan, obs, sky, D32, W32, modes, base_ms):
                                           grad_stokes_t=gst), args.steps, 1)[0]
         out["terms"] = record(ms, what="2x2 G per (timestep, antenna, channel) and Stokes per "
                                        "(timestep, source), with d chi2/dG and d chi2/dStokes_t; "
-                                       "point sources on the per-baseline kernel")
+                                       "point sources on the matrix cores as in the plain call")
         log("grad_terms", out["terms"])
         del ws, die, st, gdie, gst
     if "grad_disk" in modes:

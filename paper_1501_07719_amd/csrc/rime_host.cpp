@@ -91,8 +91,8 @@ struct rime_plan {
   int32_t ntime = 0, na = 0, nbl = 0, nchan = 0;
   int32_t beam = 0;
   double ref_freq = 0, beam_k = 0, beam_clip = 0;
-  double *d_uvw = nullptr, *d_nu_c = nullptr, *d_lnfr = nullptr, *d_bfr = nullptr;
-  double *d_clip_r2 = nullptr;
+  double *d_uvw = nullptr, *d_nu_c = nullptr, *d_lnfr = nullptr, *d_bsc = nullptr;
+  double *d_bk3 = nullptr, *d_clip_r2 = nullptr;
   double *d_pointing = nullptr, *d_gains = nullptr;
   TileSet tiles[3];
   // antenna-block pairs of the matrix-core point-source engine
@@ -577,7 +577,8 @@ KParams base_params(const rime_plan *plan) {
   p.pointing = plan->d_pointing;
   p.gains = plan->d_gains;
   p.beam = plan->beam;
-  p.bfr = plan->d_bfr;
+  p.bsc = plan->d_bsc;
+  p.bk3 = plan->d_bk3;
   p.clip_r2 = plan->d_clip_r2;
   p.beam_k = plan->beam_k;
   p.beam_clip = plan->beam_clip;
@@ -1140,7 +1141,8 @@ void rime_plan_destroy(rime_plan *plan) {
   (void)hipFree(plan->d_uvw);
   (void)hipFree(plan->d_nu_c);
   (void)hipFree(plan->d_lnfr);
-  (void)hipFree(plan->d_bfr);
+  (void)hipFree(plan->d_bsc);
+  (void)hipFree(plan->d_bk3);
   (void)hipFree(plan->d_clip_r2);
   (void)hipFree(plan->d_pointing);
   (void)hipFree(plan->d_gains);
@@ -1213,15 +1215,19 @@ rime_status rime_plan_create(const rime_obs_desc *obs, rime_plan **out) {
   pl->beam_clip = obs->beam == 1 ? obs->beam_clip : 0.0;
   const size_t nuvw = static_cast<size_t>(obs->ntime) * obs->na * 3;
   std::vector<double> uvw(obs->uvw, obs->uvw + nuvw);
-  std::vector<double> nu_c(obs->nchan), lnfr(obs->nchan), bfr(obs->nchan, 0.0),
-      clip_r2(obs->nchan, 0.0);
+  std::vector<double> nu_c(obs->nchan), lnfr(obs->nchan), bsc(obs->nchan, 0.0),
+      bk3(obs->nchan, 0.0), clip_r2(obs->nchan, 0.0);
   for (int c = 0; c < obs->nchan; ++c) {
     nu_c[c] = obs->freq[c] / kC;
     lnfr[c] = std::log(obs->freq[c] / obs->ref_freq);
     if (obs->beam == 1) {
-      bfr[c] = obs->freq[c] / obs->beam_ref_freq;
+      const double bfr = obs->freq[c] / obs->beam_ref_freq;
+      // the beam argument's scale beam_k nu / beam_ref_freq and the factor
+      // -3 bs^2 of its gradient, per channel
+      bsc[c] = obs->beam_k * bfr;
+      bk3[c] = -3.0 * bsc[c] * bsc[c];
       // radius at which beam_k r nu / beam_ref_freq reaches the clip
-      const double rc = obs->beam_k > 0 ? obs->beam_clip / (obs->beam_k * bfr[c]) : 1e300;
+      const double rc = obs->beam_k > 0 ? obs->beam_clip / (obs->beam_k * bfr) : 1e300;
       clip_r2[c] = rc * rc;
     }
   }
@@ -1237,7 +1243,7 @@ rime_status rime_plan_create(const rime_obs_desc *obs, rime_plan **out) {
   rime_status st = RIME_OK;
   if ((e = upload(&pl->d_uvw, uvw)) != hipSuccess || (e = upload(&pl->d_nu_c, nu_c)) != hipSuccess ||
       (e = upload(&pl->d_lnfr, lnfr)) != hipSuccess ||
-      (e = upload(&pl->d_bfr, bfr)) != hipSuccess ||
+      (e = upload(&pl->d_bsc, bsc)) != hipSuccess || (e = upload(&pl->d_bk3, bk3)) != hipSuccess ||
       (e = upload(&pl->d_clip_r2, clip_r2)) != hipSuccess ||
       (e = upload(&pl->d_pointing, pnt)) != hipSuccess ||
       (e = upload(&pl->d_gains, gains)) != hipSuccess) {

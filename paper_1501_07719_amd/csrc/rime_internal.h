@@ -52,7 +52,8 @@ struct KParams {
   const double *pointing;  // [ntime][na][2]  (zeros when absent)
   const double *gains;     // [na][2][2]  (unity when absent)
   int32_t beam;
-  const double *bfr;       // [nchan]  nu / beam_ref_freq
+  const double *bsc;       // [nchan]  beam_k nu / beam_ref_freq (the beam argument per radian)
+  const double *bk3;       // [nchan]  -3 bsc^2 (the beam gradient's factor)
   const double *clip_r2;   // [nchan]  (beam_clip / (beam_k nu / beam_ref_freq))^2
   double beam_k;           // beam argument is beam_k * r * nu / beam_ref_freq
   double beam_clip;

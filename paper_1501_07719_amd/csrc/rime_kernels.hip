@@ -257,7 +257,7 @@ __device__ inline void stage_tile(const KParams &p, const SetDesc &sd, int t, in
             // threshold (beam_clip / bs)^2.
             // d ln e / dl = -3 tan(x) dx/dl, dx/dl = bs (l - dl_p) / r
             //             = -3 bs^2 (l - dl_p) tan(x)/x ; zero past the clip.
-            const double bs = p.beam_k * p.bfr[c0 + c];
+            const double bs = p.bsc[c0 + c];
             const bool clipped = r2b >= p.clip_r2[c0 + c];
             const double xr = clipped ? p.beam_clip : bs * rb;
             R tx = R(0);
@@ -273,7 +273,7 @@ __device__ inline void stage_tile(const KParams &p, const SetDesc &sd, int t, in
               if (!clipped) tx = txf;
             }
             if (WITH_BETA) {
-              const R k3 = static_cast<R>(-3.0 * bs * bs) * tx;
+              const R k3 = static_cast<R>(p.bk3[c0 + c]) * tx;
               bet[c].x = k3 * static_cast<R>(dl);
               bet[c].y = k3 * static_cast<R>(dm);
             }

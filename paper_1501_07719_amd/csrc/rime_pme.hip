@@ -149,13 +149,13 @@ __global__ __launch_bounds__(256) void pme_phase(const KParams p) {
     if (p.beam) {
       // cos^3 of beam_k r nu / beam_ref_freq, clipped (eq. e_term); the clip
       // is decided in float64 on r^2 as in the per-baseline kernels
-      const double bs = p.beam_k * p.bfr[c];
+      const double bs = p.bsc[c];
       const bool clipped = r2b >= p.clip_r2[c];
       const double xd = clipped ? p.beam_clip : bs * rb;
       float tx = 0.0f;
       beam_f32(static_cast<float>(xd), k3p != nullptr, &e, &tx);
       // d ln e / dl = -3 bs^2 (l - dl_p) tan(x)/x; zero past the clip
-      if (!clipped) k3 = static_cast<float>(-3.0 * bs * bs) * tx;
+      if (!clipped) k3 = static_cast<float>(p.bk3[c]) * tx;
     }
     _Float16 rh, rl, ih, il;
     split_h(e * cs, rh, rl);

@@ -79,7 +79,8 @@ __device__ inline uint32_t rot_h2(uint32_t w) { return ((w >> 16) | (w << 16)) ^
 
 // (re, im) -> (im, -re) on the four pairs of a fragment: with a in the A
 // operand, the row of the imaginary part of a conj(b) (the adjoint's residual
-// fragments, rotated once per channel: they do not change over the sources)
+// fragments; they do not change over the sources of a channel, and hipcc
+// keeps the rotated copies in registers across the source loop)
 __device__ inline half8 rot8(half8 v) {
   half8 r;
 #pragma unroll

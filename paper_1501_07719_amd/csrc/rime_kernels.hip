@@ -482,6 +482,113 @@ __device__ inline void adjoint_loop(int wave, int nw, int nact, const RIME_CONST
   }
 }
 
+// Pass 2 inner loop of the float32 kernels with two channels per thread,
+// with both channels of a (source, baseline) in one lane: lane (source sl,
+// half hb) takes the baselines 2 j + hb of this wavefront's pairs j (and the
+// wavefront that holds a last, unpaired baseline takes it in half 0).  The
+// per-channel sums g[c][0..3] (Re(c rho_k)), g5[c], g6[c] (beam) are as in
+// adjoint_loop; the phase and shape sums are merged over the two channels,
+// each channel's final factor applied per baseline:
+//   G7..G9   sum (du, dv, dw) Pi,        Pi = sum_c tp_c Im P_c
+//   G10..G14 sum du A0 H, dv B0 H, dv A0 H, du B0 H, B0^2 H,
+//            H = sum_c dk_c h_c Re P_c, with A0 = du e.x + dv e.y and
+//            B0 = du e.z - dv e.w of the unscaled shape (el, em, R em, R el),
+//            S_c = expb(-kk_c (A0^2 + B0^2)) for a Gaussian and
+//            (1 + kk_c (A0^2 + B0^2))^(-3/2), h_c = 1 / (1 + kk_c (A0^2 + B0^2))
+//            for a disk (h_c = 1 for a Gaussian).
+// The shape coordinates are then formed once per baseline for both channels.
+struct PairConst {
+  float tp[2], kk[2], dk[2];  // 2 pi nu/c, the shape scale squared, the shape gradient factor
+};
+struct PairAcc {
+  float g[2][4], g5[2], g6[2], G[8];  // G: G7, G8, G9, G10 .. G14
+};
+
+template <int SHAPE, bool BEAM, int BETA_OFF>
+__device__ inline void adjoint_pair(int wave, int nw, int nact, int hb, const float4 *rec,
+                                    const float2 *s_rho, const char *arow, const float4 st0,
+                                    const float4 st1, const float4 e, const PairConst &k,
+                                    PairAcc &a) {
+  auto body = [&](const float4 geo, int bi) {
+    const uint32_t off = __float_as_uint(geo.w);
+    const char *pa = arow + (off & 0xffffu);
+    const char *qa = arow + (off >> 16);
+    const float4 ap = *reinterpret_cast<const float4 *>(pa);  // (channel 0, channel 1)
+    const float4 aq = *reinterpret_cast<const float4 *>(qa);
+    const float4 *rho = reinterpret_cast<const float4 *>(s_rho + bi * 2 * 4);
+    const float4 r[4] = {rho[0], rho[1], rho[2], rho[3]};  // channel 0: k 0,1 | 2,3; channel 1
+    float cr[2] = {ap.x * aq.x + ap.y * aq.y, ap.z * aq.z + ap.w * aq.w};
+    float ci[2] = {ap.y * aq.x - ap.x * aq.y, ap.w * aq.z - ap.z * aq.w};
+    float A0 = 0.0f, B0 = 0.0f, h[2] = {1.0f, 1.0f};
+    if (SHAPE != SHAPE_POINT) {
+      A0 = geo.x * e.x + geo.y * e.y;
+      B0 = geo.x * e.z - geo.y * e.w;
+      const float Q0 = A0 * A0 + B0 * B0;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        float S;
+        if (SHAPE == SHAPE_GAUSS) {
+          S = __builtin_amdgcn_exp2f(-(k.kk[c] * Q0));
+        } else {
+          const float rr = __builtin_amdgcn_rsqf(1.0f + k.kk[c] * Q0);
+          h[c] = rr * rr;
+          S = h[c] * rr;
+        }
+        cr[c] *= S;
+        ci[c] *= S;
+      }
+    }
+    float Pr[2], Pi[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const float4 ra = r[2 * c], rb = r[2 * c + 1];  // (rho_0, rho_1), (rho_2, rho_3)
+      const float4 st = c == 0 ? st0 : st1;
+      a.g[c][0] += cr[c] * ra.x;
+      a.g[c][0] -= ci[c] * ra.y;
+      a.g[c][1] += cr[c] * ra.z;
+      a.g[c][1] -= ci[c] * ra.w;
+      a.g[c][2] += cr[c] * rb.x;
+      a.g[c][2] -= ci[c] * rb.y;
+      a.g[c][3] += cr[c] * rb.z;
+      a.g[c][3] -= ci[c] * rb.w;
+      const float phr = st.x * ra.x + st.y * ra.z + st.z * rb.x + st.w * rb.z;
+      const float phi = st.x * ra.y + st.y * ra.w + st.z * rb.y + st.w * rb.w;
+      Pr[c] = cr[c] * phr - ci[c] * phi;
+      Pi[c] = cr[c] * phi + ci[c] * phr;
+    }
+    if (BEAM) {
+      const float4 bp = *reinterpret_cast<const float4 *>(pa + BETA_OFF);
+      const float4 bq = *reinterpret_cast<const float4 *>(qa + BETA_OFF);
+      a.g5[0] += (bp.x + bq.x) * Pr[0];
+      a.g6[0] += (bp.y + bq.y) * Pr[0];
+      a.g5[1] += (bp.z + bq.z) * Pr[1];
+      a.g6[1] += (bp.w + bq.w) * Pr[1];
+    }
+    const float Pt = k.tp[0] * Pi[0] + k.tp[1] * Pi[1];
+    a.G[0] += geo.x * Pt;
+    a.G[1] += geo.y * Pt;
+    a.G[2] += geo.z * Pt;
+    if (SHAPE != SHAPE_POINT) {
+      const float H = k.dk[0] * h[0] * Pr[0] + k.dk[1] * h[1] * Pr[1];
+      const float t1 = A0 * H, t2 = B0 * H;
+      a.G[3] += geo.x * t1;
+      a.G[4] += geo.y * t2;
+      a.G[5] += geo.y * t1;
+      a.G[6] += geo.x * t2;
+      a.G[7] += B0 * t2;
+    }
+  };
+  const int npair = nact >> 1;
+  // records are read one pair ahead (the record array is padded)
+  float4 geo_n = rec[2 * wave + hb];
+  for (int bj = wave; bj < npair; bj += nw) {
+    const float4 geo = geo_n;
+    geo_n = rec[2 * (bj + nw) + hb];
+    body(geo, 2 * bj + hb);
+  }
+  if ((nact & 1) && hb == 0 && wave == npair % nw) body(rec[nact - 1], nact - 1);
+}
+
 // Source tiles of a set: points first, then Gaussians, then disks; tile k
 // covers sources [s0, s0 + cnt) of one morphology.
 struct SrcTile {
@@ -860,7 +967,12 @@ void rime_main(const KParams p) {
       const int lane = tid % kWave;
       // wavefront index, uniform across the wavefront (scalar loop counters)
       const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
-      const int sl = lane / NC, cl = lane - (lane / NC) * NC;
+      // float32 with two channels per thread: lane = (source, baseline half)
+      // holding both channels (adjoint_pair); otherwise lane = (source, channel)
+      constexpr bool kPair = sizeof(R) == 4 && NC == 2;
+      const int sl = kPair ? (lane & 31) : lane / NC;
+      const int cl = kPair ? 0 : lane - (lane / NC) * NC;
+      const int hb = kPair ? (lane >> 5) : 0;
       const bool lane_ok_c = cl < ncv;
       const double nuc_l = lane_ok_c ? p.nu_c[c0 + cl] : 0.0;
       const R tpnc = static_cast<R>(2.0 * kPi * nuc_l);
@@ -877,6 +989,19 @@ void rime_main(const KParams p) {
       const double lnfr_l = lane_ok_c ? p.lnfr[c0 + cl] : 0.0;
       const RIME_CONST Quad<R> *rec =
           const_ptr<Quad<R>>(p.bl_rec) + (static_cast<int64_t>(t) * p.ntile + tile) * NBT;
+      // both channels of a paired lane (zero past the last channel)
+      double nuc2[2] = {0.0, 0.0}, lnfr2[2] = {0.0, 0.0};
+      PairConst pc{};
+      if (kPair) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+          if (c < ncv) {
+            nuc2[c] = p.nu_c[c0 + c];
+            lnfr2[c] = p.lnfr[c0 + c];
+          }
+        pc.tp[0] = static_cast<float>(2.0 * kPi * nuc2[0]);
+        pc.tp[1] = static_cast<float>(2.0 * kPi * nuc2[1]);
+      }
       // gradient partials: [set][item][nsrc][10], sets laid out by src_off
       double *gout = p.grad_part + sd.src_off * p.items_per_set * 10 +
                      static_cast<int64_t>(local_item) * nsrc * 10;
@@ -893,7 +1018,77 @@ void rime_main(const KParams p) {
         R gl[10];
 #pragma unroll
         for (int j = 0; j < 10; ++j) gl[j] = R(0);
-        if (sl < cnt && lane_ok_c) {
+        if constexpr (kPair) {
+          if (sl < cnt) {
+            const float4 st0 = s_src[sl * L::SREC], st1 = s_src[sl * L::SREC + 1];
+            const double2 lo = p.src_lon[sd.src_off + s0 + sl];
+            float4 e = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (shaped) e = s_src[sl * L::SREC + NC];
+            // the shape scale per channel: kap^2 (Gaussian, kap = sqrt(kGauss
+            // kExpScale) nu/c) or kapd^2 (disk, kapd = 2 pi nu/c), and the
+            // factor that turns the sums into d chi^2 / d shape (2 gq / kap or
+            // -3 kapd, times the scale)
+            PairConst pk = pc;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+              const double kg = sqrt(kGauss * N::kExpScale) * nuc2[c], kd = 2.0 * kPi * nuc2[c];
+              pk.kk[c] = static_cast<float>(disk ? kd * kd : kg * kg);
+              pk.dk[c] = static_cast<float>(disk ? -3.0 * kd * kd : -2.0 * kg * kg / N::kExpScale);
+            }
+            const char *arow =
+                smem + opaque_vgpr(static_cast<uint32_t>(L::OFF_A + sl * L::AST * sizeof(R2)));
+            const float4 *recv = reinterpret_cast<const float4 *>(p.bl_rec) +
+                                 (static_cast<int64_t>(t) * p.ntile + tile) * NBT;
+            const float2 *rho2 = reinterpret_cast<const float2 *>(s_rho);
+            constexpr int BO = static_cast<int>(L::OFF_BETA - L::OFF_A);
+            PairAcc a{};
+            if (p.beam) {
+              if (tl.shape == SHAPE_GAUSS)
+                adjoint_pair<SHAPE_GAUSS, true, BO>(wave, NW, nact, hb, recv, rho2, arow, st0, st1,
+                                                    e, pk, a);
+              else if (disk)
+                adjoint_pair<SHAPE_DISK, true, BO>(wave, NW, nact, hb, recv, rho2, arow, st0, st1,
+                                                   e, pk, a);
+              else
+                adjoint_pair<SHAPE_POINT, true, BO>(wave, NW, nact, hb, recv, rho2, arow, st0, st1,
+                                                    e, pk, a);
+            } else {
+              if (tl.shape == SHAPE_GAUSS)
+                adjoint_pair<SHAPE_GAUSS, false, BO>(wave, NW, nact, hb, recv, rho2, arow, st0,
+                                                     st1, e, pk, a);
+              else if (disk)
+                adjoint_pair<SHAPE_DISK, false, BO>(wave, NW, nact, hb, recv, rho2, arow, st0, st1,
+                                                    e, pk, a);
+              else
+                adjoint_pair<SHAPE_POINT, false, BO>(wave, NW, nact, hb, recv, rho2, arow, st0,
+                                                     st1, e, pk, a);
+            }
+            // assemble this half's sums over its baselines (both channels)
+            const double al = sd.alpha[s0 + sl];
+            const float f0 = static_cast<float>(exp(al * lnfr2[0]));
+            const float f1 = static_cast<float>(exp(al * lnfr2[1]));
+            const float lon = static_cast<float>(lo.x), mon = static_cast<float>(lo.y);
+            gl[0] = a.g5[0] + a.g5[1] + (a.G[0] - lon * a.G[2]);
+            gl[1] = a.g6[0] + a.g6[1] + (a.G[1] - mon * a.G[2]);
+            gl[2] = a.g[0][0] * f0 + a.g[1][0] * f1;
+            gl[3] = a.g[0][1] * f0 + a.g[1][1] * f1;
+            gl[4] = a.g[0][2] * f0 + a.g[1][2] * f1;
+            gl[5] = a.g[0][3] * f0 + a.g[1][3] * f1;
+            gl[6] = (st0.x * a.g[0][0] + st0.y * a.g[0][1] + st0.z * a.g[0][2] +
+                     st0.w * a.g[0][3]) * static_cast<float>(lnfr2[0]) +
+                    (st1.x * a.g[1][0] + st1.y * a.g[1][1] + st1.z * a.g[1][2] +
+                     st1.w * a.g[1][3]) * static_cast<float>(lnfr2[1]);
+            if (shaped) {
+              const int xi = s0 + sl - sd.npsrc;
+              const double Rr =
+                  disk ? sd.xshape[3 * (xi - sd.ngsrc) + 2] : sd.gshape[3 * xi + 2];
+              const float Rf = static_cast<float>(Rr);
+              gl[7] = a.G[3] - Rf * a.G[4];
+              gl[8] = a.G[5] + Rf * a.G[6];
+              gl[9] = Rr > 0.0 ? static_cast<float>(static_cast<double>(a.G[7]) / Rr) : 0.0f;
+            }
+          }
+        } else if (sl < cnt && lane_ok_c) {
           const R4 st = s_src[sl * L::SREC + cl];
           const double2 lo = p.src_lon[sd.src_off + s0 + sl];
           R4 e;
@@ -963,14 +1158,20 @@ void rime_main(const KParams p) {
                         : R(0);
           }
         }
-        // sum the NC channel lanes of each source (adjacent lanes), then
-        // across wavefronts through LDS in a fixed order
+        // sum the lanes of each source (its NC channel lanes, adjacent; or
+        // its two baseline halves), then across wavefronts through LDS in a
+        // fixed order
 #pragma unroll
-        for (int j = 0; j < 10; ++j)
+        for (int j = 0; j < 10; ++j) {
+          if (kPair) {
+            gl[j] += __shfl_xor(gl[j], 32, kWave);
+          } else {
 #pragma unroll
-          for (int d = 1; d < NC; d <<= 1) gl[j] += __shfl_xor(gl[j], d, kWave);
+            for (int d = 1; d < NC; d <<= 1) gl[j] += __shfl_xor(gl[j], d, kWave);
+          }
+        }
         __syncthreads();  // the reduction buffer aliases the beta, Stokes and shape tiles
-        if (cl == 0) {
+        if (cl == 0 && hb == 0) {
 #pragma unroll
           for (int j = 0; j < 10; ++j) s_red[(wave * NS + sl) * 10 + j] = gl[j];
         }

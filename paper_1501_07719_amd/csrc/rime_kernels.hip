@@ -13,16 +13,18 @@
 // and then, per visibility, forms V, the residual and the weighted squared
 // residual of eq. lhood, reduced in float64 with compensated (two-sum)
 // arithmetic.  In gradient mode the weighted residual stays in LDS and a
-// second source sweep (lanes over sources x channels, loop over baselines)
-// accumulates d chi^2 / d theta_s without ever storing V.
+// second source sweep (lanes over sources x channels, loop over baselines;
+// in the float32 kernels with two channels per thread, lanes over sources x
+// two baseline halves, each lane with both channels) accumulates
+// d chi^2 / d theta_s without ever storing V.
 //
-// Precision: R = double (plain FP64) or R = float (mixed).  In the mixed path
-// the phase argument is formed error-free in float64 and reduced to
-// [-1/2, 1/2] turns before a float32 sine/cosine accurate to about one unit;
-// the beam clip decision is taken in
-// float64; the per-visibility source sums run in float32 within a source tile
-// and are folded into float64 after each tile; chi^2 and gradient sums are
-// float64.
+// Precision: R = double (plain FP64) or R = float (mixed).  The phase argument
+// is formed in float64 (error-free in the FP64 path, in plain float64 within
+// about 1e-12 turns in the mixed one) and reduced to [-1/2, 1/2] turns before
+// the sine/cosine (in the mixed path a float32 one accurate to about one
+// unit); the beam clip decision is taken in float64; the per-visibility source
+// sums run in float32 within a source tile and are folded into float64 after
+// each tile; chi^2 and gradient sums are float64.
 #include "rime_device.h"
 
 namespace rime {

@@ -421,6 +421,7 @@ def bench_single(args):
     modes = [m for m in args.modes.split(",") if m]
     if args.no_fp64:
         modes = [m for m in modes if not m.endswith("fp64")]
+
     fp_steps = max(2, args.steps // 2)
     spec = {"grad_mixed": (R.MODE_CHI2_GRAD, R.MIXED, args.steps, args.warmup),
             "grad_fp64": (R.MODE_CHI2_GRAD, R.FP64, fp_steps, 1),
@@ -911,6 +912,9 @@ def main():
     if args.write_traffic:
         write_traffic(args.write_traffic, args.traffic, args.config)
         return
+    if args.config in ("c1", "c2", "c4") and "grad_mixed" not in args.modes.split(","):
+        # the line's value, roofline and traffic are those of grad_mixed
+        raise SystemExit("bench.py: --modes must include grad_mixed (the timed headline)")
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
